@@ -1,0 +1,128 @@
+/*
+ * gp.h -- C-ABI of the MI355X (gfx950) split-step Crank-Nicolson solver for the 3D
+ * Gross-Pitaevskii equation in a fully anisotropic harmonic trap,
+ *
+ *     i dpsi/dt = [ -1/2 lap + 1/2 (nux^2 x^2 + nuy^2 y^2 + nuz^2 z^2) + g |psi|^2 ] psi,
+ *
+ * propagated in imaginary time (ground states, renormalised every step) or real time
+ * (dynamics).  Method: paper, program summary "Solution method" and program summaries
+ * (i) imagtime3d / (ii) realtime3d: discretise space and time, split the Hamiltonian into
+ * the potential+nonlinear part (calcnu) and one Crank-Nicolson solve per axis (calclux,
+ * calcluy, calcluz), and propagate over small steps; norm, rms sizes, chemical potential
+ * and energy (calcrms, calcmuen) are global sums.
+ *
+ * Layout (paper, "Summary of revisions"): psi is ONE contiguous device array
+ * [nx][ny][nz] with z stride 1, y stride nz, x stride ny*nz; complex values interleaved
+ * (re, im): complex64 = 2 x float, complex128 = 2 x double.
+ *
+ * Grid: x_i = (i - (nx-1)/2) dx, i = 0..nx-1 (centred at 0), homogeneous Dirichlet
+ * ghosts at i = -1 and i = nx; same for y and z.  One step (split = GP_SPLIT_LIE):
+ *   psi <- exp(-tau (V + g|psi|^2)) psi     (tau = dt imaginary, i dt real)
+ *   then one Crank-Nicolson solve along x, y, z with c = dt/(4 d^2) (imaginary) or
+ *   i dt/(4 d^2) (real):  -c u_{i-1} + (1+2c) u_i - c u_{i+1} = c p_{i-1} + (1-2c) p_i + c p_{i+1}
+ *   imaginary time then renormalises psi to dx dy dz sum|psi|^2 = 1.
+ * GP_SPLIT_STRANG uses half potential steps before and after the sweeps.
+ *
+ * Ownership: psi is caller-owned device memory (e.g. a torch tensor); the library keeps
+ * a non-owning pointer and never frees it.  The context owns its coefficient tables,
+ * reduction scratch, device-side parameters and graphs.  The HIP stream is borrowed;
+ * every call is ordered on it.  Step calls do not synchronise; gp_norm, gp_energy_mu,
+ * gp_rms, gp_raw_sums, gp_status and gp_converge_imag synchronise the stream.  A context
+ * is not thread-safe; use one context per stream.
+ *
+ * Errors: every function returns GP_OK (0) or a negative GP_ERR_* code; nothing aborts
+ * or prints.  An asynchronous kernel fault surfaces at the next synchronising call as
+ * GP_ERR_HIP; gp_last_error(ctx) returns the runtime's message.
+ */
+#ifndef GP_H
+#define GP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GP_OK = 0,
+  GP_ERR_INVALID = -1,     /* bad parameter, null pointer, psi not device memory */
+  GP_ERR_HIP = -2,         /* HIP runtime error (message: gp_last_error) */
+  GP_ERR_OOM = -3,         /* device allocation failed */
+  GP_ERR_NONFINITE = -4,   /* a norm or observable came out NaN/Inf */
+  GP_ERR_ZERO_NORM = -5,   /* psi has zero norm */
+  GP_ERR_UNSUPPORTED = -6  /* grid too large for the kernels' line mapping */
+};
+
+enum { GP_C64 = 0, GP_C128 = 1 };                 /* storage / sweep precision */
+enum { GP_SPLIT_LIE = 0, GP_SPLIT_STRANG = 1 };
+enum { GP_FLAG_NONFINITE = 1, GP_FLAG_ZERO_NORM = 2 }; /* gp_status flags */
+
+typedef struct gp_ctx gp_ctx;
+
+typedef struct {
+  int32_t nx, ny, nz;     /* 3 <= n <= 1024 grid points per axis */
+  double dx, dy, dz;      /* > 0 spacings */
+  double nux, nuy, nuz;   /* >= 0 trap frequencies */
+  double g;               /* nonlinearity, any finite real */
+  double dt;              /* > 0 time step, used by both step kinds */
+  int32_t precision;      /* GP_C64 (complex64 storage, FP32 sweeps, FP64 sums) or GP_C128 */
+  int32_t split;          /* GP_SPLIT_LIE (default) or GP_SPLIT_STRANG */
+} gp_params;
+
+/* Create a context for psi (device pointer, nx*ny*nz complex values of the chosen
+ * precision) on hip_stream (a hipStream_t; NULL = default stream). */
+int gp_init(const gp_params* p, void* psi_dev, void* hip_stream, gp_ctx** out);
+int gp_destroy(gp_ctx* c);
+
+/* nsteps imaginary-time steps (paper: program summary (i)); psi is renormalised every
+ * step and is normalised to dx dy dz sum|psi|^2 = 1 on return. Does not synchronise. */
+int gp_step_imag(gp_ctx* c, int32_t nsteps);
+/* nsteps real-time steps (paper: program summary (ii)); no renormalisation. */
+int gp_step_real(gp_ctx* c, int32_t nsteps);
+
+/* dx dy dz sum |psi|^2 in FP64.  Synchronises. */
+int gp_norm(gp_ctx* c, double* norm);
+/* Energy and chemical potential of the normalised state phi = psi/sqrt(N) (calcmuen):
+ *   E = (T+U)/N + (g/2) I/N^2,  mu = (T+U)/N + g I/N^2, with T the kinetic link sum
+ *   1/2 dV sum_a sum_links |dpsi|^2/da^2 over all +1 links including the ghost links,
+ *   U = dV sum V|psi|^2, I = dV sum |psi|^4, N = dV sum |psi|^2.  Synchronises. */
+int gp_energy_mu(gp_ctx* c, double* energy, double* mu);
+/* rms[4] = <x^2>^1/2, <y^2>^1/2, <z^2>^1/2, <r^2>^1/2 of the normalised state (calcrms). */
+int gp_rms(gp_ctx* c, double rms[4]);
+/* raw[9] = { N, Tx, Ty, Tz, U, I, dV sum x^2|psi|^2, dV sum y^2|psi|^2, dV sum z^2|psi|^2 } */
+int gp_raw_sums(gp_ctx* c, double raw[9]);
+
+/* Change g (quench).  Stream-ordered device-side update; no graph rebuild. */
+int gp_set_g(gp_ctx* c, double g);
+/* Point the context at another caller buffer of the same shape and precision. */
+int gp_set_psi(gp_ctx* c, void* psi_dev);
+/* Steps done so far, the last cheap chemical-potential estimate -ln(N_pre)/(2 dt) from
+ * the imaginary-time renormalisation, and GP_FLAG_* bits.  Synchronises. */
+int gp_status(gp_ctx* c, int64_t* steps_done, double* mu_est, int32_t* flags);
+
+/* Imaginary-time propagation until |mu_n - mu_{n-K}| <= tol |mu_n|, mu evaluated every
+ * check_every = K steps (K <= 0 selects ceil(0.25/dt)), at most max_steps steps.
+ * Returns the steps taken and the final mu.  GP_OK also when max_steps is reached;
+ * *converged tells which.  Synchronises at every check. */
+int gp_converge_imag(gp_ctx* c, double tol, int32_t check_every, int64_t max_steps,
+                     int64_t* steps_taken, double* mu, int32_t* converged);
+
+/* Per-kernel timing: while enabled, eager launches are bracketed by HIP events on the
+ * context's stream (graphs are not used).  gp_get_timing returns the mean duration in ms
+ * of each kernel kind { x sweep, y sweep, z sweep, norm finalize, other } and the number
+ * of launches of each, accumulated since enabling.  Synchronises. */
+int gp_set_timing(gp_ctx* c, int32_t enable);
+int gp_get_timing(gp_ctx* c, double ms_mean[5], int64_t launches[5]);
+
+/* Line mapping in use: {m_x, m_y, segments_z, m_z}; m = points per thread along x/y,
+ * segments_z = threads per z line.  gp_set_mapping overrides it (0 = keep); invalid
+ * combinations return GP_ERR_INVALID. */
+int gp_get_mapping(gp_ctx* c, int32_t map[4]);
+int gp_set_mapping(gp_ctx* c, const int32_t map[4]);
+
+const char* gp_strerror(int code);
+const char* gp_last_error(gp_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

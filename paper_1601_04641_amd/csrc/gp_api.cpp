@@ -1,0 +1,758 @@
+// C-ABI of the split-step Crank-Nicolson Gross-Pitaevskii solver (declared in gp.h).
+//
+// Host side: parameter checks, the per-axis Crank-Nicolson coefficient tables (computed
+// in FP64, rounded once to the storage precision), device-resident state, the launch
+// sequence of one step, HIP graphs of fixed step counts, per-kernel event timing and the
+// FP64 observables.  All compute runs in the HIP kernels of gp_kernels.hip.
+#include "../../include/gp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gp_internal.h"
+
+using gpk::DevState;
+typedef std::complex<double> cd;
+
+namespace {
+
+constexpr int kGraphSteps = 16;   // steps per captured graph
+constexpr int kKinds = 5;         // timing kinds: x, y, z, finalize, other
+constexpr int kEventPool = 4096;  // event pairs before a forced harvest
+
+struct Mapping {
+  int mx, swx, my, swy;  // x/y: points per thread, segments per wavefront
+  int segz, mz;          // z: threads per line (power of two), points per thread
+};
+
+struct TimingRec {
+  int kind;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct gp_ctx {
+  gp_params p;
+  void* psi = nullptr;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // private stream used only for graph capture
+  int device = 0;
+  int64_t npts = 0;
+  size_t esize = 0;
+  Mapping map{};
+
+  DevState* st = nullptr;      // device
+  void* tab[2][3] = {{nullptr}};  // [imag, real][axis], storage precision, 4n complex each
+  void* vtab[3] = {nullptr};      // storage-precision 1/2 nu^2 a^2
+  double* vd[3] = {nullptr};      // FP64 potential tables
+  double* a2[3] = {nullptr};      // FP64 coordinate squares
+  double* zpart = nullptr;
+  int zgrid = 0;
+  double* opart = nullptr;
+  int ogrid = 0;
+  double* oout = nullptr;
+  double* host = nullptr;  // pinned readback buffer (16 doubles)
+
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [imag, real], kGraphSteps steps each
+  bool use_graphs = true;
+
+  bool timing = false;
+  std::vector<TimingRec> recs;
+  std::vector<hipEvent_t> pool;
+  double tsum[kKinds] = {0};
+  int64_t tcnt[kKinds] = {0};
+
+  int64_t steps_done = 0;
+  char err[256] = {0};
+};
+
+namespace {
+
+int fail_hip(gp_ctx* c, hipError_t e, const char* where) {
+  if (c) snprintf(c->err, sizeof(c->err), "%s: %s", where, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? GP_ERR_OOM : GP_ERR_HIP;
+}
+
+#define HIPCHK(c, expr)                                \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return fail_hip(c, e_, #expr); \
+  } while (0)
+
+bool bad_params(const gp_params* p) {
+  if (!p) return true;
+  if (p->nx < 3 || p->ny < 3 || p->nz < 3) return true;
+  if (!(p->dx > 0) || !(p->dy > 0) || !(p->dz > 0) || !(p->dt > 0)) return true;
+  if (!std::isfinite(p->dx) || !std::isfinite(p->dy) || !std::isfinite(p->dz) || !std::isfinite(p->dt)) return true;
+  if (!(p->nux >= 0) || !(p->nuy >= 0) || !(p->nuz >= 0)) return true;
+  if (!std::isfinite(p->nux) || !std::isfinite(p->nuy) || !std::isfinite(p->nuz)) return true;
+  if (!std::isfinite(p->g)) return true;
+  if (p->precision != GP_C64 && p->precision != GP_C128) return true;
+  if (p->split != GP_SPLIT_LIE && p->split != GP_SPLIT_STRANG) return true;
+  return false;
+}
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// x/y line mapping: smallest supported m whose block (ceil(nseg/sw) wavefronts) fits 16.
+bool pick_lines(int prec, int n, int* m_out, int* sw_out) {
+  const int ms[] = {8, 16, 32};
+  for (int sw : {1, 2, 4})
+    for (int m : ms) {
+      if (!gpk::sweep_lines_supported(prec, m, sw)) continue;
+      if (ceil_div(ceil_div(n, m), sw) <= 16) {
+        *m_out = m;
+        *sw_out = sw;
+        return true;
+      }
+    }
+  return false;
+}
+
+// register-array size of the kernel instance that runs m points per thread (0: none)
+int lines_maxm(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 0; }
+int z_maxm(int m) { return m <= 4 ? 4 : m <= 8 ? 8 : 16; }
+
+bool valid_lines(int prec, int n, int m, int sw) {
+  if (m < 1 || sw < 1 || lines_maxm(m) == 0) return false;
+  if (!gpk::sweep_lines_supported(prec, lines_maxm(m), sw)) return false;
+  return ceil_div(ceil_div(n, m), sw) <= 16;
+}
+
+bool valid_z(int nz, int seg, int m, size_t esize) {
+  if (seg < 1 || seg > 64 || (seg & (seg - 1)) != 0) return false;
+  if (m < 1 || m > 16) return false;
+  // LDS: 4 wavefronts x (64/seg) lines x nz values, plus 32 B of static reduction space
+  if ((size_t)4 * (64 / seg) * nz * esize + 64 > 65536) return false;
+  return (int64_t)seg * m >= nz;  // trailing empty segments act as identity maps
+}
+
+bool pick_z(int nz, size_t esize, int* seg_out, int* m_out) {
+  int seg = 4;
+  while (seg < 64 && seg * 8 < nz) seg <<= 1;
+  const int m = ceil_div(nz, seg);
+  if (!valid_z(nz, seg, m, esize)) return false;
+  *seg_out = seg;
+  *m_out = m;
+  return true;
+}
+
+// Crank-Nicolson tables of one axis: a_i = c gamma_i, b_i = (1-2c) gamma_i, and the
+// within-segment products pi_i, rho_i (segments of length m).  gamma_i is the Thomas
+// pivot inverse 1/(1 + 2c + c c'_{i-1}) with c'_i = -c gamma_i, c'_{-1} = 0.
+void cn_tables(int n, cd c, int m, std::vector<cd>& t) {
+  t.assign(4 * (size_t)n, cd(0, 0));
+  cd cprev(0, 0);
+  for (int i = 0; i < n; ++i) {
+    const cd gam = 1.0 / (1.0 + 2.0 * c + c * cprev);
+    cprev = -c * gam;
+    t[i] = c * gam;
+    t[n + i] = (1.0 - 2.0 * c) * gam;
+  }
+  for (int s = 0; s < n; s += m) {
+    const int e = std::min(s + m, n);
+    cd pr(1, 0);
+    for (int i = s; i < e; ++i) {
+      pr *= t[i];
+      t[2 * n + i] = pr;
+    }
+    cd rr(1, 0);
+    for (int i = e - 1; i >= s; --i) {
+      rr *= t[i];
+      t[3 * n + i] = rr;
+    }
+  }
+}
+
+int upload_complex(gp_ctx* c, void* dst, const std::vector<cd>& src) {
+  if (c->p.precision == GP_C128) {
+    HIPCHK(c, hipMemcpy(dst, src.data(), src.size() * sizeof(cd), hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(2 * src.size());
+    for (size_t i = 0; i < src.size(); ++i) {
+      f[2 * i] = (float)src[i].real();
+      f[2 * i + 1] = (float)src[i].imag();
+    }
+    HIPCHK(c, hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+  return GP_OK;
+}
+
+int build_tables(gp_ctx* c) {
+  const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+  const double d[3] = {c->p.dx, c->p.dy, c->p.dz};
+  const int m[3] = {c->map.mx, c->map.my, c->map.mz};
+  std::vector<cd> t;
+  for (int mode = 0; mode < 2; ++mode)
+    for (int a = 0; a < 3; ++a) {
+      const double k = c->p.dt / (4.0 * d[a] * d[a]);
+      cn_tables(n[a], mode == 0 ? cd(k, 0) : cd(0, k), m[a], t);
+      int rc = upload_complex(c, c->tab[mode][a], t);
+      if (rc) return rc;
+    }
+  return GP_OK;
+}
+
+void destroy_graphs(gp_ctx* c) {
+  for (auto& g : c->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+gpk::SweepLaunch lines_args(gp_ctx* c, int axis, int mode) {
+  gpk::SweepLaunch a{};
+  const gp_params& p = c->p;
+  a.psi = c->psi;
+  a.psi_bytes = (uint32_t)(c->npts * (int64_t)c->esize);
+  a.tab = c->tab[mode][axis];
+  a.n = axis == 0 ? p.nx : p.ny;
+  a.m = axis == 0 ? c->map.mx : c->map.my;
+  a.sw = axis == 0 ? c->map.swx : c->map.swy;
+  a.nseg = ceil_div(a.n, a.m);
+  a.nlines = axis == 0 ? (int64_t)p.ny * p.nz : (int64_t)p.nx * p.nz;
+  a.inner = axis == 0 ? (int64_t)p.ny * p.nz : (int64_t)p.nz;
+  a.nstep = 0;
+  if (axis == 0) {
+    a.nstep = mode == 0 ? 1 : 2;
+    a.tau = p.split == GP_SPLIT_LIE ? p.dt : 0.5 * p.dt;
+    a.vx = c->vtab[0];
+    a.vy = c->vtab[1];
+    a.vz = c->vtab[2];
+  }
+  a.ny = p.ny;
+  a.nz = p.nz;
+  a.st = c->st;
+  return a;
+}
+
+gpk::SweepLaunch z_args(gp_ctx* c, int mode) {
+  gpk::SweepLaunch a{};
+  const gp_params& p = c->p;
+  a.psi = c->psi;
+  a.tab = c->tab[mode][2];
+  a.n = p.nz;
+  a.m = c->map.mz;
+  a.nseg = c->map.segz;
+  a.nlines = (int64_t)p.nx * p.ny;
+  a.inner = 1;
+  a.nstep = p.split == GP_SPLIT_STRANG ? (mode == 0 ? 1 : 2) : 0;
+  a.tau = 0.5 * p.dt;
+  a.vx = c->vtab[0];
+  a.vy = c->vtab[1];
+  a.vz = c->vtab[2];
+  a.ny = p.ny;
+  a.nz = p.nz;
+  a.st = c->st;
+  a.partials = mode == 0 ? c->zpart : nullptr;
+  a.grid = c->zgrid;
+  return a;
+}
+
+hipEvent_t pool_get(gp_ctx* c) {
+  if (c->pool.empty()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = c->pool.back();
+  c->pool.pop_back();
+  return e;
+}
+
+int harvest(gp_ctx* c) {
+  if (c->recs.empty()) return GP_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& r : c->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->tsum[r.kind] += ms;
+      c->tcnt[r.kind] += 1;
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->recs.clear();
+  return GP_OK;
+}
+
+// Launch one kernel (through fn) with optional event bracketing.
+template <typename F>
+int timed(gp_ctx* c, hipStream_t s, int kind, F fn) {
+  if (!c->timing || s != c->stream) {
+    hipError_t e = fn(s);
+    return e == hipSuccess ? GP_OK : fail_hip(c, e, "kernel launch");
+  }
+  if ((int)c->recs.size() >= kEventPool) {
+    int rc = harvest(c);
+    if (rc) return rc;
+  }
+  hipEvent_t a = pool_get(c), b = pool_get(c);
+  if (!a || !b) return fail_hip(c, hipErrorOutOfMemory, "hipEventCreate");
+  HIPCHK(c, hipEventRecord(a, s));
+  hipError_t e = fn(s);
+  if (e != hipSuccess) return fail_hip(c, e, "kernel launch");
+  HIPCHK(c, hipEventRecord(b, s));
+  c->recs.push_back({kind, a, b});
+  return GP_OK;
+}
+
+// One full step on stream s. mode 0 imaginary (renormalising), 1 real.
+int enqueue_step(gp_ctx* c, int mode, hipStream_t s) {
+  const int prec = c->p.precision;
+  const bool cc = mode == 1;
+  gpk::SweepLaunch ax = lines_args(c, 0, mode), ay = lines_args(c, 1, mode), az = z_args(c, mode);
+  const int mxm = lines_maxm(c->map.mx), mym = lines_maxm(c->map.my), mzm = z_maxm(c->map.mz);
+  int rc = timed(c, s, 0, [&](hipStream_t t) { return gpk::launch_sweep_lines(prec, cc, mxm, ax, t); });
+  if (rc) return rc;
+  rc = timed(c, s, 1, [&](hipStream_t t) { return gpk::launch_sweep_lines(prec, cc, mym, ay, t); });
+  if (rc) return rc;
+  rc = timed(c, s, 2, [&](hipStream_t t) { return gpk::launch_sweep_z(prec, cc, mzm, az, t); });
+  if (rc) return rc;
+  if (mode == 0) {
+    const double dV = c->p.dx * c->p.dy * c->p.dz;
+    rc = timed(c, s, 3, [&](hipStream_t t) {
+      return gpk::launch_finalize_norm(c->zpart, c->zgrid, dV, c->p.dt, c->st, t);
+    });
+    if (rc) return rc;
+  }
+  return GP_OK;
+}
+
+int ensure_graph(gp_ctx* c, int mode) {
+  if (c->gexec[mode]) return GP_OK;
+  if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  int rc = GP_OK;
+  for (int k = 0; k < kGraphSteps && rc == GP_OK; ++k) rc = enqueue_step(c, mode, c->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail_hip(c, e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&c->gexec[mode], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->gexec[mode] = nullptr;
+    return fail_hip(c, e, "hipGraphInstantiate");
+  }
+  return GP_OK;
+}
+
+int run_steps(gp_ctx* c, int mode, int32_t n) {
+  int32_t left = n;
+  if (c->use_graphs && !c->timing && n >= kGraphSteps) {
+    int rc = ensure_graph(c, mode);
+    if (rc) return rc;
+    while (left >= kGraphSteps) {
+      HIPCHK(c, hipGraphLaunch(c->gexec[mode], c->stream));
+      left -= kGraphSteps;
+    }
+  }
+  for (int32_t k = 0; k < left; ++k) {
+    int rc = enqueue_step(c, mode, c->stream);
+    if (rc) return rc;
+  }
+  c->steps_done += n;
+  return GP_OK;
+}
+
+int observe(gp_ctx* c, double raw[9]) {
+  gpk::ObsLaunch o{};
+  o.psi = c->psi;
+  o.nx = c->p.nx;
+  o.ny = c->p.ny;
+  o.nz = c->p.nz;
+  o.x2 = c->a2[0];
+  o.y2 = c->a2[1];
+  o.z2 = c->a2[2];
+  o.vx = c->vd[0];
+  o.vy = c->vd[1];
+  o.vz = c->vd[2];
+  o.partials = c->opart;
+  o.grid = c->ogrid;
+  o.out = c->oout;
+  int rc = timed(c, c->stream, 4, [&](hipStream_t t) { return gpk::launch_observables(c->p.precision, o, t); });
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->host, c->oout, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double dV = c->p.dx * c->p.dy * c->p.dz;
+  const double d2[3] = {c->p.dx * c->p.dx, c->p.dy * c->p.dy, c->p.dz * c->p.dz};
+  raw[0] = c->host[0] * dV;
+  for (int a = 0; a < 3; ++a) raw[1 + a] = 0.5 * c->host[1 + a] * dV / d2[a];
+  for (int q = 4; q < 9; ++q) raw[q] = c->host[q] * dV;
+  for (int q = 0; q < 9; ++q)
+    if (!std::isfinite(raw[q])) return GP_ERR_NONFINITE;
+  if (!(raw[0] > 0)) return GP_ERR_ZERO_NORM;
+  return GP_OK;
+}
+
+template <typename T>
+int dalloc(gp_ctx* c, T** p, size_t bytes) {
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail_hip(c, e, "hipMalloc");
+  }
+  return GP_OK;
+}
+
+void release(gp_ctx* c) {
+  destroy_graphs(c);
+  for (auto& r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  (void)hipFree(c->st);
+  for (auto& m : c->tab)
+    for (auto p : m) hipFree(p);
+  for (int a = 0; a < 3; ++a) {
+    (void)hipFree(c->vtab[a]);
+    (void)hipFree(c->vd[a]);
+    (void)hipFree(c->a2[a]);
+  }
+  (void)hipFree(c->zpart);
+  (void)hipFree(c->opart);
+  (void)hipFree(c->oout);
+  if (c->host) (void)hipHostFree(c->host);
+}
+
+int check_psi(gp_ctx* c, void* psi) {
+  if (!psi) return GP_ERR_INVALID;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, psi) != hipSuccess) {
+    (void)hipGetLastError();
+    snprintf(c->err, sizeof(c->err), "psi is not a HIP device pointer");
+    return GP_ERR_INVALID;
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) {
+    snprintf(c->err, sizeof(c->err), "psi is not device memory");
+    return GP_ERR_INVALID;
+  }
+  if (attr.device != c->device) {
+    snprintf(c->err, sizeof(c->err), "psi lives on device %d, context on device %d", attr.device, c->device);
+    return GP_ERR_INVALID;
+  }
+  if (reinterpret_cast<uintptr_t>(psi) % c->esize != 0) {
+    snprintf(c->err, sizeof(c->err), "psi is not aligned to its complex element size");
+    return GP_ERR_INVALID;
+  }
+  return GP_OK;
+}
+
+int init_body(gp_ctx* c) {
+  const gp_params& p = c->p;
+  const int prec = p.precision;
+  if (!pick_lines(prec, p.nx, &c->map.mx, &c->map.swx) || !pick_lines(prec, p.ny, &c->map.my, &c->map.swy) ||
+      !pick_z(p.nz, c->esize, &c->map.segz, &c->map.mz)) {
+    snprintf(c->err, sizeof(c->err), "grid %dx%dx%d exceeds the supported line lengths", p.nx, p.ny, p.nz);
+    return GP_ERR_UNSUPPORTED;
+  }
+  const int n[3] = {p.nx, p.ny, p.nz};
+  const double d[3] = {p.dx, p.dy, p.dz};
+  const double nu[3] = {p.nux, p.nuy, p.nuz};
+  int rc;
+  if ((rc = dalloc(c, &c->st, sizeof(DevState)))) return rc;
+  for (int mode = 0; mode < 2; ++mode)
+    for (int a = 0; a < 3; ++a)
+      if ((rc = dalloc(c, &c->tab[mode][a], 4 * (size_t)n[a] * c->esize))) return rc;
+  for (int a = 0; a < 3; ++a) {
+    if ((rc = dalloc(c, &c->vtab[a], (size_t)n[a] * c->esize / 2))) return rc;
+    if ((rc = dalloc(c, &c->vd[a], (size_t)n[a] * sizeof(double)))) return rc;
+    if ((rc = dalloc(c, &c->a2[a], (size_t)n[a] * sizeof(double)))) return rc;
+    std::vector<double> x2(n[a]), v(n[a]);
+    std::vector<float> vf(n[a]);
+    for (int i = 0; i < n[a]; ++i) {
+      const double x = (i - 0.5 * (n[a] - 1)) * d[a];
+      x2[i] = x * x;
+      v[i] = 0.5 * nu[a] * nu[a] * x * x;
+      vf[i] = (float)v[i];
+    }
+    HIPCHK(c, hipMemcpy(c->a2[a], x2.data(), n[a] * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->vd[a], v.data(), n[a] * sizeof(double), hipMemcpyHostToDevice));
+    if (prec == GP_C128)
+      HIPCHK(c, hipMemcpy(c->vtab[a], v.data(), n[a] * sizeof(double), hipMemcpyHostToDevice));
+    else
+      HIPCHK(c, hipMemcpy(c->vtab[a], vf.data(), n[a] * sizeof(float), hipMemcpyHostToDevice));
+  }
+  if ((rc = build_tables(c))) return rc;
+  const int64_t zlines = (int64_t)p.nx * p.ny;
+  const int64_t zgroups = (zlines + 4 * (64 / c->map.segz) - 1) / (4 * (64 / c->map.segz));
+  c->zgrid = (int)std::min<int64_t>(zgroups, 2048);
+  const int64_t oblocks = (c->npts + 255) / 256;
+  c->ogrid = (int)std::min<int64_t>(oblocks, 2048);
+  if ((rc = dalloc(c, &c->zpart, (size_t)c->zgrid * sizeof(double)))) return rc;
+  if ((rc = dalloc(c, &c->opart, (size_t)c->ogrid * 9 * sizeof(double)))) return rc;
+  if ((rc = dalloc(c, &c->oout, 16 * sizeof(double)))) return rc;
+  HIPCHK(c, hipHostMalloc((void**)&c->host, 16 * sizeof(double), hipHostMallocDefault));
+  DevState s0{};
+  s0.s = 1.0;
+  s0.g = p.g;
+  s0.npre = 1.0;
+  HIPCHK(c, hipMemcpy(c->st, &s0, sizeof(s0), hipMemcpyHostToDevice));
+  return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gp_init(const gp_params* p, void* psi_dev, void* hip_stream, gp_ctx** out) {
+  if (!out) return GP_ERR_INVALID;
+  *out = nullptr;
+  if (bad_params(p) || !psi_dev) return GP_ERR_INVALID;
+  if (p->nx > 1024 || p->ny > 1024 || p->nz > 1024) return GP_ERR_UNSUPPORTED;
+  // the sweeps address psi through 32-bit buffer offsets
+  if ((int64_t)p->nx * p->ny * p->nz * (p->precision == GP_C128 ? 16 : 8) >= (int64_t)1 << 32)
+    return GP_ERR_UNSUPPORTED;
+  gp_ctx* c = new (std::nothrow) gp_ctx;
+  if (!c) return GP_ERR_OOM;
+  c->p = *p;
+  c->stream = (hipStream_t)hip_stream;
+  c->npts = (int64_t)p->nx * p->ny * p->nz;
+  c->esize = p->precision == GP_C128 ? 16 : 8;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return GP_ERR_HIP;
+  }
+  int rc = check_psi(c, psi_dev);
+  if (rc == GP_OK) {
+    c->psi = psi_dev;
+    rc = init_body(c);
+  }
+  if (rc != GP_OK) {
+    release(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return GP_OK;
+}
+
+int gp_destroy(gp_ctx* c) {
+  if (!c) return GP_ERR_INVALID;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  release(c);
+  delete c;
+  return GP_OK;
+}
+
+int gp_step_imag(gp_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return GP_ERR_INVALID;
+  if (nsteps == 0) return GP_OK;
+  int rc = run_steps(c, 0, nsteps);
+  if (rc) return rc;
+  // psi is kept unnormalised between steps (the scale rides into the next potential
+  // step); apply it so the caller sees dV sum|psi|^2 = 1.
+  return timed(c, c->stream, 4, [&](hipStream_t t) {
+    return gpk::launch_scale(c->p.precision, c->psi, c->npts, c->st, t);
+  });
+}
+
+int gp_step_real(gp_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return GP_ERR_INVALID;
+  if (nsteps == 0) return GP_OK;
+  return run_steps(c, 1, nsteps);
+}
+
+int gp_raw_sums(gp_ctx* c, double raw[9]) {
+  if (!c || !raw) return GP_ERR_INVALID;
+  return observe(c, raw);
+}
+
+int gp_norm(gp_ctx* c, double* norm) {
+  if (!c || !norm) return GP_ERR_INVALID;
+  double r[9];
+  int rc = observe(c, r);
+  *norm = r[0];
+  return rc;
+}
+
+int gp_energy_mu(gp_ctx* c, double* energy, double* mu) {
+  if (!c || !energy || !mu) return GP_ERR_INVALID;
+  double r[9];
+  int rc = observe(c, r);
+  if (rc) return rc;
+  const double N = r[0];
+  const double lin = (r[1] + r[2] + r[3] + r[4]) / N;
+  const double nl = c->p.g * r[5] / (N * N);
+  *energy = lin + 0.5 * nl;
+  *mu = lin + nl;
+  return GP_OK;
+}
+
+int gp_rms(gp_ctx* c, double rms[4]) {
+  if (!c || !rms) return GP_ERR_INVALID;
+  double r[9];
+  int rc = observe(c, r);
+  if (rc) return rc;
+  const double N = r[0];
+  rms[0] = std::sqrt(r[6] / N);
+  rms[1] = std::sqrt(r[7] / N);
+  rms[2] = std::sqrt(r[8] / N);
+  rms[3] = std::sqrt((r[6] + r[7] + r[8]) / N);
+  return GP_OK;
+}
+
+int gp_set_g(gp_ctx* c, double g) {
+  if (!c || !std::isfinite(g)) return GP_ERR_INVALID;
+  c->p.g = g;
+  c->host[12] = g;  // staged in pinned memory so the copy is stream-ordered
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpyAsync(&c->st->g, &c->host[12], sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GP_OK;
+}
+
+int gp_set_psi(gp_ctx* c, void* psi_dev) {
+  if (!c) return GP_ERR_INVALID;
+  int rc = check_psi(c, psi_dev);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->psi = psi_dev;
+  destroy_graphs(c);
+  return GP_OK;
+}
+
+int gp_status(gp_ctx* c, int64_t* steps_done, double* mu_est, int32_t* flags) {
+  if (!c) return GP_ERR_INVALID;
+  DevState s{};
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(&s, c->st, sizeof(s), hipMemcpyDeviceToHost));
+  if (steps_done) *steps_done = c->steps_done;
+  if (mu_est) *mu_est = s.mu_est;
+  if (flags) *flags = s.flags;
+  return GP_OK;
+}
+
+int gp_converge_imag(gp_ctx* c, double tol, int32_t check_every, int64_t max_steps, int64_t* steps_taken,
+                     double* mu, int32_t* converged) {
+  if (!c || !(tol > 0) || max_steps < 0) return GP_ERR_INVALID;
+  int32_t K = check_every > 0 ? check_every : (int32_t)std::ceil(0.25 / c->p.dt);
+  if (K < 1) K = 1;
+  int64_t done = 0;
+  double prev = NAN, cur = NAN, e = 0;
+  int32_t conv = 0;
+  while (done < max_steps) {
+    const int32_t n = (int32_t)std::min<int64_t>(K, max_steps - done);
+    int rc = gp_step_imag(c, n);
+    if (rc) return rc;
+    done += n;
+    rc = gp_energy_mu(c, &e, &cur);
+    if (rc) return rc;
+    if (std::isfinite(prev) && std::fabs(cur - prev) <= tol * std::fabs(cur)) {
+      conv = 1;
+      break;
+    }
+    prev = cur;
+  }
+  if (steps_taken) *steps_taken = done;
+  if (mu) *mu = cur;
+  if (converged) *converged = conv;
+  return GP_OK;
+}
+
+int gp_set_timing(gp_ctx* c, int32_t enable) {
+  if (!c) return GP_ERR_INVALID;
+  int rc = harvest(c);
+  if (rc) return rc;
+  c->timing = enable != 0;
+  for (int k = 0; k < kKinds; ++k) {
+    c->tsum[k] = 0;
+    c->tcnt[k] = 0;
+  }
+  return GP_OK;
+}
+
+int gp_get_timing(gp_ctx* c, double ms_mean[5], int64_t launches[5]) {
+  if (!c) return GP_ERR_INVALID;
+  int rc = harvest(c);
+  if (rc) return rc;
+  for (int k = 0; k < kKinds; ++k) {
+    if (ms_mean) ms_mean[k] = c->tcnt[k] ? c->tsum[k] / c->tcnt[k] : 0.0;
+    if (launches) launches[k] = c->tcnt[k];
+  }
+  return GP_OK;
+}
+
+int gp_get_mapping(gp_ctx* c, int32_t map[4]) {
+  if (!c || !map) return GP_ERR_INVALID;
+  map[0] = c->map.mx;
+  map[1] = c->map.my;
+  map[2] = c->map.segz;
+  map[3] = c->map.mz;
+  return GP_OK;
+}
+
+int gp_set_mapping(gp_ctx* c, const int32_t map[4]) {
+  if (!c || !map) return GP_ERR_INVALID;
+  Mapping nm = c->map;
+  const int prec = c->p.precision;
+  auto pick_sw = [&](int n, int m, int* sw) {
+    for (int s : {1, 2, 4})
+      if (valid_lines(prec, n, m, s)) {
+        *sw = s;
+        return true;
+      }
+    return false;
+  };
+  if (map[0] > 0 && !(nm.mx = map[0], pick_sw(c->p.nx, nm.mx, &nm.swx))) return GP_ERR_INVALID;
+  if (map[1] > 0 && !(nm.my = map[1], pick_sw(c->p.ny, nm.my, &nm.swy))) return GP_ERR_INVALID;
+  if (map[2] > 0 || map[3] > 0) {
+    const int seg = map[2] > 0 ? map[2] : nm.segz;
+    const int m = map[3] > 0 ? map[3] : ceil_div(c->p.nz, seg);
+    if (!valid_z(c->p.nz, seg, m, c->esize)) return GP_ERR_INVALID;
+    nm.segz = seg;
+    nm.mz = m;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const Mapping old = c->map;
+  c->map = nm;
+  const int64_t zlines = (int64_t)c->p.nx * c->p.ny;
+  const int64_t zgroups = (zlines + 4 * (64 / nm.segz) - 1) / (4 * (64 / nm.segz));
+  const int zgrid = (int)std::min<int64_t>(zgroups, 2048);
+  if (zgrid > c->zgrid) {
+    double* np = nullptr;
+    int rc = dalloc(c, &np, (size_t)zgrid * sizeof(double));
+    if (rc) {
+      c->map = old;
+      return rc;
+    }
+    (void)hipFree(c->zpart);
+    c->zpart = np;
+  }
+  c->zgrid = zgrid;
+  destroy_graphs(c);
+  return build_tables(c);
+}
+
+const char* gp_strerror(int code) {
+  switch (code) {
+    case GP_OK: return "ok";
+    case GP_ERR_INVALID: return "invalid argument";
+    case GP_ERR_HIP: return "HIP runtime error";
+    case GP_ERR_OOM: return "out of device memory";
+    case GP_ERR_NONFINITE: return "non-finite norm or observable";
+    case GP_ERR_ZERO_NORM: return "zero norm";
+    case GP_ERR_UNSUPPORTED: return "unsupported grid size";
+    default: return "unknown error code";
+  }
+}
+
+const char* gp_last_error(gp_ctx* c) { return c ? c->err : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Internal interface between the C-ABI host code (gp_api.cpp) and the HIP kernels
+// (gp_kernels.hip).  Not installed; not part of the C-ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpk {
+
+// Device-resident solver state, read by the kernels through a pointer so that captured
+// graphs stay valid when g or the renormalisation scale change.
+struct DevState {
+  double s;       // pending renormalisation scale, applied by the next potential step
+  double g;       // nonlinearity
+  double npre;    // dV sum|psi|^2 before the last renormalisation
+  double mu_est;  // -ln(npre) / (2 dt)
+  int32_t flags;  // GP_FLAG_* bits
+  int32_t pad;
+};
+
+// Per-axis Crank-Nicolson coefficient table in storage precision, 4 rows of n complex
+// values: a_i = c gamma_i, b_i = (1-2c) gamma_i, pi_i = prod_{j=seg start..i} a_j,
+// rho_i = prod_{j=i..seg end-1} a_j (segments of length m along the line).
+struct SweepLaunch {
+  void* psi;
+  uint32_t psi_bytes;  // size of psi in bytes (< 4 GiB: buffer addressing)
+  const void* tab;
+  int n;            // points along the swept axis
+  int m;            // points per thread segment
+  int nseg;         // segments per line
+  int64_t nlines;   // number of lines
+  int64_t inner;    // x sweep: ny*nz; y sweep: nz (line l -> base (l/inner)*n*inner + l%inner)
+  int sw;           // segments per wavefront (x/y kernels)
+  // potential step fused into the load (x sweep) or store (z sweep, Strang)
+  int nstep;        // 0 none, 1 imaginary, 2 real
+  double tau;
+  const void* vx;   // storage-precision potential tables 1/2 nu^2 a^2
+  const void* vy;
+  const void* vz;
+  int ny, nz;
+  const DevState* st;
+  double* partials; // z sweep: per-block FP64 sum |psi|^2 (imaginary time), else null
+  int grid;         // z sweep: number of blocks
+};
+
+// precision: 0 complex64, 1 complex128; cc: complex coefficients (real time)
+hipError_t launch_sweep_lines(int precision, bool cc, int maxm, const SweepLaunch& a, hipStream_t s);
+hipError_t launch_sweep_z(int precision, bool cc, int mz, const SweepLaunch& a, hipStream_t s);
+
+hipError_t launch_finalize_norm(const double* partials, int nb, double dV, double dt, DevState* st,
+                                hipStream_t s);
+hipError_t launch_scale(int precision, void* psi, int64_t n, DevState* st, hipStream_t s);
+
+// Observables: 9 FP64 sums per block into partials[nb][9], then a fixed-order final sum
+// into out[9] (raw, without dV or 1/(2 d^2) factors).
+struct ObsLaunch {
+  const void* psi;
+  int nx, ny, nz;
+  const double* x2;  // coordinate squares per axis (FP64)
+  const double* y2;
+  const double* z2;
+  const double* vx;  // FP64 potential tables
+  const double* vy;
+  const double* vz;
+  double* partials;
+  int grid;
+  double* out;
+};
+hipError_t launch_observables(int precision, const ObsLaunch& a, hipStream_t s);
+
+// Supported line mappings (x/y kernels: points per thread and segments per wavefront)
+bool sweep_lines_supported(int precision, int m, int sw);
+bool sweep_z_supported(int precision, int mz);
+
+}  // namespace gpk

@@ -1,0 +1,557 @@
+// HIP kernels (gfx950, wave64) of the split-step Crank-Nicolson Gross-Pitaevskii step.
+//
+// One step streams psi through three kernels (paper: "Summary of revisions", the
+// sub-steps calcnu, calclux, calcluy, calcluz):
+//   k_sweep_lines  x sweep with the potential/nonlinear step fused into its load, then
+//                  the y sweep (same kernel, no potential step).  Lanes run over the
+//                  contiguous line index, so every row of a line bundle is one coalesced
+//                  512 B (complex64) / 1 KB (complex128) access.
+//   k_sweep_z      z sweep over the contiguous axis: line blocks staged through LDS with
+//                  coalesced copies, each z line split over a group of lanes; in
+//                  imaginary time it also emits FP64 per-block sums of |psi|^2.
+//   k_finalize_norm  fixed-order FP64 sum of those partials -> renormalisation scale,
+//                  which the next potential step applies (paper: renormalisation of the
+//                  wavefunction after each imaginary-time step).
+//
+// Each Crank-Nicolson solve along a line,
+//   -c u_{i-1} + (1+2c) u_i - c u_{i+1} = c p_{i-1} + (1-2c) p_i + c p_{i+1},
+// is the Thomas algorithm written as two first-order linear recurrences with the
+// constant tables a_i = c gamma_i and b_i = (1-2c) gamma_i of the forward sweep:
+//   forward   d_i = a_i (p_{i-1} + p_{i+1} + d_{i-1}) + b_i p_i,   d_{-1} = 0
+//   backward  u_i = d_i + a_i u_{i+1},                             u_n = 0
+// A line is cut into segments of m points, one segment per thread.  Each thread runs
+// both recurrences over its segment from a zero start; the true start values follow
+// from composing the segments' affine maps x -> A x + B (A = product of a over the
+// segment), and the fix-up d_i += pi_i D_in, u_i += rho_i U_in uses the tabulated
+// within-segment products pi, rho.  This is algebraically the same elimination as the
+// serial Thomas sweep (only rounding order differs) and needs no d' storage beyond the
+// segment held in registers, so psi is read once and written once per sweep.
+#include "gp_internal.h"
+
+namespace gpk {
+
+template <typename R> struct VecOf;
+template <> struct VecOf<float> { typedef float2 T; };
+template <> struct VecOf<double> { typedef double2 T; };
+
+template <typename V> __device__ __forceinline__ V vmake(decltype(V::x) x, decltype(V::x) y) {
+  V r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+template <typename V> __device__ __forceinline__ V vzero() { return vmake<V>(0, 0); }
+template <typename V> __device__ __forceinline__ V vone() { return vmake<V>(1, 0); }
+template <typename V> __device__ __forceinline__ V vadd(V a, V b) { return vmake<V>(a.x + b.x, a.y + b.y); }
+
+// coefficient * value; with real coefficients (CC = false) only a.x is used
+template <bool CC, typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  if (CC) return vmake<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return vmake<V>(a.x * b.x, a.x * b.y);
+}
+// a * b + c
+template <bool CC, typename V> __device__ __forceinline__ V cfma(V a, V b, V c) {
+  if (CC) return vmake<V>(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+  return vmake<V>(fma(a.x, b.x, c.x), fma(a.x, b.y, c.y));
+}
+
+__device__ __forceinline__ float dexp(float v) { return expf(v); }
+__device__ __forceinline__ double dexp(double v) { return exp(v); }
+__device__ __forceinline__ void dsincos(float v, float* s, float* c) { sincosf(v, s, c); }
+__device__ __forceinline__ void dsincos(double v, double* s, double* c) { sincos(v, s, c); }
+
+// Potential + nonlinear step on one value (calcnu): p <- scale p, then
+// imaginary time p <- exp(-tau (V + g|p|^2)) p, real time p <- exp(-i tau (V + g|p|^2)) p.
+template <int MODE, typename R, typename V>
+__device__ __forceinline__ V nstep(V v, R scale, R pot, R g, R tau) {
+  const R re = v.x * scale, im = v.y * scale;
+  const R w = fma(g, fma(re, re, im * im), pot);
+  if (MODE == 1) {
+    const R f = dexp(-tau * w);
+    return vmake<V>(f * re, f * im);
+  }
+  R sn, cs;
+  dsincos(-tau * w, &sn, &cs);
+  return vmake<V>(cs * re - sn * im, fma(cs, im, sn * re));
+}
+
+// Raw buffer access: an SGPR resource for the whole array, a 32-bit per-lane byte offset
+// (VGPR) and a uniform per-row byte offset (SGPR), so a strided line costs one VGPR of
+// addressing instead of a 64-bit address per element.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+typedef unsigned int u32x4 __attribute__((__vector_size__(16)));
+__device__ __forceinline__ void bload(float2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ void bload(double2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ void bstore(const float2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void bstore(const double2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)vo, (int)so, 0);
+}
+
+template <typename V> __device__ __forceinline__ V shfl_up_v(V v, int off, int width) {
+  return vmake<V>(__shfl_up(v.x, off, width), __shfl_up(v.y, off, width));
+}
+template <typename V> __device__ __forceinline__ V shfl_down_v(V v, int off, int width) {
+  return vmake<V>(__shfl_down(v.x, off, width), __shfl_down(v.y, off, width));
+}
+
+// ---------------------------------------------------------------------------------------
+// x / y sweep.  Block = ceil(nseg/SW) wavefronts; a wavefront holds SW segments of
+// LW = 64/SW consecutive lines (lane = segment-in-wave * LW + line).  Lines l of a block
+// are blockIdx.x*LW + [0, LW); element i of line l sits at base(l) + i*inner.
+// ---------------------------------------------------------------------------------------
+template <typename R, int M, int SW, bool CC, int NSTEP>
+__global__ void __launch_bounds__(1024)
+k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, uint32_t psi_bytes,
+              const typename VecOf<R>::T* __restrict__ tab,
+              int n, int m, int nseg, int64_t nlines, int64_t inner, const R* __restrict__ vline,
+              const R* __restrict__ vy, const R* __restrict__ vz, int nz, R tau,
+              const DevState* __restrict__ st) {
+  typedef typename VecOf<R>::T V;
+  constexpr int LW = 64 / SW;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nslot = (int)(blockDim.x >> 6) * SW;  // segment slots in this block
+  V* sh_first = reinterpret_cast<V*>(smem_raw);
+  V* sh_last = sh_first + nslot * LW;
+  V* sh_B = sh_last + nslot * LW;
+  V* sh_U = sh_B + nslot * LW;
+
+  const int lane = threadIdx.x & 63;
+  const int li = lane % LW;
+  const int p = (SW == 1) ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))
+                          : (int)(threadIdx.x >> 6) * SW + lane / LW;
+  const int64_t line = (int64_t)blockIdx.x * LW + li;
+  const bool active = line < nlines;
+  const int64_t base = active ? (line / inner) * (inner * n) + (line % inner) : 0;
+  const int s = p * m;
+  const int len = max(0, min(m, n - s));
+  const V* ta = tab;
+  const V* tb = tab + n;
+  const V* tpi = tab + 2 * n;
+  const V* trho = tab + 3 * n;
+
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(psi, psi_bytes);
+  const uint32_t voff = (uint32_t)((base + (int64_t)s * inner) * (int64_t)sizeof(V));
+  const uint32_t srow = (uint32_t)(inner * (int64_t)sizeof(V));
+  V v[M];
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    v[t] = vzero<V>();
+    if (t < len && active) bload(v[t], rs, voff, (uint32_t)t * srow);
+  }
+  if (NSTEP != 0) {
+    const R scale = (R)st->s;
+    const R g = (R)st->g;
+    R vyz = 0;
+    if (active) vyz = vy[line / nz] + vz[line % nz];  // x-sweep line index = j*nz + k
+#pragma unroll
+    for (int t = 0; t < M; ++t)
+      if (t < len) v[t] = nstep<NSTEP, R, V>(v[t], scale, vline[s + t] + vyz, g, tau);
+  }
+
+  // neighbours across segment boundaries (right-hand side of the first and last rows)
+  V last = v[0];
+#pragma unroll
+  for (int t = 1; t < M; ++t)
+    if (t == len - 1) last = v[t];
+  sh_first[p * LW + li] = v[0];
+  sh_last[p * LW + li] = last;
+  __syncthreads();
+  const V left = (p > 0 && p < nseg) ? sh_last[(p - 1) * LW + li] : vzero<V>();
+  const V right = (p < nseg - 1) ? sh_first[(p + 1) * LW + li] : vzero<V>();
+
+  // forward recurrence over the segment from d_{s-1} = 0
+  V prev = left, d = vzero<V>();
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    if (t < len) {
+      V nxt = right;
+      if (t + 1 < M && t + 1 < len) nxt = v[t + 1];
+      const V sum = vadd(vadd(prev, nxt), d);
+      const V dn = cfma<CC>(tb[s + t], v[t], cmul<CC>(ta[s + t], sum));
+      prev = v[t];
+      v[t] = dn;
+      d = dn;
+    }
+  }
+  sh_B[p * LW + li] = d;
+  __syncthreads();
+  // incoming d_{s-1}: compose the earlier segments' maps D -> pi_end D + B
+  V D = vzero<V>();
+  for (int q = 0; q < p && q < nseg; ++q) D = cfma<CC>(tpi[min((q + 1) * m, n) - 1], D, sh_B[q * LW + li]);
+#pragma unroll
+  for (int t = 0; t < M; ++t)
+    if (t < len) v[t] = cfma<CC>(tpi[s + t], D, v[t]);
+
+  // backward recurrence over the segment from u_e = 0
+  V u = vzero<V>();
+#pragma unroll
+  for (int t = M - 1; t >= 0; --t) {
+    if (t < len) {
+      u = cfma<CC>(ta[s + t], u, v[t]);
+      v[t] = u;
+    }
+  }
+  sh_U[p * LW + li] = u;
+  __syncthreads();
+  V U = vzero<V>();
+  for (int q = nseg - 1; q > p; --q) U = cfma<CC>(trho[q * m], U, sh_U[q * LW + li]);
+#pragma unroll
+  for (int t = 0; t < M; ++t)
+    if (t < len) v[t] = cfma<CC>(trho[s + t], U, v[t]);
+
+#pragma unroll
+  for (int t = 0; t < M; ++t)
+    if (t < len && active) bstore(v[t], rs, voff, (uint32_t)t * srow);
+}
+
+// ---------------------------------------------------------------------------------------
+// z sweep.  Block = 4 wavefronts; a wavefront holds L = 64/nseg z lines, lane =
+// line-in-wave * nseg + segment.  Each iteration copies 4L consecutive lines (contiguous
+// in memory) into LDS, solves them, and copies them back.
+// ---------------------------------------------------------------------------------------
+template <typename R, int MZ, bool CC, bool NORM, int EPI>
+__global__ void __launch_bounds__(256)
+k_sweep_z(typename VecOf<R>::T* __restrict__ psi, const typename VecOf<R>::T* __restrict__ tab, int nz,
+          int m, int nseg, int64_t nlines, double* __restrict__ partials, const R* __restrict__ vx,
+          const R* __restrict__ vy, const R* __restrict__ vz, int ny, R tau,
+          const DevState* __restrict__ st) {
+  typedef typename VecOf<R>::T V;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  V* sdata = reinterpret_cast<V*>(smem_raw);
+  __shared__ double red[4];
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int L = 64 / nseg;
+  const int l = lane / nseg, p = lane % nseg;
+  const int lines_per_grp = 4 * L;
+  const int64_t ngrp = (nlines + lines_per_grp - 1) / lines_per_grp;
+  const int s = p * m;
+  const int len = max(0, min(m, nz - s));
+  const V* ta = tab;
+  const V* tb = tab + nz;
+  const V* tpi = tab + 2 * nz;
+  const V* trho = tab + 3 * nz;
+  R g = 0;
+  if (EPI != 0) g = (R)st->g;
+  double acc = 0.0;
+
+  for (int64_t grp = blockIdx.x; grp < ngrp; grp += gridDim.x) {
+    const int64_t line0 = grp * lines_per_grp;
+    const int nl = (int)min((int64_t)lines_per_grp, nlines - line0);
+    const int cnt = nl * nz;
+    const V* src = psi + line0 * nz;
+    for (int q = tid; q < cnt; q += 256) sdata[q] = src[q];
+    __syncthreads();
+
+    const int ll = w * L + l;
+    const bool act = (ll < nl) && (len > 0);
+    V* row = sdata + (act ? ll * nz : 0);
+    V v[MZ];
+#pragma unroll
+    for (int t = 0; t < MZ; ++t) v[t] = (act && t < len) ? row[s + t] : vzero<V>();
+    const V left = (act && s > 0) ? row[s - 1] : vzero<V>();
+    const V right = (act && s + len < nz) ? row[s + len] : vzero<V>();
+
+    V prev = left, d = vzero<V>();
+#pragma unroll
+    for (int t = 0; t < MZ; ++t) {
+      if (t < len) {
+        V nxt = right;
+        if (t + 1 < MZ && t + 1 < len) nxt = v[t + 1];
+        const V sum = vadd(vadd(prev, nxt), d);
+        const V dn = cfma<CC>(tb[s + t], v[t], cmul<CC>(ta[s + t], sum));
+        prev = v[t];
+        v[t] = dn;
+        d = dn;
+      }
+    }
+    // inclusive scan of the segment maps x -> A x + B along the line
+    V A = act ? tpi[s + len - 1] : vone<V>();
+    V B = act ? d : vzero<V>();
+    for (int off = 1; off < nseg; off <<= 1) {
+      const V Ap = shfl_up_v(A, off, nseg);
+      const V Bp = shfl_up_v(B, off, nseg);
+      if (p >= off) {
+        B = cfma<CC>(A, Bp, B);
+        A = cmul<CC>(A, Ap);
+      }
+    }
+    V D = shfl_up_v(B, 1, nseg);
+    if (p == 0) D = vzero<V>();
+#pragma unroll
+    for (int t = 0; t < MZ; ++t)
+      if (t < len) v[t] = cfma<CC>(tpi[s + t], D, v[t]);
+
+    V u = vzero<V>();
+#pragma unroll
+    for (int t = MZ - 1; t >= 0; --t) {
+      if (t < len) {
+        u = cfma<CC>(ta[s + t], u, v[t]);
+        v[t] = u;
+      }
+    }
+    V Ab = act ? trho[s] : vone<V>();
+    V Bu = act ? u : vzero<V>();
+    for (int off = 1; off < nseg; off <<= 1) {
+      const V Ap = shfl_down_v(Ab, off, nseg);
+      const V Bp = shfl_down_v(Bu, off, nseg);
+      if (p + off < nseg) {
+        Bu = cfma<CC>(Ab, Bp, Bu);
+        Ab = cmul<CC>(Ab, Ap);
+      }
+    }
+    V U = shfl_down_v(Bu, 1, nseg);
+    if (p == nseg - 1) U = vzero<V>();
+#pragma unroll
+    for (int t = 0; t < MZ; ++t)
+      if (t < len) v[t] = cfma<CC>(trho[s + t], U, v[t]);
+
+    if (act) {
+      R vxy = 0;
+      if (EPI != 0) {
+        const int64_t zl = line0 + ll;  // z line index = i*ny + j
+        vxy = vx[zl / ny] + vy[zl % ny];
+      }
+#pragma unroll
+      for (int t = 0; t < MZ; ++t) {
+        if (t < len) {
+          if (EPI != 0) v[t] = nstep<EPI, R, V>(v[t], (R)1, vxy + vz[s + t], g, tau);
+          if (NORM) acc = fma((double)v[t].x, (double)v[t].x, fma((double)v[t].y, (double)v[t].y, acc));
+          row[s + t] = v[t];
+        }
+      }
+    }
+    __syncthreads();
+    V* dst = psi + line0 * nz;
+    for (int q = tid; q < cnt; q += 256) dst[q] = sdata[q];
+    __syncthreads();
+  }
+  if (NORM) {
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) red[w] = acc;
+    __syncthreads();
+    if (tid == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// reductions and small kernels
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum_256(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  const double r = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(256)
+k_finalize_norm(const double* __restrict__ partials, int nb, double dV, double dt, DevState* st) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < nb; q += 256) acc += partials[q];
+  const double tot = block_sum_256(acc, red);
+  if (threadIdx.x == 0) {
+    const double npre = tot * dV;
+    int f = 0;
+    if (!isfinite(npre)) f = 1;
+    else if (!(npre > 0.0)) f = 2;
+    st->npre = npre;
+    st->mu_est = (f == 0) ? -log(npre) / (2.0 * dt) : 0.0;
+    st->flags |= f;
+    st->s = (f == 0) ? 1.0 / sqrt(npre) : 1.0;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_scale(typename VecOf<R>::T* __restrict__ psi, int64_t n, DevState* st) {
+  const R s = (R)st->s;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
+    typename VecOf<R>::T v = psi[q];
+    v.x *= s;
+    v.y *= s;
+    psi[q] = v;
+  }
+}
+
+__global__ void k_reset_scale(DevState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->s = 1.0;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_observables(const typename VecOf<R>::T* __restrict__ psi, int nx, int ny, int nz, const double* __restrict__ x2,
+              const double* __restrict__ y2, const double* __restrict__ z2, const double* __restrict__ vxt,
+              const double* __restrict__ vyt, const double* __restrict__ vzt, double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int64_t total = (int64_t)nx * ny * nz;
+  const int64_t sx = (int64_t)ny * nz;
+  double acc[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256) {
+    const int k = (int)(q % nz);
+    const int64_t r = q / nz;
+    const int j = (int)(r % ny);
+    const int i = (int)(r / ny);
+    const double re = psi[q].x, im = psi[q].y;
+    const double n2 = re * re + im * im;
+    double ex = 0, ey = 0, ez = 0, fx = 0, fy = 0, fz = 0;
+    if (i + 1 < nx) { ex = psi[q + sx].x; fx = psi[q + sx].y; }
+    if (j + 1 < ny) { ey = psi[q + nz].x; fy = psi[q + nz].y; }
+    if (k + 1 < nz) { ez = psi[q + 1].x; fz = psi[q + 1].y; }
+    double lx = (ex - re) * (ex - re) + (fx - im) * (fx - im);
+    double ly = (ey - re) * (ey - re) + (fy - im) * (fy - im);
+    double lz = (ez - re) * (ez - re) + (fz - im) * (fz - im);
+    if (i == 0) lx += n2;  // link from the zero ghost at -1
+    if (j == 0) ly += n2;
+    if (k == 0) lz += n2;
+    acc[0] += n2;
+    acc[1] += lx;
+    acc[2] += ly;
+    acc[3] += lz;
+    acc[4] += (vxt[i] + vyt[j] + vzt[k]) * n2;
+    acc[5] += n2 * n2;
+    acc[6] += x2[i] * n2;
+    acc[7] += y2[j] * n2;
+    acc[8] += z2[k] * n2;
+  }
+  for (int c = 0; c < 9; ++c) {
+    const double t = block_sum_256(acc[c], red);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * 9 + c] = t;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_obs_final(const double* __restrict__ partials, int nb, double* __restrict__ out) {
+  __shared__ double red[4];
+  for (int c = 0; c < 9; ++c) {
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) acc += partials[(int64_t)q * 9 + c];
+    const double t = block_sum_256(acc, red);
+    if (threadIdx.x == 0) out[c] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+template <typename R, int M, int SW, bool CC, int NSTEP>
+static hipError_t go_lines(const SweepLaunch& a, hipStream_t s) {
+  typedef typename VecOf<R>::T V;
+  constexpr int LW = 64 / SW;
+  const int waves = (a.nseg + SW - 1) / SW;
+  const size_t lds = (size_t)4 * waves * SW * LW * sizeof(V);
+  const int64_t blocks = (a.nlines + LW - 1) / LW;
+  hipLaunchKernelGGL((k_sweep_lines<R, M, SW, CC, NSTEP>), dim3((unsigned)blocks), dim3(waves * 64), lds, s,
+                     (V*)a.psi, a.psi_bytes, (const V*)a.tab, a.n, a.m, a.nseg, a.nlines, a.inner, (const R*)a.vx,
+                     (const R*)a.vy, (const R*)a.vz, a.nz, (R)a.tau, a.st);
+  return hipGetLastError();
+}
+
+template <typename R, int M, int SW>
+static hipError_t go_lines_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
+  if (!cc) return a.nstep ? go_lines<R, M, SW, false, 1>(a, s) : go_lines<R, M, SW, false, 0>(a, s);
+  return a.nstep ? go_lines<R, M, SW, true, 2>(a, s) : go_lines<R, M, SW, true, 0>(a, s);
+}
+
+bool sweep_lines_supported(int precision, int m, int sw) {
+  if (precision == 0) return (sw == 1 && (m == 8 || m == 16 || m == 32)) || (sw == 2 && m == 32);
+  return (sw == 1 && (m == 8 || m == 16)) || ((sw == 2 || sw == 4) && m == 16);
+}
+
+hipError_t launch_sweep_lines(int precision, bool cc, int maxm, const SweepLaunch& a, hipStream_t s) {
+  if (precision == 0) {
+    if (a.sw == 1 && maxm == 8) return go_lines_mode<float, 8, 1>(cc, a, s);
+    if (a.sw == 1 && maxm == 16) return go_lines_mode<float, 16, 1>(cc, a, s);
+    if (a.sw == 1 && maxm == 32) return go_lines_mode<float, 32, 1>(cc, a, s);
+    if (a.sw == 2 && maxm == 32) return go_lines_mode<float, 32, 2>(cc, a, s);
+  } else {
+    if (a.sw == 1 && maxm == 8) return go_lines_mode<double, 8, 1>(cc, a, s);
+    if (a.sw == 1 && maxm == 16) return go_lines_mode<double, 16, 1>(cc, a, s);
+    if (a.sw == 2 && maxm == 16) return go_lines_mode<double, 16, 2>(cc, a, s);
+    if (a.sw == 4 && maxm == 16) return go_lines_mode<double, 16, 4>(cc, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename R, int MZ, bool CC, bool NORM, int EPI>
+static hipError_t go_z(const SweepLaunch& a, hipStream_t s) {
+  typedef typename VecOf<R>::T V;
+  const int L = 64 / a.nseg;
+  const size_t lds = (size_t)4 * L * a.nz * sizeof(V);
+  hipLaunchKernelGGL((k_sweep_z<R, MZ, CC, NORM, EPI>), dim3(a.grid), dim3(256), lds, s, (V*)a.psi,
+                     (const V*)a.tab, a.nz, a.m, a.nseg, a.nlines, a.partials, (const R*)a.vx, (const R*)a.vy,
+                     (const R*)a.vz, a.ny, (R)a.tau, a.st);
+  return hipGetLastError();
+}
+
+template <typename R, int MZ>
+static hipError_t go_z_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
+  if (!cc) {  // imaginary time: FP64 norm partials
+    return a.nstep ? go_z<R, MZ, false, true, 1>(a, s) : go_z<R, MZ, false, true, 0>(a, s);
+  }
+  return a.nstep ? go_z<R, MZ, true, false, 2>(a, s) : go_z<R, MZ, true, false, 0>(a, s);
+}
+
+bool sweep_z_supported(int precision, int mz) {
+  (void)precision;
+  return mz == 4 || mz == 8 || mz == 16;
+}
+
+hipError_t launch_sweep_z(int precision, bool cc, int mz, const SweepLaunch& a, hipStream_t s) {
+  if (precision == 0) {
+    if (mz == 4) return go_z_mode<float, 4>(cc, a, s);
+    if (mz == 8) return go_z_mode<float, 8>(cc, a, s);
+    if (mz == 16) return go_z_mode<float, 16>(cc, a, s);
+  } else {
+    if (mz == 4) return go_z_mode<double, 4>(cc, a, s);
+    if (mz == 8) return go_z_mode<double, 8>(cc, a, s);
+    if (mz == 16) return go_z_mode<double, 16>(cc, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize_norm(const double* partials, int nb, double dV, double dt, DevState* st,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_norm, dim3(1), dim3(256), 0, s, partials, nb, dV, dt, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(int precision, void* psi, int64_t n, DevState* st, hipStream_t s) {
+  const int64_t want = (n + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+  if (precision == 0)
+    hipLaunchKernelGGL(k_scale<float>, dim3(blocks), dim3(256), 0, s, (float2*)psi, n, st);
+  else
+    hipLaunchKernelGGL(k_scale<double>, dim3(blocks), dim3(256), 0, s, (double2*)psi, n, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reset_scale, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_observables(int precision, const ObsLaunch& a, hipStream_t s) {
+  if (precision == 0)
+    hipLaunchKernelGGL(k_observables<float>, dim3(a.grid), dim3(256), 0, s, (const float2*)a.psi, a.nx, a.ny, a.nz,
+                       a.x2, a.y2, a.z2, a.vx, a.vy, a.vz, a.partials);
+  else
+    hipLaunchKernelGGL(k_observables<double>, dim3(a.grid), dim3(256), 0, s, (const double2*)a.psi, a.nx, a.ny,
+                       a.nz, a.x2, a.y2, a.z2, a.vx, a.vy, a.vz, a.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, s, a.partials, a.grid, a.out);
+  return hipGetLastError();
+}
+
+}  // namespace gpk

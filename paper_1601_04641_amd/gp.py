@@ -1,0 +1,225 @@
+"""Thin ctypes binding of the C-ABI in include/gp.h (libgpsscn.so).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels of the
+library.  torch is used for device memory (``psi`` tensors) and streams, nothing else.
+Functions carry the C names; :class:`Solver` bundles them around one context.
+``load()`` raises if the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpsscn.so")
+
+GP_OK, GP_ERR_INVALID, GP_ERR_HIP, GP_ERR_OOM = 0, -1, -2, -3
+GP_ERR_NONFINITE, GP_ERR_ZERO_NORM, GP_ERR_UNSUPPORTED = -4, -5, -6
+GP_C64, GP_C128 = 0, 1
+GP_SPLIT_LIE, GP_SPLIT_STRANG = 0, 1
+GP_FLAG_NONFINITE, GP_FLAG_ZERO_NORM = 1, 2
+
+# names declared in include/gp.h (checked against the built library by the tests)
+EXPORTS = ("gp_init", "gp_destroy", "gp_step_imag", "gp_step_real", "gp_norm", "gp_energy_mu",
+           "gp_rms", "gp_raw_sums", "gp_set_g", "gp_set_psi", "gp_status", "gp_converge_imag",
+           "gp_set_timing", "gp_get_timing", "gp_get_mapping", "gp_set_mapping", "gp_strerror",
+           "gp_last_error")
+
+
+class GPError(RuntimeError):
+    def __init__(self, code, where, detail=""):
+        self.code = code
+        msg = f"{where}: {gp_strerror(code)} ({code})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+class gp_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("nux", ctypes.c_double), ("nuy", ctypes.c_double), ("nuz", ctypes.c_double),
+                ("g", ctypes.c_double), ("dt", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("split", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raise if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "gp_init": [P(gp_params), vp, vp, P(vp)],
+        "gp_destroy": [vp],
+        "gp_step_imag": [vp, i32],
+        "gp_step_real": [vp, i32],
+        "gp_norm": [vp, P(d)],
+        "gp_energy_mu": [vp, P(d), P(d)],
+        "gp_rms": [vp, P(d)],
+        "gp_raw_sums": [vp, P(d)],
+        "gp_set_g": [vp, d],
+        "gp_set_psi": [vp, vp],
+        "gp_status": [vp, P(i64), P(d), P(i32)],
+        "gp_converge_imag": [vp, d, i32, i64, P(i64), P(d), P(i32)],
+        "gp_set_timing": [vp, i32],
+        "gp_get_timing": [vp, P(d), P(i64)],
+        "gp_get_mapping": [vp, P(i32)],
+        "gp_set_mapping": [vp, P(i32)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.gp_strerror.argtypes = [ctypes.c_int]
+    L.gp_strerror.restype = ctypes.c_char_p
+    L.gp_last_error.argtypes = [vp]
+    L.gp_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def gp_strerror(code: int) -> str:
+    return load().gp_strerror(int(code)).decode()
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_params(nx, ny, nz, dx, dy, dz, nux, nuy, nuz, g, dt, precision=GP_C128,
+                split=GP_SPLIT_LIE) -> gp_params:
+    return gp_params(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz), float(nux),
+                     float(nuy), float(nuz), float(g), float(dt), int(precision), int(split))
+
+
+def gp_init(params: gp_params, psi_ptr: int, stream_ptr: int):
+    """Returns (code, handle)."""
+    h = ctypes.c_void_p()
+    rc = load().gp_init(ctypes.byref(params), ctypes.c_void_p(psi_ptr), ctypes.c_void_p(stream_ptr),
+                        ctypes.byref(h))
+    return rc, h
+
+
+class Solver:
+    """One gp_ctx bound to a caller-owned complex torch tensor psi of shape (nx, ny, nz)."""
+
+    def __init__(self, psi, dx, dy, dz, nux, nuy, nuz, g, dt, split=GP_SPLIT_LIE, stream=None):
+        import torch
+        if not psi.is_cuda or not psi.is_contiguous() or psi.dim() != 3:
+            raise ValueError("psi must be a contiguous 3D device tensor")
+        if psi.dtype == torch.complex128:
+            prec = GP_C128
+        elif psi.dtype == torch.complex64:
+            prec = GP_C64
+        else:
+            raise ValueError("psi must be complex64 or complex128")
+        self.psi = psi
+        self.stream = stream if stream is not None else torch.cuda.current_stream(psi.device)
+        nx, ny, nz = psi.shape
+        self.params = make_params(nx, ny, nz, dx, dy, dz, nux, nuy, nuz, g, dt, prec, split)
+        with torch.cuda.device(psi.device):
+            rc, h = gp_init(self.params, psi.data_ptr(), self.stream.cuda_stream)
+        if rc != GP_OK:
+            raise GPError(rc, "gp_init")
+        self._h = h
+        self._L = load()
+
+    @classmethod
+    def from_workload(cls, psi, w: dict, split=GP_SPLIT_LIE, stream=None):
+        return cls(psi, w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"], w["nuz"], w["g"], w["dt"],
+                   split=split, stream=stream)
+
+    def _chk(self, rc, name):
+        if rc != GP_OK:
+            raise GPError(rc, name, self._L.gp_last_error(self._h).decode(errors="replace"))
+
+    def step_imag(self, n: int):
+        self._chk(self._L.gp_step_imag(self._h, int(n)), "gp_step_imag")
+
+    def step_real(self, n: int):
+        self._chk(self._L.gp_step_real(self._h, int(n)), "gp_step_real")
+
+    def norm(self) -> float:
+        v = ctypes.c_double()
+        self._chk(self._L.gp_norm(self._h, ctypes.byref(v)), "gp_norm")
+        return v.value
+
+    def energy_mu(self):
+        e, m = ctypes.c_double(), ctypes.c_double()
+        self._chk(self._L.gp_energy_mu(self._h, ctypes.byref(e), ctypes.byref(m)), "gp_energy_mu")
+        return e.value, m.value
+
+    def rms(self) -> np.ndarray:
+        out = np.zeros(4)
+        self._chk(self._L.gp_rms(self._h, _dp(out)), "gp_rms")
+        return out
+
+    def raw_sums(self) -> np.ndarray:
+        out = np.zeros(9)
+        self._chk(self._L.gp_raw_sums(self._h, _dp(out)), "gp_raw_sums")
+        return out
+
+    def set_g(self, g: float):
+        self._chk(self._L.gp_set_g(self._h, float(g)), "gp_set_g")
+
+    def set_psi(self, psi):
+        self._chk(self._L.gp_set_psi(self._h, ctypes.c_void_p(psi.data_ptr())), "gp_set_psi")
+        self.psi = psi
+
+    def status(self):
+        s, m, f = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int32()
+        self._chk(self._L.gp_status(self._h, ctypes.byref(s), ctypes.byref(m), ctypes.byref(f)), "gp_status")
+        return s.value, m.value, f.value
+
+    def converge_imag(self, tol=1e-7, check_every=0, max_steps=10 ** 7):
+        s, m, c = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int32()
+        self._chk(self._L.gp_converge_imag(self._h, float(tol), int(check_every), int(max_steps),
+                                           ctypes.byref(s), ctypes.byref(m), ctypes.byref(c)),
+                  "gp_converge_imag")
+        return s.value, m.value, bool(c.value)
+
+    def set_timing(self, on: bool):
+        self._chk(self._L.gp_set_timing(self._h, int(bool(on))), "gp_set_timing")
+
+    def get_timing(self):
+        ms = np.zeros(5)
+        n = np.zeros(5, dtype=np.int64)
+        self._chk(self._L.gp_get_timing(self._h, _dp(ms), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+                  "gp_get_timing")
+        return ms, n
+
+    def get_mapping(self):
+        out = (ctypes.c_int32 * 4)()
+        self._chk(self._L.gp_get_mapping(self._h, out), "gp_get_mapping")
+        return list(out)
+
+    def set_mapping(self, mx=0, my=0, segz=0, mz=0):
+        arr = (ctypes.c_int32 * 4)(int(mx), int(my), int(segz), int(mz))
+        self._chk(self._L.gp_set_mapping(self._h, arr), "gp_set_mapping")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.gp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

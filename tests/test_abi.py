@@ -1,0 +1,81 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every function
+include/gp.h declares, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1601_04641_amd import gp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gp[a-z_]*)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(gp.LIB_PATH):
+        from paper_1601_04641_amd import build
+        build.build()
+    return gp.load()
+
+
+def test_header_declares_the_binding_names():
+    assert set(declared("gp.h")) == set(gp.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared("gp.h"):
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_codes(lib):
+    assert gp.gp_strerror(gp.GP_OK) == "ok"
+    for code in (gp.GP_ERR_INVALID, gp.GP_ERR_HIP, gp.GP_ERR_OOM, gp.GP_ERR_NONFINITE,
+                 gp.GP_ERR_ZERO_NORM, gp.GP_ERR_UNSUPPORTED):
+        assert gp.gp_strerror(code) not in ("ok", "unknown error code")
+    assert gp.gp_strerror(12345) == "unknown error code"
+
+
+@pytest.mark.parametrize("field,value", [("nx", 2), ("ny", 0), ("dx", 0.0), ("dz", -1.0),
+                                         ("dt", 0.0), ("nuy", -0.5), ("g", float("nan")),
+                                         ("dt", float("inf")), ("precision", 2), ("split", 7)])
+def test_init_rejects_bad_params_without_device(lib, field, value):
+    p = gp.make_params(8, 8, 8, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001)
+    setattr(p, field, value)
+    rc, h = gp.gp_init(p, 0x1000, 0)
+    assert rc == gp.GP_ERR_INVALID and not h.value
+
+
+def test_init_rejects_oversized_grids_without_device(lib):
+    p = gp.make_params(2048, 8, 8, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001)
+    rc, _ = gp.gp_init(p, 0x1000, 0)
+    assert rc == gp.GP_ERR_UNSUPPORTED
+    p = gp.make_params(1024, 1024, 600, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001, gp.GP_C128)
+    rc, _ = gp.gp_init(p, 0x1000, 0)
+    assert rc == gp.GP_ERR_UNSUPPORTED
+
+
+def test_null_arguments(lib):
+    p = gp.make_params(8, 8, 8, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001)
+    assert lib.gp_init(ctypes.byref(p), None, None, None) == gp.GP_ERR_INVALID
+    assert lib.gp_step_imag(None, 1) == gp.GP_ERR_INVALID
+    assert lib.gp_step_real(None, 1) == gp.GP_ERR_INVALID
+    assert lib.gp_norm(None, None) == gp.GP_ERR_INVALID
+    assert lib.gp_destroy(None) == gp.GP_ERR_INVALID
+    assert lib.gp_last_error(None) == b"null context"
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(RuntimeError):
+        gp._lib_backup = gp._lib
+        try:
+            gp._lib = None
+            gp.load(str(tmp_path / "nope.so"))
+        finally:
+            gp._lib = gp._lib_backup
