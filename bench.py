@@ -1,0 +1,199 @@
+"""Benchmark: grid-point updates/s of the split-step Crank-Nicolson step on one MI355X.
+
+Workload: the real-time quench on a 512x480x448 grid (dx = 0.05, nu = (1, 1.4142, 1.7321),
+g = 100 -> 50, dt = 0.01 dx^2).  The state is prepared by a short imaginary-time run from
+the Gaussian, g is quenched, W untimed real-time steps run, then K timed real-time steps.
+A step is one full pass of the hot path: potential/nonlinear step + x sweep, y sweep,
+z sweep.  psi is resident in HBM when the timed region starts.
+
+Prints ONE JSON line on stdout.  The roofline object prices the dominant kernel: its
+algorithmic bytes per launch (2 x 8 B per point for complex64: one read and one write of
+psi) over its mean duration from HIP events recorded on the library's stream during the
+timed region.  cpu_baseline times the CPU FP64 oracle on host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
+KINDS = ("x_sweep", "y_sweep", "z_sweep", "norm_finalize", "other")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--prep", type=int, default=200, help="imaginary-time preparation steps")
+    ap.add_argument("--precision", choices=("c64", "c128"), default="c64")
+    ap.add_argument("--also-c128", action="store_true", default=True)
+    ap.add_argument("--no-also-c128", dest="also_c128", action="store_false")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    return ap.parse_args()
+
+
+def run_precision(torch, gp, inputs, w, prec, args):
+    nx, ny, nz = w["nx"], w["ny"], w["nz"]
+    npts = nx * ny * nz
+    dtype = torch.complex64 if prec == gp.GP_C64 else torch.complex128
+    # Thomas-Fermi-like seed is not needed for throughput; the Gaussian of the trap is the
+    # documented starting state of the preparation run.
+    psi0 = inputs.gaussian_psi(nx, ny, nz, w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"], w["nuz"],
+                               dtype=np.complex64 if prec == gp.GP_C64 else np.complex128)
+    psi = torch.from_numpy(psi0).to("cuda", dtype=dtype)
+    del psi0
+    prm = dict(w, dt=w["dt_imag"])
+    s_imag = gp.Solver.from_workload(psi, prm)
+    log(f"[bench] prep: {args.prep} imaginary steps ({'c64' if prec == gp.GP_C64 else 'c128'})")
+    s_imag.step_imag(args.prep)
+    e, mu = s_imag.energy_mu()
+    s_imag.close()
+    log(f"[bench] prepared state: mu={mu:.6f} E={e:.6f}")
+    s = gp.Solver.from_workload(psi, w)
+    s.set_g(w["g_quench"])
+    n0 = s.norm()
+    s.step_real(args.warmup)
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    log(f"[bench] timed: {args.steps} real-time steps")
+    t0 = time.perf_counter()
+    s.step_real(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, n = s.get_timing()
+    s.set_timing(False)
+    n1 = s.norm()
+    rms = s.rms()
+    mapping = s.get_mapping()
+    s.close()
+    del psi
+    torch.cuda.empty_cache()
+    wall = t1 - t0
+    esz = 8 if prec == gp.GP_C64 else 16
+    per_kernel = {}
+    for k, name in enumerate(KINDS[:3]):
+        if n[k]:
+            per_kernel[name] = dict(ms=float(ms[k]), launches=int(n[k]),
+                                    algorithmic_GBps=2 * esz * npts / (ms[k] * 1e-3) / 1e9)
+    return dict(npts=npts, wall=wall, ms=ms, n=n, per_kernel=per_kernel, esz=esz,
+                norm_drift=abs(n1 - n0) / n0, rms=rms.tolist(), mapping=mapping)
+
+
+def cpu_baseline(inputs, w, seconds):
+    import oracle
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    oracle.set_threads(nthreads)
+    psi0 = inputs.gaussian_psi(w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"], w["nuz"])
+    o = oracle.Oracle.from_params(dict(w, g=w["g_quench"]), psi0)
+    del psi0
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step_real(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 50:
+            break
+    npts = w["nx"] * w["ny"] * w["nz"]
+    o.close()
+    return dict(value=npts * steps / el, unit="grid-point updates/s", cores=nthreads, kind="oracle",
+                sample=f"{steps} real-time steps of the 512x480x448 quench workload, complex128 FP64 "
+                       f"oracle, OpenMP over lines, {el:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        log("bench.py runs on one GPU only: the multi-GPU decomposition is not built "
+            "(see DESIGN.md, 'Sharding'); use --gpus 1")
+        sys.exit(2)
+    import torch
+
+    from paper_1601_04641_amd import gp, inputs
+    gp.load()
+    w = dict(inputs.WORKLOADS["quench_512x480x448"])
+    res = {}
+    precs = [gp.GP_C64 if args.precision == "c64" else gp.GP_C128]
+    if args.also_c128 and precs[0] == gp.GP_C64:
+        precs.append(gp.GP_C128)
+    for prec in precs:
+        res[prec] = run_precision(torch, gp, inputs, w, prec, args)
+    if args.calib_copy:
+        n = 1 << 27  # 2^27 complex64 = 1 GiB
+        a = torch.empty(n, dtype=torch.complex64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {n * 8} bytes read, {n * 8} bytes written")
+        del a, b
+
+    main_r = res[precs[0]]
+    npts, K = main_r["npts"], args.steps
+    value = npts * K / main_r["wall"]
+    pk = main_r["per_kernel"]
+    dom = max(pk, key=lambda k: pk[k]["ms"])
+    achieved = pk[dom]["algorithmic_GBps"]
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            traffic = tj.get(f"{'c64' if precs[0] == gp.GP_C64 else 'c128'}:{dom}")
+        except Exception:
+            traffic = None
+    out = {
+        "metric": "grid-point updates/s per SSCN step (% HBM roofline); time-to-ground-state at mu tol 1e-7",
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["wall"] / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if precs[0] == gp.GP_C64 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "quench_512x480x448_real_time", "grid": [w["nx"], w["ny"], w["nz"]],
+                   "precision": "complex64 storage+sweeps, FP64 reductions" if precs[0] == gp.GP_C64
+                   else "complex128", "dx": w["dx"], "nu": [w["nux"], w["nuy"], w["nuz"]],
+                   "g": [w["g"], w["g_quench"]], "dt": w["dt"], "split": "lie",
+                   "prep_imag_steps": args.prep, "mapping": main_r["mapping"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM / 1e9,
+                     "unit": "GB/s", "frac": achieved / (PEAK_HBM / 1e9), "traffic": traffic},
+        "algorithmic_frac_of_hbm_peak": value * 3 * 2 * main_r["esz"] / PEAK_HBM,
+        "kernels": pk,
+        "norm_drift": main_r["norm_drift"],
+    }
+    if gp.GP_C128 in res and precs[0] != gp.GP_C128:
+        r = res[gp.GP_C128]
+        out["complex128"] = {"value": r["npts"] * K / r["wall"], "ms_per_step": r["wall"] / K * 1e3,
+                             "kernels": r["per_kernel"], "norm_drift": r["norm_drift"]}
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds:.0f} s")
+        out["cpu_baseline"] = cpu_baseline(inputs, w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -50,7 +50,7 @@ struct gp_ctx {
   Mapping map{};
 
   DevState* st = nullptr;      // device
-  void* tab[2][3] = {{nullptr}};  // [imag, real][axis], storage precision, 4n complex each
+  void* tab[2][3] = {{nullptr}};  // [imag, real][axis], storage precision, 5n complex each
   void* vtab[3] = {nullptr};      // storage-precision 1/2 nu^2 a^2
   double* vd[3] = {nullptr};      // FP64 potential tables
   double* a2[3] = {nullptr};      // FP64 coordinate squares
@@ -149,7 +149,7 @@ bool pick_z(int nz, size_t esize, int* seg_out, int* m_out) {
 // within-segment products pi_i, rho_i (segments of length m).  gamma_i is the Thomas
 // pivot inverse 1/(1 + 2c + c c'_{i-1}) with c'_i = -c gamma_i, c'_{-1} = 0.
 void cn_tables(int n, cd c, int m, std::vector<cd>& t) {
-  t.assign(4 * (size_t)n, cd(0, 0));
+  t.assign(5 * (size_t)n, cd(0, 0));
   cd cprev(0, 0);
   for (int i = 0; i < n; ++i) {
     const cd gam = 1.0 / (1.0 + 2.0 * c + c * cprev);
@@ -172,7 +172,8 @@ void cn_tables(int n, cd c, int m, std::vector<cd>& t) {
   }
 }
 
-int upload_complex(gp_ctx* c, void* dst, const std::vector<cd>& src) {
+// Upload a 5-row table; in complex64 storage row 4 receives the low part of row 1.
+int upload_table(gp_ctx* c, void* dst, const std::vector<cd>& src, int n) {
   if (c->p.precision == GP_C128) {
     HIPCHK(c, hipMemcpy(dst, src.data(), src.size() * sizeof(cd), hipMemcpyHostToDevice));
   } else {
@@ -180,6 +181,11 @@ int upload_complex(gp_ctx* c, void* dst, const std::vector<cd>& src) {
     for (size_t i = 0; i < src.size(); ++i) {
       f[2 * i] = (float)src[i].real();
       f[2 * i + 1] = (float)src[i].imag();
+    }
+    for (int i = 0; i < n; ++i) {
+      const cd b = src[n + i];
+      f[2 * (4 * (size_t)n + i)] = (float)(b.real() - (double)f[2 * (n + i)]);
+      f[2 * (4 * (size_t)n + i) + 1] = (float)(b.imag() - (double)f[2 * (n + i) + 1]);
     }
     HIPCHK(c, hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
   }
@@ -195,7 +201,7 @@ int build_tables(gp_ctx* c) {
     for (int a = 0; a < 3; ++a) {
       const double k = c->p.dt / (4.0 * d[a] * d[a]);
       cn_tables(n[a], mode == 0 ? cd(k, 0) : cd(0, k), m[a], t);
-      int rc = upload_complex(c, c->tab[mode][a], t);
+      int rc = upload_table(c, c->tab[mode][a], t, n[a]);
       if (rc) return rc;
     }
   return GP_OK;
@@ -468,7 +474,7 @@ int init_body(gp_ctx* c) {
   if ((rc = dalloc(c, &c->st, sizeof(DevState)))) return rc;
   for (int mode = 0; mode < 2; ++mode)
     for (int a = 0; a < 3; ++a)
-      if ((rc = dalloc(c, &c->tab[mode][a], 4 * (size_t)n[a] * c->esize))) return rc;
+      if ((rc = dalloc(c, &c->tab[mode][a], 5 * (size_t)n[a] * c->esize))) return rc;
   for (int a = 0; a < 3; ++a) {
     if ((rc = dalloc(c, &c->vtab[a], (size_t)n[a] * c->esize / 2))) return rc;
     if ((rc = dalloc(c, &c->vd[a], (size_t)n[a] * sizeof(double)))) return rc;

@@ -17,9 +17,10 @@ struct DevState {
   int32_t pad;
 };
 
-// Per-axis Crank-Nicolson coefficient table in storage precision, 4 rows of n complex
-// values: a_i = c gamma_i, b_i = (1-2c) gamma_i, pi_i = prod_{j=seg start..i} a_j,
-// rho_i = prod_{j=i..seg end-1} a_j (segments of length m along the line).
+// Per-axis Crank-Nicolson coefficient table in storage precision, 5 rows of n complex
+// values: a_i = c gamma_i, b_i = (1-2c) gamma_i (rounded), pi_i = prod_{j=seg start..i} a_j,
+// rho_i = prod_{j=i..seg end-1} a_j (segments of length m along the line), and
+// b_i - rounded(b_i) (the low part, used in complex64 storage only).
 struct SweepLaunch {
   void* psi;
   uint32_t psi_bytes;  // size of psi in bytes (< 4 GiB: buffer addressing)

@@ -16,7 +16,10 @@
 // Each Crank-Nicolson solve along a line,
 //   -c u_{i-1} + (1+2c) u_i - c u_{i+1} = c p_{i-1} + (1-2c) p_i + c p_{i+1},
 // is the Thomas algorithm written as two first-order linear recurrences with the
-// constant tables a_i = c gamma_i and b_i = (1-2c) gamma_i of the forward sweep:
+// constant tables a_i = c gamma_i and b_i = (1-2c) gamma_i of the forward sweep
+// (in complex64 storage b, which is close to unit modulus, is carried as an FP32 hi+lo
+// pair: rounding it to one float would make every real-time sweep non-unitary by ~1e-7
+// in the same direction, a norm drift linear in the step count):
 //   forward   d_i = a_i (p_{i-1} + p_{i+1} + d_{i-1}) + b_i p_i,   d_{-1} = 0
 //   backward  u_i = d_i + a_i u_{i+1},                             u_n = 0
 // A line is cut into segments of m points, one segment per thread.  Each thread runs
@@ -137,6 +140,7 @@ k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, uint32_t psi_bytes,
   const V* tb = tab + n;
   const V* tpi = tab + 2 * n;
   const V* trho = tab + 3 * n;
+  const V* tbl = tab + 4 * n;
 
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(psi, psi_bytes);
   const uint32_t voff = (uint32_t)((base + (int64_t)s * inner) * (int64_t)sizeof(V));
@@ -176,7 +180,9 @@ k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, uint32_t psi_bytes,
       V nxt = right;
       if (t + 1 < M && t + 1 < len) nxt = v[t + 1];
       const V sum = vadd(vadd(prev, nxt), d);
-      const V dn = cfma<CC>(tb[s + t], v[t], cmul<CC>(ta[s + t], sum));
+      V dn = cmul<CC>(ta[s + t], sum);
+      if (sizeof(R) == 4) dn = cfma<CC>(tbl[s + t], v[t], dn);  // low part of b (FP32 hi+lo pair)
+      dn = cfma<CC>(tb[s + t], v[t], dn);
       prev = v[t];
       v[t] = dn;
       d = dn;
@@ -240,6 +246,7 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, const typename VecOf<R>::T* __
   const V* tb = tab + nz;
   const V* tpi = tab + 2 * nz;
   const V* trho = tab + 3 * nz;
+  const V* tbl = tab + 4 * nz;
   R g = 0;
   if (EPI != 0) g = (R)st->g;
   double acc = 0.0;
@@ -268,7 +275,9 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, const typename VecOf<R>::T* __
         V nxt = right;
         if (t + 1 < MZ && t + 1 < len) nxt = v[t + 1];
         const V sum = vadd(vadd(prev, nxt), d);
-        const V dn = cfma<CC>(tb[s + t], v[t], cmul<CC>(ta[s + t], sum));
+        V dn = cmul<CC>(ta[s + t], sum);
+        if (sizeof(R) == 4) dn = cfma<CC>(tbl[s + t], v[t], dn);  // low part of b
+        dn = cfma<CC>(tb[s + t], v[t], dn);
         prev = v[t];
         v[t] = dn;
         d = dn;

@@ -221,7 +221,10 @@ def test_full_size_step_matches_oracle(prec, imag):
     say(f"  oracle done ({time.time() - t0:.1f}s)")
     err = rel_err(out, ref)
     say(f"  rel err {err:.2e}")
-    assert err <= (1e-13 if prec == gp.GP_C128 else 2e-6)
+    # imaginary time renormalises by a sum of 1.1e8 terms; the oracle's sequential FP64
+    # partial sums (~7e6 terms per thread) carry ~sqrt(7e6)*1.1e-16 = 3e-13 relative error
+    tol = (1e-12 if imag else 1e-13) if prec == gp.GP_C128 else 2e-6
+    assert err <= tol
 
 
 # ----------------------------------------------------------------------------------------
@@ -239,7 +242,12 @@ def test_real_time_norm_conserved(prec):
         n1 = s.norm()
     drift = abs(n1 - n0) / n0
     say(f"case: norm drift prec {prec}: {drift:.2e}")
-    assert drift <= (1e-12 if prec == gp.GP_C128 else 1e-4)
+    # complex128: FP64 roundoff.  complex64: the near-unit-modulus CN coefficient is
+    # carried as an FP32 hi+lo pair, which removes the ~1.7e-4 per-1000-step bias of a
+    # single-float coefficient; what remains is the per-point FP32 rounding of the phase
+    # factor and of the stored values, fixed per point from step to step, whose
+    # |psi|^2-weighted mean over a few hundred effective points is ~1e-9 per step.
+    assert drift <= (1e-12 if prec == gp.GP_C128 else 3e-5)
 
 
 @pytest.mark.parametrize("prec", [gp.GP_C128, gp.GP_C64])
