@@ -113,11 +113,13 @@ int gp_converge_imag(gp_ctx* c, double tol, int32_t check_every, int64_t max_ste
 int gp_set_timing(gp_ctx* c, int32_t enable);
 int gp_get_timing(gp_ctx* c, double ms_mean[5], int64_t launches[5]);
 
-/* Line mapping in use: {m_x, m_y, segments_z, m_z}; m = points per thread along x/y,
- * segments_z = threads per z line.  gp_set_mapping overrides it (0 = keep); invalid
- * combinations return GP_ERR_INVALID. */
-int gp_get_mapping(gp_ctx* c, int32_t map[4]);
-int gp_set_mapping(gp_ctx* c, const int32_t map[4]);
+/* Line mapping in use: {m_x, sw_x, m_y, sw_y, segments_z, m_z}.  m = points per thread
+ * along a line, sw = line segments per wavefront for the x and y sweeps (a wavefront then
+ * covers 64/sw lines), segments_z = threads per z line (power of two <= 64).
+ * gp_set_mapping overrides it (0 = keep / choose); combinations the kernels do not cover
+ * return GP_ERR_INVALID and leave the mapping unchanged.  Synchronises. */
+int gp_get_mapping(gp_ctx* c, int32_t map[6]);
+int gp_set_mapping(gp_ctx* c, const int32_t map[6]);
 
 const char* gp_strerror(int code);
 const char* gp_last_error(gp_ctx* c);

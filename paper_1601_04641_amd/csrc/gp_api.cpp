@@ -50,7 +50,9 @@ struct gp_ctx {
   Mapping map{};
 
   DevState* st = nullptr;      // device
-  void* tab[2][3] = {{nullptr}};  // [imag, real][axis], storage precision, 5n complex each
+  void* tab[2][3] = {{nullptr}};  // [imag, real][axis]: omega, storage precision, n complex
+  int nw[2][3] = {{0}};
+  double coef[2][3][8] = {{{0}}};  // a, b, b_lo, P = a^m as (re, im)
   void* vtab[3] = {nullptr};      // storage-precision 1/2 nu^2 a^2
   double* vd[3] = {nullptr};      // FP64 potential tables
   double* a2[3] = {nullptr};      // FP64 coordinate squares
@@ -102,106 +104,129 @@ bool bad_params(const gp_params* p) {
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// x/y line mapping: smallest supported m whose block (ceil(nseg/sw) wavefronts) fits 16.
-bool pick_lines(int prec, int n, int* m_out, int* sw_out) {
-  const int ms[] = {8, 16, 32};
-  for (int sw : {1, 2, 4})
-    for (int m : ms) {
-      if (!gpk::sweep_lines_supported(prec, m, sw)) continue;
-      if (ceil_div(ceil_div(n, m), sw) <= 16) {
+// x/y line mapping: m points per thread (the kernel instance's register count) and sw
+// segments per wavefront; a block holds ceil(ceil(n/m)/sw) <= 16 wavefronts.
+bool valid_lines(int prec, int n, int m, int sw) {
+  if (!gpk::sweep_lines_supported(prec, m, sw)) return false;
+  return ceil_div(ceil_div(n, m), sw) <= 16;
+}
+
+// Default: 16 points per thread; 4 segments per wavefront once a line has >= 16 segments
+// (16-line bundles, 8 wavefronts per block), else the fewest wavefronts-per-segment that
+// fit.  complex128 with the fused potential step uses 8 points per thread (register
+// budget).  gp_set_mapping / the autotuner can override this.
+bool pick_lines(int prec, int n, bool nstep, int* m_out, int* sw_out) {
+  const int m0 = (prec == GP_C128 && nstep) ? 8 : 16;
+  const int pref_sw = ceil_div(n, m0) >= 16 ? 4 : 1;
+  for (int m = m0; m <= 32; m *= 2) {
+    if (valid_lines(prec, n, m, pref_sw)) {
+      *m_out = m;
+      *sw_out = pref_sw;
+      return true;
+    }
+    for (int sw : {1, 2, 4})
+      if (valid_lines(prec, n, m, sw)) {
         *m_out = m;
         *sw_out = sw;
         return true;
       }
-    }
+  }
   return false;
 }
 
-// register-array size of the kernel instance that runs m points per thread (0: none)
-int lines_maxm(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 0; }
-int z_maxm(int m) { return m <= 4 ? 4 : m <= 8 ? 8 : 16; }
-
-bool valid_lines(int prec, int n, int m, int sw) {
-  if (m < 1 || sw < 1 || lines_maxm(m) == 0) return false;
-  if (!gpk::sweep_lines_supported(prec, lines_maxm(m), sw)) return false;
-  return ceil_div(ceil_div(n, m), sw) <= 16;
-}
-
+// z mapping: seg threads per line (power of two <= 64), m points per thread (an instance
+// size), seg*m >= nz, block LDS (4 wavefronts x 64/seg lines x nz values + 512 B) <= 64 KiB.
 bool valid_z(int nz, int seg, int m, size_t esize) {
-  if (seg < 1 || seg > 64 || (seg & (seg - 1)) != 0) return false;
-  if (m < 1 || m > 16) return false;
-  // LDS: 4 wavefronts x (64/seg) lines x nz values, plus 32 B of static reduction space
-  if ((size_t)4 * (64 / seg) * nz * esize + 64 > 65536) return false;
-  return (int64_t)seg * m >= nz;  // trailing empty segments act as identity maps
+  if (seg < 2 || seg > 64 || (seg & (seg - 1)) != 0) return false;
+  if (!gpk::sweep_z_supported(0, m)) return false;
+  if ((size_t)4 * (64 / seg) * nz * esize + 512 > 65536) return false;
+  return (int64_t)seg * m >= nz;  // trailing positions are zero-coefficient padding
 }
 
 bool pick_z(int nz, size_t esize, int* seg_out, int* m_out) {
-  int seg = 4;
-  while (seg < 64 && seg * 8 < nz) seg <<= 1;
-  const int m = ceil_div(nz, seg);
-  if (!valid_z(nz, seg, m, esize)) return false;
-  *seg_out = seg;
-  *m_out = m;
+  const int ms[] = {2, 4, 6, 7, 8, 12, 16};
+  int best_seg = 0, best_m = 0;
+  long best_score = -1;
+  for (int seg = 64; seg >= 2; seg >>= 1)
+    for (int m : ms) {
+      if (!valid_z(nz, seg, m, esize)) continue;
+      const long waste = (long)seg * m - nz;
+      const long score = waste * 16 + std::abs(m - 8);
+      if (best_score < 0 || score < best_score) {
+        best_score = score;
+        best_seg = seg;
+        best_m = m;
+      }
+      break;  // smallest m for this seg
+    }
+  if (best_score < 0) return false;
+  *seg_out = best_seg;
+  *m_out = best_m;
   return true;
 }
 
-// Crank-Nicolson tables of one axis: a_i = c gamma_i, b_i = (1-2c) gamma_i, and the
-// within-segment products pi_i, rho_i (segments of length m).  gamma_i is the Thomas
-// pivot inverse 1/(1 + 2c + c c'_{i-1}) with c'_i = -c gamma_i, c'_{-1} = 0.
-void cn_tables(int n, cd c, int m, std::vector<cd>& t) {
-  t.assign(5 * (size_t)n, cd(0, 0));
-  cd cprev(0, 0);
+// Constant-pivot Crank-Nicolson solve along one axis (see gp_kernels.hip): c'_inf is the
+// root of modulus < 1 of c x^2 + (1+2c) x + c = 0 (taken in the cancellation-free form
+// -2c / ((1+2c) +- sqrt((1+2c)^2 - 4c^2))), gamma = 1/(1 + 2c + c c'_inf), a = c gamma,
+// b = (1-2c) gamma, kappa = c c'_inf.  omega = kappa w / (1 - kappa w_0) with
+// w = A'^{-1} e_0 (forward d_i = gamma a^i, backward w_i = d_i + a w_{i+1}); nw counts
+// the leading omega_i above 1/100 of the storage precision's unit roundoff.
+int build_axis_table(gp_ctx* c, int mode, int axis) {
+  const int n = axis == 0 ? c->p.nx : axis == 1 ? c->p.ny : c->p.nz;
+  const double d = axis == 0 ? c->p.dx : axis == 1 ? c->p.dy : c->p.dz;
+  const int m = axis == 0 ? c->map.mx : axis == 1 ? c->map.my : c->map.mz;
+  const double k = c->p.dt / (4.0 * d * d);
+  const cd cc = mode == 0 ? cd(k, 0) : cd(0, k);
+  const cd s1 = 1.0 + 2.0 * cc;
+  const cd disc = std::sqrt(s1 * s1 - 4.0 * cc * cc);
+  const cd q = std::abs(s1 + disc) >= std::abs(s1 - disc) ? s1 + disc : s1 - disc;
+  const cd cpinf = -2.0 * cc / q;
+  const cd gam = 1.0 / (1.0 + 2.0 * cc + cc * cpinf);
+  const cd a = cc * gam, b = (1.0 - 2.0 * cc) * gam, kappa = cc * cpinf;
+  cd P(1, 0);
+  for (int i = 0; i < m; ++i) P *= a;
+  std::vector<cd> w(n);
+  cd dd = gam;
   for (int i = 0; i < n; ++i) {
-    const cd gam = 1.0 / (1.0 + 2.0 * c + c * cprev);
-    cprev = -c * gam;
-    t[i] = c * gam;
-    t[n + i] = (1.0 - 2.0 * c) * gam;
+    w[i] = dd;
+    dd *= a;
   }
-  for (int s = 0; s < n; s += m) {
-    const int e = std::min(s + m, n);
-    cd pr(1, 0);
-    for (int i = s; i < e; ++i) {
-      pr *= t[i];
-      t[2 * n + i] = pr;
-    }
-    cd rr(1, 0);
-    for (int i = e - 1; i >= s; --i) {
-      rr *= t[i];
-      t[3 * n + i] = rr;
-    }
+  for (int i = n - 2; i >= 0; --i) w[i] += a * w[i + 1];
+  const cd beta = kappa / (1.0 - kappa * w[0]);
+  const bool f32 = c->p.precision == GP_C64;
+  const double thr = 0.01 * (f32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53));
+  int nw = 0;
+  for (int i = 0; i < n; ++i)
+    if (std::abs(beta * w[i]) > thr) nw = i + 1;
+  auto rnd = [&](cd v) { return f32 ? cd((float)v.real(), (float)v.imag()) : v; };
+  const cd rb = rnd(b);
+  const cd vals[4] = {rnd(a), rb, f32 ? rnd(b - rb) : cd(0, 0), rnd(P)};
+  for (int q2 = 0; q2 < 4; ++q2) {
+    c->coef[mode][axis][2 * q2] = vals[q2].real();
+    c->coef[mode][axis][2 * q2 + 1] = vals[q2].imag();
   }
-}
-
-// Upload a 5-row table; in complex64 storage row 4 receives the low part of row 1.
-int upload_table(gp_ctx* c, void* dst, const std::vector<cd>& src, int n) {
-  if (c->p.precision == GP_C128) {
-    HIPCHK(c, hipMemcpy(dst, src.data(), src.size() * sizeof(cd), hipMemcpyHostToDevice));
+  c->nw[mode][axis] = nw;
+  if (nw == 0) return GP_OK;
+  if (f32) {
+    std::vector<float> f(2 * (size_t)nw);
+    for (int i = 0; i < nw; ++i) {
+      const cd o = beta * w[i];
+      f[2 * i] = (float)o.real();
+      f[2 * i + 1] = (float)o.imag();
+    }
+    HIPCHK(c, hipMemcpy(c->tab[mode][axis], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
   } else {
-    std::vector<float> f(2 * src.size());
-    for (size_t i = 0; i < src.size(); ++i) {
-      f[2 * i] = (float)src[i].real();
-      f[2 * i + 1] = (float)src[i].imag();
-    }
-    for (int i = 0; i < n; ++i) {
-      const cd b = src[n + i];
-      f[2 * (4 * (size_t)n + i)] = (float)(b.real() - (double)f[2 * (n + i)]);
-      f[2 * (4 * (size_t)n + i) + 1] = (float)(b.imag() - (double)f[2 * (n + i) + 1]);
-    }
-    HIPCHK(c, hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    std::vector<cd> o(nw);
+    for (int i = 0; i < nw; ++i) o[i] = beta * w[i];
+    HIPCHK(c, hipMemcpy(c->tab[mode][axis], o.data(), o.size() * sizeof(cd), hipMemcpyHostToDevice));
   }
   return GP_OK;
 }
 
 int build_tables(gp_ctx* c) {
-  const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
-  const double d[3] = {c->p.dx, c->p.dy, c->p.dz};
-  const int m[3] = {c->map.mx, c->map.my, c->map.mz};
-  std::vector<cd> t;
   for (int mode = 0; mode < 2; ++mode)
     for (int a = 0; a < 3; ++a) {
-      const double k = c->p.dt / (4.0 * d[a] * d[a]);
-      cn_tables(n[a], mode == 0 ? cd(k, 0) : cd(0, k), m[a], t);
-      int rc = upload_table(c, c->tab[mode][a], t, n[a]);
+      int rc = build_axis_table(c, mode, a);
       if (rc) return rc;
     }
   return GP_OK;
@@ -220,11 +245,13 @@ gpk::SweepLaunch lines_args(gp_ctx* c, int axis, int mode) {
   const gp_params& p = c->p;
   a.psi = c->psi;
   a.psi_bytes = (uint32_t)(c->npts * (int64_t)c->esize);
-  a.tab = c->tab[mode][axis];
   a.n = axis == 0 ? p.nx : p.ny;
   a.m = axis == 0 ? c->map.mx : c->map.my;
   a.sw = axis == 0 ? c->map.swx : c->map.swy;
   a.nseg = ceil_div(a.n, a.m);
+  for (int q = 0; q < 8; ++q) a.coef[q] = c->coef[mode][axis][q];
+  a.omega = c->tab[mode][axis];
+  a.nw = c->nw[mode][axis];
   a.nlines = axis == 0 ? (int64_t)p.ny * p.nz : (int64_t)p.nx * p.nz;
   a.inner = axis == 0 ? (int64_t)p.ny * p.nz : (int64_t)p.nz;
   a.nstep = 0;
@@ -245,7 +272,9 @@ gpk::SweepLaunch z_args(gp_ctx* c, int mode) {
   gpk::SweepLaunch a{};
   const gp_params& p = c->p;
   a.psi = c->psi;
-  a.tab = c->tab[mode][2];
+  for (int q = 0; q < 8; ++q) a.coef[q] = c->coef[mode][2][q];
+  a.omega = c->tab[mode][2];
+  a.nw = c->nw[mode][2];
   a.n = p.nz;
   a.m = c->map.mz;
   a.nseg = c->map.segz;
@@ -317,12 +346,11 @@ int enqueue_step(gp_ctx* c, int mode, hipStream_t s) {
   const int prec = c->p.precision;
   const bool cc = mode == 1;
   gpk::SweepLaunch ax = lines_args(c, 0, mode), ay = lines_args(c, 1, mode), az = z_args(c, mode);
-  const int mxm = lines_maxm(c->map.mx), mym = lines_maxm(c->map.my), mzm = z_maxm(c->map.mz);
-  int rc = timed(c, s, 0, [&](hipStream_t t) { return gpk::launch_sweep_lines(prec, cc, mxm, ax, t); });
+  int rc = timed(c, s, 0, [&](hipStream_t t) { return gpk::launch_sweep_lines(prec, cc, ax, t); });
   if (rc) return rc;
-  rc = timed(c, s, 1, [&](hipStream_t t) { return gpk::launch_sweep_lines(prec, cc, mym, ay, t); });
+  rc = timed(c, s, 1, [&](hipStream_t t) { return gpk::launch_sweep_lines(prec, cc, ay, t); });
   if (rc) return rc;
-  rc = timed(c, s, 2, [&](hipStream_t t) { return gpk::launch_sweep_z(prec, cc, mzm, az, t); });
+  rc = timed(c, s, 2, [&](hipStream_t t) { return gpk::launch_sweep_z(prec, cc, az, t); });
   if (rc) return rc;
   if (mode == 0) {
     const double dV = c->p.dx * c->p.dy * c->p.dz;
@@ -462,7 +490,7 @@ int check_psi(gp_ctx* c, void* psi) {
 int init_body(gp_ctx* c) {
   const gp_params& p = c->p;
   const int prec = p.precision;
-  if (!pick_lines(prec, p.nx, &c->map.mx, &c->map.swx) || !pick_lines(prec, p.ny, &c->map.my, &c->map.swy) ||
+  if (!pick_lines(prec, p.nx, true, &c->map.mx, &c->map.swx) || !pick_lines(prec, p.ny, false, &c->map.my, &c->map.swy) ||
       !pick_z(p.nz, c->esize, &c->map.segz, &c->map.mz)) {
     snprintf(c->err, sizeof(c->err), "grid %dx%dx%d exceeds the supported line lengths", p.nx, p.ny, p.nz);
     return GP_ERR_UNSUPPORTED;
@@ -474,7 +502,7 @@ int init_body(gp_ctx* c) {
   if ((rc = dalloc(c, &c->st, sizeof(DevState)))) return rc;
   for (int mode = 0; mode < 2; ++mode)
     for (int a = 0; a < 3; ++a)
-      if ((rc = dalloc(c, &c->tab[mode][a], 5 * (size_t)n[a] * c->esize))) return rc;
+      if ((rc = dalloc(c, &c->tab[mode][a], (size_t)n[a] * c->esize))) return rc;
   for (int a = 0; a < 3; ++a) {
     if ((rc = dalloc(c, &c->vtab[a], (size_t)n[a] * c->esize / 2))) return rc;
     if ((rc = dalloc(c, &c->vd[a], (size_t)n[a] * sizeof(double)))) return rc;
@@ -695,32 +723,50 @@ int gp_get_timing(gp_ctx* c, double ms_mean[5], int64_t launches[5]) {
   return GP_OK;
 }
 
-int gp_get_mapping(gp_ctx* c, int32_t map[4]) {
+int gp_get_mapping(gp_ctx* c, int32_t map[6]) {
   if (!c || !map) return GP_ERR_INVALID;
   map[0] = c->map.mx;
-  map[1] = c->map.my;
-  map[2] = c->map.segz;
-  map[3] = c->map.mz;
+  map[1] = c->map.swx;
+  map[2] = c->map.my;
+  map[3] = c->map.swy;
+  map[4] = c->map.segz;
+  map[5] = c->map.mz;
   return GP_OK;
 }
 
-int gp_set_mapping(gp_ctx* c, const int32_t map[4]) {
+int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
   if (!c || !map) return GP_ERR_INVALID;
   Mapping nm = c->map;
   const int prec = c->p.precision;
-  auto pick_sw = [&](int n, int m, int* sw) {
+  // x and y: points per thread and segments per wavefront (0 keeps the current value)
+  auto lines = [&](int n, int m_in, int sw_in, int* m, int* sw) {
+    const int mm = m_in > 0 ? m_in : *m;  // must be an instance size (8, 16, 32)
+    if (sw_in > 0) {
+      if (!valid_lines(prec, n, mm, sw_in)) return false;
+      *m = mm;
+      *sw = sw_in;
+      return true;
+    }
     for (int s : {1, 2, 4})
-      if (valid_lines(prec, n, m, s)) {
+      if (valid_lines(prec, n, mm, s)) {
+        *m = mm;
         *sw = s;
         return true;
       }
     return false;
   };
-  if (map[0] > 0 && !(nm.mx = map[0], pick_sw(c->p.nx, nm.mx, &nm.swx))) return GP_ERR_INVALID;
-  if (map[1] > 0 && !(nm.my = map[1], pick_sw(c->p.ny, nm.my, &nm.swy))) return GP_ERR_INVALID;
-  if (map[2] > 0 || map[3] > 0) {
-    const int seg = map[2] > 0 ? map[2] : nm.segz;
-    const int m = map[3] > 0 ? map[3] : ceil_div(c->p.nz, seg);
+  if ((map[0] > 0 || map[1] > 0) && !lines(c->p.nx, map[0], map[1], &nm.mx, &nm.swx)) return GP_ERR_INVALID;
+  if ((map[2] > 0 || map[3] > 0) && !lines(c->p.ny, map[2], map[3], &nm.my, &nm.swy)) return GP_ERR_INVALID;
+  if (map[4] > 0 || map[5] > 0) {
+    const int seg = map[4] > 0 ? map[4] : nm.segz;
+    int m = map[5];
+    if (m <= 0) {  // smallest instance size that covers the line
+      for (int cand : {2, 4, 6, 7, 8, 12, 16})
+        if ((int64_t)seg * cand >= c->p.nz) {
+          m = cand;
+          break;
+        }
+    }
     if (!valid_z(c->p.nz, seg, m, c->esize)) return GP_ERR_INVALID;
     nm.segz = seg;
     nm.mz = m;

@@ -17,16 +17,17 @@ struct DevState {
   int32_t pad;
 };
 
-// Per-axis Crank-Nicolson coefficient table in storage precision, 5 rows of n complex
-// values: a_i = c gamma_i, b_i = (1-2c) gamma_i (rounded), pi_i = prod_{j=seg start..i} a_j,
-// rho_i = prod_{j=i..seg end-1} a_j (segments of length m along the line), and
-// b_i - rounded(b_i) (the low part, used in complex64 storage only).
+// Per-axis Crank-Nicolson constants of the constant-pivot solve (see gp_kernels.hip):
+// coef = {a, b, b_lo, P} as (re, im) pairs, P = a^m; omega[nw] (storage precision,
+// device) the Sherman-Morrison head correction.
 struct SweepLaunch {
   void* psi;
   uint32_t psi_bytes;  // size of psi in bytes (< 4 GiB: buffer addressing)
-  const void* tab;
+  double coef[8];
+  const void* omega;
+  int nw;
   int n;            // points along the swept axis
-  int m;            // points per thread segment
+  int m;            // points per thread segment (= the kernel instance's register count)
   int nseg;         // segments per line
   int64_t nlines;   // number of lines
   int64_t inner;    // x sweep: ny*nz; y sweep: nz (line l -> base (l/inner)*n*inner + l%inner)
@@ -44,8 +45,8 @@ struct SweepLaunch {
 };
 
 // precision: 0 complex64, 1 complex128; cc: complex coefficients (real time)
-hipError_t launch_sweep_lines(int precision, bool cc, int maxm, const SweepLaunch& a, hipStream_t s);
-hipError_t launch_sweep_z(int precision, bool cc, int mz, const SweepLaunch& a, hipStream_t s);
+hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipStream_t s);
+hipError_t launch_sweep_z(int precision, bool cc, const SweepLaunch& a, hipStream_t s);
 
 hipError_t launch_finalize_norm(const double* partials, int nb, double dV, double dt, DevState* st,
                                 hipStream_t s);

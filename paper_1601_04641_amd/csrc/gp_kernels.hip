@@ -25,8 +25,8 @@
 // A line is cut into segments of m points, one segment per thread.  Each thread runs
 // both recurrences over its segment from a zero start; the true start values follow
 // from composing the segments' affine maps x -> A x + B (A = product of a over the
-// segment), and the fix-up d_i += pi_i D_in, u_i += rho_i U_in uses the tabulated
-// within-segment products pi, rho.  This is algebraically the same elimination as the
+// segment), and the fix-ups d_i += (a_s..a_i) D_in, u_i += (a_i..a_e-1) U_in run as
+// running products.  This is algebraically the same elimination as the
 // serial Thomas sweep (only rounding order differs) and needs no d' storage beyond the
 // segment held in registers, so psi is read once and written once per sweep.
 #include "gp_internal.h"
@@ -107,40 +107,68 @@ template <typename V> __device__ __forceinline__ V shfl_down_v(V v, int off, int
 }
 
 // ---------------------------------------------------------------------------------------
+// Constant-pivot form of the solve.  The Thomas pivots of A = tridiag(-c, 1+2c, -c)
+// converge to gamma_inf = 1/(1 + 2c + c c'_inf), c'_inf the root of modulus < 1 of
+// c x^2 + (1+2c) x + c = 0.  Running the elimination with gamma_inf from the first row on
+// solves A' = A + kappa e_0 e_0^T, kappa = c c'_inf, exactly; the solution of A follows
+// from the Sherman-Morrison identity u = u' + omega u'_0 with
+// omega = kappa A'^{-1} e_0 / (1 - kappa (A'^{-1} e_0)_0), which decays like c'_inf^i,
+// so only the first nw points of a line are corrected (nw: last |omega_i| above the
+// storage precision's rounding level).  The sweeps therefore use three constants:
+//   a = c gamma_inf, b = (1-2c) gamma_inf (complex64 storage: b as an FP32 hi+lo pair)
+// and P = a^M, the product of a over a full segment.  Points past the end of a line
+// (padding of a last segment) are forced to zero in the backward recurrence, which is
+// all the exact solve needs (their forward values never reach a stored point).
+// ---------------------------------------------------------------------------------------
+template <typename V> struct Coef {
+  V a, b, bl;
+};
+
+// one forward-recurrence point: d = a (prev + next + d) + (b + b_lo) p
+template <bool CC, typename R, typename V>
+__device__ __forceinline__ V fwd_point(const Coef<V>& c, V prev, V nxt, V d, V p) {
+  const V sum = vadd(vadd(prev, nxt), d);
+  V dn = cmul<CC>(c.a, sum);
+  if (sizeof(R) == 4) dn = cfma<CC>(c.bl, p, dn);  // low part of b (complex64 storage)
+  return cfma<CC>(c.b, p, dn);
+}
+
+// ---------------------------------------------------------------------------------------
 // x / y sweep.  Block = ceil(nseg/SW) wavefronts; a wavefront holds SW segments of
 // LW = 64/SW consecutive lines (lane = segment-in-wave * LW + line).  Lines l of a block
-// are blockIdx.x*LW + [0, LW); element i of line l sits at base(l) + i*inner.
+// are blockIdx.x*LW + [0, LW) (lanes past the last line repeat it: they compute and store
+// identical values); element i of line l sits at base(l) + i*inner.  Each thread holds M
+// consecutive points of one line in registers.  nwi > 0: the omega correction is applied
+// here (nwi <= M, so it stays inside segment 0); otherwise k_head_correction follows.
 // ---------------------------------------------------------------------------------------
 template <typename R, int M, int SW, bool CC, int NSTEP>
 __global__ void __launch_bounds__(1024)
-k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, uint32_t psi_bytes,
-              const typename VecOf<R>::T* __restrict__ tab,
-              int n, int m, int nseg, int64_t nlines, int64_t inner, const R* __restrict__ vline,
-              const R* __restrict__ vy, const R* __restrict__ vz, int nz, R tau,
-              const DevState* __restrict__ st) {
+k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, uint32_t psi_bytes, typename VecOf<R>::T ca,
+              typename VecOf<R>::T cb, typename VecOf<R>::T cbl, typename VecOf<R>::T cP,
+              const typename VecOf<R>::T* __restrict__ omega, int nwi, int n, int nseg, int64_t nlines,
+              int64_t inner, const R* __restrict__ vline, const R* __restrict__ vy, const R* __restrict__ vz, int nz,
+              R tau, const DevState* __restrict__ st) {
   typedef typename VecOf<R>::T V;
   constexpr int LW = 64 / SW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nslot = (int)(blockDim.x >> 6) * SW;  // segment slots in this block
-  V* sh_first = reinterpret_cast<V*>(smem_raw);
+  V* sh_first = reinterpret_cast<V*>(smem_raw);  // reused for the backward exchange
   V* sh_last = sh_first + nslot * LW;
   V* sh_B = sh_last + nslot * LW;
-  V* sh_U = sh_B + nslot * LW;
+  V* sh_U = sh_first;
 
   const int lane = threadIdx.x & 63;
   const int li = lane % LW;
-  const int p = (SW == 1) ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))
-                          : (int)(threadIdx.x >> 6) * SW + lane / LW;
-  const int64_t line = (int64_t)blockIdx.x * LW + li;
-  const bool active = line < nlines;
-  const int64_t base = active ? (line / inner) * (inner * n) + (line % inner) : 0;
-  const int s = p * m;
-  const int len = max(0, min(m, n - s));
-  const V* ta = tab;
-  const V* tb = tab + n;
-  const V* tpi = tab + 2 * n;
-  const V* trho = tab + 3 * n;
-  const V* tbl = tab + 4 * n;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int p = (SW == 1) ? w : w * SW + lane / LW;
+  const int64_t line = min((int64_t)blockIdx.x * LW + li, nlines - 1);
+  const int64_t base = (line / inner) * (inner * n) + (line % inner);
+  const int s = p * M;
+  const int len = max(0, min(M, n - s));
+  Coef<V> cf;
+  cf.a = ca;
+  cf.b = cb;
+  cf.bl = cbl;
 
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(psi, psi_bytes);
   const uint32_t voff = (uint32_t)((base + (int64_t)s * inner) * (int64_t)sizeof(V));
@@ -149,87 +177,121 @@ k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, uint32_t psi_bytes,
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     v[t] = vzero<V>();
-    if (t < len && active) bload(v[t], rs, voff, (uint32_t)t * srow);
+    if (t < len) bload(v[t], rs, voff, (uint32_t)t * srow);
   }
   if (NSTEP != 0) {
     const R scale = (R)st->s;
     const R g = (R)st->g;
-    R vyz = 0;
-    if (active) vyz = vy[line / nz] + vz[line % nz];  // x-sweep line index = j*nz + k
+    const R vyz = vy[line / nz] + vz[line % nz];  // x-sweep line index = j*nz + k
 #pragma unroll
-    for (int t = 0; t < M; ++t)
-      if (t < len) v[t] = nstep<NSTEP, R, V>(v[t], scale, vline[s + t] + vyz, g, tau);
+    for (int t = 0; t < M; ++t) {
+      const int pos = min(s + t, n - 1);
+      v[t] = nstep<NSTEP, R, V>(v[t], scale, vline[pos] + vyz, g, tau);  // padding stays 0
+    }
   }
 
-  // neighbours across segment boundaries (right-hand side of the first and last rows)
-  V last = v[0];
-#pragma unroll
-  for (int t = 1; t < M; ++t)
-    if (t == len - 1) last = v[t];
+  // neighbours across segment boundaries (right-hand side of the first and last rows);
+  // a segment that ends early is the line's last, so nobody reads its last value
   sh_first[p * LW + li] = v[0];
-  sh_last[p * LW + li] = last;
+  sh_last[p * LW + li] = v[M - 1];
   __syncthreads();
   const V left = (p > 0 && p < nseg) ? sh_last[(p - 1) * LW + li] : vzero<V>();
   const V right = (p < nseg - 1) ? sh_first[(p + 1) * LW + li] : vzero<V>();
 
   // forward recurrence over the segment from d_{s-1} = 0
-  V prev = left, d = vzero<V>();
+  {
+    V prev = left, d = vzero<V>();
 #pragma unroll
-  for (int t = 0; t < M; ++t) {
-    if (t < len) {
+    for (int t = 0; t < M; ++t) {
       V nxt = right;
-      if (t + 1 < M && t + 1 < len) nxt = v[t + 1];
-      const V sum = vadd(vadd(prev, nxt), d);
-      V dn = cmul<CC>(ta[s + t], sum);
-      if (sizeof(R) == 4) dn = cfma<CC>(tbl[s + t], v[t], dn);  // low part of b (FP32 hi+lo pair)
-      dn = cfma<CC>(tb[s + t], v[t], dn);
+      if (t + 1 < M) nxt = v[t + 1];
+      const V dn = fwd_point<CC, R, V>(cf, prev, nxt, d, v[t]);
       prev = v[t];
       v[t] = dn;
       d = dn;
     }
+    sh_B[p * LW + li] = d;
   }
-  sh_B[p * LW + li] = d;
   __syncthreads();
-  // incoming d_{s-1}: compose the earlier segments' maps D -> pi_end D + B
-  V D = vzero<V>();
-  for (int q = 0; q < p && q < nseg; ++q) D = cfma<CC>(tpi[min((q + 1) * m, n) - 1], D, sh_B[q * LW + li]);
+  // incoming d_{s-1}: compose the earlier segments' maps D -> P D + B_q, then add
+  // a^(t+1) D_in as a running product
+  {
+    V D = vzero<V>();
+    for (int q = 0; q < p && q < nseg; ++q) D = cfma<CC>(cP, D, sh_B[q * LW + li]);
+    V r = D;
 #pragma unroll
-  for (int t = 0; t < M; ++t)
-    if (t < len) v[t] = cfma<CC>(tpi[s + t], D, v[t]);
-
-  // backward recurrence over the segment from u_e = 0
-  V u = vzero<V>();
-#pragma unroll
-  for (int t = M - 1; t >= 0; --t) {
-    if (t < len) {
-      u = cfma<CC>(ta[s + t], u, v[t]);
-      v[t] = u;
+    for (int t = 0; t < M; ++t) {
+      r = cmul<CC>(ca, r);
+      v[t] = vadd(v[t], r);
     }
   }
-  sh_U[p * LW + li] = u;
-  __syncthreads();
-  V U = vzero<V>();
-  for (int q = nseg - 1; q > p; --q) U = cfma<CC>(trho[q * m], U, sh_U[q * LW + li]);
+  // backward recurrence over the segment from u_e = 0 (u = 0 past the end of the line)
+  {
+    V u = vzero<V>();
 #pragma unroll
-  for (int t = 0; t < M; ++t)
-    if (t < len) v[t] = cfma<CC>(trho[s + t], U, v[t]);
+    for (int t = M - 1; t >= 0; --t) {
+      u = cfma<CC>(ca, u, v[t]);
+      if (t >= len) u = vzero<V>();
+      v[t] = u;
+    }
+    sh_U[p * LW + li] = u;  // every halo read of sh_first precedes the barrier above
+  }
+  __syncthreads();
+  {
+    V U = vzero<V>();
+    for (int q = nseg - 1; q > p; --q) U = cfma<CC>(cP, U, sh_U[q * LW + li]);
+    V r = U;
+#pragma unroll
+    for (int t = M - 1; t >= 0; --t) {
+      r = cmul<CC>(ca, r);
+      v[t] = vadd(v[t], r);
+    }
+  }
+  // Sherman-Morrison head correction of segment 0
+  if (w == 0 && nwi > 0) {
+    const bool mine = (SW == 1) || (lane < LW);
+    const V u0 = v[0];
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      if (t < nwi) {
+        const V c = cfma<CC>(omega[t], u0, v[t]);
+        if (mine) v[t] = c;
+      }
+    }
+  }
 
 #pragma unroll
   for (int t = 0; t < M; ++t)
-    if (t < len && active) bstore(v[t], rs, voff, (uint32_t)t * srow);
+    if (t < len) bstore(v[t], rs, voff, (uint32_t)t * srow);
+}
+
+// Sherman-Morrison head correction u_i += omega_i u_0, i < nw, one thread per line, for
+// x/y lines when the correction reaches past the first segment (large c).  Lines as in
+// k_sweep_lines.
+template <typename R, bool CC>
+__global__ void __launch_bounds__(256)
+k_head_correction(typename VecOf<R>::T* __restrict__ psi, const typename VecOf<R>::T* __restrict__ omega, int nw,
+                  int n, int64_t nlines, int64_t inner) {
+  typedef typename VecOf<R>::T V;
+  for (int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x; line < nlines; line += (int64_t)gridDim.x * 256) {
+    const int64_t base = (line / inner) * (inner * n) + (line % inner);
+    const V u0 = psi[base];
+    for (int i = nw - 1; i >= 0; --i) psi[base + i * inner] = cfma<CC>(omega[i], u0, psi[base + i * inner]);
+  }
 }
 
 // ---------------------------------------------------------------------------------------
 // z sweep.  Block = 4 wavefronts; a wavefront holds L = 64/nseg z lines, lane =
-// line-in-wave * nseg + segment.  Each iteration copies 4L consecutive lines (contiguous
-// in memory) into LDS, solves them, and copies them back.
+// line-in-wave * nseg + segment, MZ points per thread.  Each iteration copies 4L
+// consecutive lines (contiguous in memory) into LDS, solves them, and copies them back.
+// The omega correction runs here (any nw), u'_0 broadcast along the line by a shuffle.
 // ---------------------------------------------------------------------------------------
 template <typename R, int MZ, bool CC, bool NORM, int EPI>
 __global__ void __launch_bounds__(256)
-k_sweep_z(typename VecOf<R>::T* __restrict__ psi, const typename VecOf<R>::T* __restrict__ tab, int nz,
-          int m, int nseg, int64_t nlines, double* __restrict__ partials, const R* __restrict__ vx,
-          const R* __restrict__ vy, const R* __restrict__ vz, int ny, R tau,
-          const DevState* __restrict__ st) {
+k_sweep_z(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typename VecOf<R>::T cb,
+          typename VecOf<R>::T cbl, typename VecOf<R>::T cP, const typename VecOf<R>::T* __restrict__ omega, int nwi,
+          int nz, int nseg, int64_t nlines, double* __restrict__ partials, const R* __restrict__ vx,
+          const R* __restrict__ vy, const R* __restrict__ vz, int ny, R tau, const DevState* __restrict__ st) {
   typedef typename VecOf<R>::T V;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   V* sdata = reinterpret_cast<V*>(smem_raw);
@@ -240,13 +302,12 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, const typename VecOf<R>::T* __
   const int l = lane / nseg, p = lane % nseg;
   const int lines_per_grp = 4 * L;
   const int64_t ngrp = (nlines + lines_per_grp - 1) / lines_per_grp;
-  const int s = p * m;
-  const int len = max(0, min(m, nz - s));
-  const V* ta = tab;
-  const V* tb = tab + nz;
-  const V* tpi = tab + 2 * nz;
-  const V* trho = tab + 3 * nz;
-  const V* tbl = tab + 4 * nz;
+  const int s = p * MZ;
+  const int len = max(0, min(MZ, nz - s));
+  Coef<V> cf;
+  cf.a = ca;
+  cf.b = cb;
+  cf.bl = cbl;
   R g = 0;
   if (EPI != 0) g = (R)st->g;
   double acc = 0.0;
@@ -264,27 +325,28 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, const typename VecOf<R>::T* __
     V* row = sdata + (act ? ll * nz : 0);
     V v[MZ];
 #pragma unroll
-    for (int t = 0; t < MZ; ++t) v[t] = (act && t < len) ? row[s + t] : vzero<V>();
+    for (int t = 0; t < MZ; ++t) {
+      v[t] = vzero<V>();
+      if (act && t < len) v[t] = row[s + t];
+    }
     const V left = (act && s > 0) ? row[s - 1] : vzero<V>();
     const V right = (act && s + len < nz) ? row[s + len] : vzero<V>();
 
-    V prev = left, d = vzero<V>();
+    V d = vzero<V>();
+    {
+      V prev = left;
 #pragma unroll
-    for (int t = 0; t < MZ; ++t) {
-      if (t < len) {
+      for (int t = 0; t < MZ; ++t) {
         V nxt = right;
-        if (t + 1 < MZ && t + 1 < len) nxt = v[t + 1];
-        const V sum = vadd(vadd(prev, nxt), d);
-        V dn = cmul<CC>(ta[s + t], sum);
-        if (sizeof(R) == 4) dn = cfma<CC>(tbl[s + t], v[t], dn);  // low part of b
-        dn = cfma<CC>(tb[s + t], v[t], dn);
+        if (t + 1 < MZ) nxt = v[t + 1];
+        const V dn = fwd_point<CC, R, V>(cf, prev, nxt, d, v[t]);
         prev = v[t];
         v[t] = dn;
         d = dn;
       }
     }
     // inclusive scan of the segment maps x -> A x + B along the line
-    V A = act ? tpi[s + len - 1] : vone<V>();
+    V A = act ? cP : vone<V>();
     V B = act ? d : vzero<V>();
     for (int off = 1; off < nseg; off <<= 1) {
       const V Ap = shfl_up_v(A, off, nseg);
@@ -296,19 +358,22 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, const typename VecOf<R>::T* __
     }
     V D = shfl_up_v(B, 1, nseg);
     if (p == 0) D = vzero<V>();
+    {
+      V r = D;
 #pragma unroll
-    for (int t = 0; t < MZ; ++t)
-      if (t < len) v[t] = cfma<CC>(tpi[s + t], D, v[t]);
-
+      for (int t = 0; t < MZ; ++t) {
+        r = cmul<CC>(ca, r);
+        v[t] = vadd(v[t], r);
+      }
+    }
     V u = vzero<V>();
 #pragma unroll
     for (int t = MZ - 1; t >= 0; --t) {
-      if (t < len) {
-        u = cfma<CC>(ta[s + t], u, v[t]);
-        v[t] = u;
-      }
+      u = cfma<CC>(ca, u, v[t]);
+      if (t >= len) u = vzero<V>();
+      v[t] = u;
     }
-    V Ab = act ? trho[s] : vone<V>();
+    V Ab = act ? cP : vone<V>();
     V Bu = act ? u : vzero<V>();
     for (int off = 1; off < nseg; off <<= 1) {
       const V Ap = shfl_down_v(Ab, off, nseg);
@@ -320,9 +385,27 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, const typename VecOf<R>::T* __
     }
     V U = shfl_down_v(Bu, 1, nseg);
     if (p == nseg - 1) U = vzero<V>();
+    {
+      V r = U;
 #pragma unroll
-    for (int t = 0; t < MZ; ++t)
-      if (t < len) v[t] = cfma<CC>(trho[s + t], U, v[t]);
+      for (int t = MZ - 1; t >= 0; --t) {
+        r = cmul<CC>(ca, r);
+        v[t] = vadd(v[t], r);
+      }
+    }
+    // Sherman-Morrison head correction: u_i += omega_i u_0 for i < nwi
+    if (nwi > 0) {
+      const V u0 = vmake<V>(__shfl(v[0].x, l * nseg, 64), __shfl(v[0].y, l * nseg, 64));
+#pragma unroll
+      for (int t = 0; t < MZ; ++t) {
+        if (t < nwi) {  // uniform: segment-0 lanes need it whenever t < nwi
+          const int pos = s + t;
+          const V om = omega[min(pos, nwi - 1)];
+          const V c = cfma<CC>(om, u0, v[t]);
+          if (pos < nwi) v[t] = c;
+        }
+      }
+    }
 
     if (act) {
       R vxy = 0;
@@ -455,16 +538,30 @@ __global__ void __launch_bounds__(256) k_obs_final(const double* __restrict__ pa
 // ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
+template <typename R> static typename VecOf<R>::T cval(const double* c) {
+  typename VecOf<R>::T v;
+  v.x = (R)c[0];
+  v.y = (R)c[1];
+  return v;
+}
+
 template <typename R, int M, int SW, bool CC, int NSTEP>
 static hipError_t go_lines(const SweepLaunch& a, hipStream_t s) {
   typedef typename VecOf<R>::T V;
   constexpr int LW = 64 / SW;
   const int waves = (a.nseg + SW - 1) / SW;
-  const size_t lds = (size_t)4 * waves * SW * LW * sizeof(V);
+  const size_t lds = (size_t)3 * waves * SW * LW * sizeof(V);
   const int64_t blocks = (a.nlines + LW - 1) / LW;
+  const int nwi = (a.nw <= M) ? a.nw : 0;
   hipLaunchKernelGGL((k_sweep_lines<R, M, SW, CC, NSTEP>), dim3((unsigned)blocks), dim3(waves * 64), lds, s,
-                     (V*)a.psi, a.psi_bytes, (const V*)a.tab, a.n, a.m, a.nseg, a.nlines, a.inner, (const R*)a.vx,
+                     (V*)a.psi, a.psi_bytes, cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4),
+                     cval<R>(a.coef + 6), (const V*)a.omega, nwi, a.n, a.nseg, a.nlines, a.inner, (const R*)a.vx,
                      (const R*)a.vy, (const R*)a.vz, a.nz, (R)a.tau, a.st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nwi > 0 || a.nw == 0) return e;
+  const int64_t want = (a.nlines + 255) / 256;
+  hipLaunchKernelGGL((k_head_correction<R, CC>), dim3((unsigned)(want < 2048 ? want : 2048)), dim3(256), 0, s,
+                     (V*)a.psi, (const V*)a.omega, a.nw, a.n, a.nlines, a.inner);
   return hipGetLastError();
 }
 
@@ -474,25 +571,33 @@ static hipError_t go_lines_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
   return a.nstep ? go_lines<R, M, SW, true, 2>(a, s) : go_lines<R, M, SW, true, 0>(a, s);
 }
 
+// Instances: complex64 M in {8, 16, 32}, complex128 M in {8, 16} (32 complex doubles per
+// thread would not fit the 128-VGPR budget of 1024-thread blocks); SW in {1, 2, 4}.
 bool sweep_lines_supported(int precision, int m, int sw) {
-  if (precision == 0) return (sw == 1 && (m == 8 || m == 16 || m == 32)) || (sw == 2 && m == 32);
-  return (sw == 1 && (m == 8 || m == 16)) || ((sw == 2 || sw == 4) && m == 16);
+  if (sw != 1 && sw != 2 && sw != 4) return false;
+  if (precision == 0) return m == 8 || m == 16 || m == 32;
+  return m == 8 || m == 16;
 }
 
-hipError_t launch_sweep_lines(int precision, bool cc, int maxm, const SweepLaunch& a, hipStream_t s) {
+#define GP_LINES_SW(R, M)                                                    \
+  do {                                                                       \
+    if (a.sw == 1) return go_lines_mode<R, M, 1>(cc, a, s);                 \
+    if (a.sw == 2) return go_lines_mode<R, M, 2>(cc, a, s);                 \
+    if (a.sw == 4) return go_lines_mode<R, M, 4>(cc, a, s);                 \
+  } while (0)
+
+hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipStream_t s) {
   if (precision == 0) {
-    if (a.sw == 1 && maxm == 8) return go_lines_mode<float, 8, 1>(cc, a, s);
-    if (a.sw == 1 && maxm == 16) return go_lines_mode<float, 16, 1>(cc, a, s);
-    if (a.sw == 1 && maxm == 32) return go_lines_mode<float, 32, 1>(cc, a, s);
-    if (a.sw == 2 && maxm == 32) return go_lines_mode<float, 32, 2>(cc, a, s);
+    if (a.m == 8) GP_LINES_SW(float, 8);
+    if (a.m == 16) GP_LINES_SW(float, 16);
+    if (a.m == 32) GP_LINES_SW(float, 32);
   } else {
-    if (a.sw == 1 && maxm == 8) return go_lines_mode<double, 8, 1>(cc, a, s);
-    if (a.sw == 1 && maxm == 16) return go_lines_mode<double, 16, 1>(cc, a, s);
-    if (a.sw == 2 && maxm == 16) return go_lines_mode<double, 16, 2>(cc, a, s);
-    if (a.sw == 4 && maxm == 16) return go_lines_mode<double, 16, 4>(cc, a, s);
+    if (a.m == 8) GP_LINES_SW(double, 8);
+    if (a.m == 16) GP_LINES_SW(double, 16);
   }
   return hipErrorInvalidValue;
 }
+#undef GP_LINES_SW
 
 template <typename R, int MZ, bool CC, bool NORM, int EPI>
 static hipError_t go_z(const SweepLaunch& a, hipStream_t s) {
@@ -500,7 +605,8 @@ static hipError_t go_z(const SweepLaunch& a, hipStream_t s) {
   const int L = 64 / a.nseg;
   const size_t lds = (size_t)4 * L * a.nz * sizeof(V);
   hipLaunchKernelGGL((k_sweep_z<R, MZ, CC, NORM, EPI>), dim3(a.grid), dim3(256), lds, s, (V*)a.psi,
-                     (const V*)a.tab, a.nz, a.m, a.nseg, a.nlines, a.partials, (const R*)a.vx, (const R*)a.vy,
+                     cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4), cval<R>(a.coef + 6),
+                     (const V*)a.omega, a.nw, a.nz, a.nseg, a.nlines, a.partials, (const R*)a.vx, (const R*)a.vy,
                      (const R*)a.vz, a.ny, (R)a.tau, a.st);
   return hipGetLastError();
 }
@@ -513,23 +619,31 @@ static hipError_t go_z_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
   return a.nstep ? go_z<R, MZ, true, false, 2>(a, s) : go_z<R, MZ, true, false, 0>(a, s);
 }
 
+// z instances: points per thread MZ in {2, 4, 6, 7, 8, 12, 16}
 bool sweep_z_supported(int precision, int mz) {
   (void)precision;
-  return mz == 4 || mz == 8 || mz == 16;
+  return mz == 2 || mz == 4 || mz == 6 || mz == 7 || mz == 8 || mz == 12 || mz == 16;
 }
 
-hipError_t launch_sweep_z(int precision, bool cc, int mz, const SweepLaunch& a, hipStream_t s) {
-  if (precision == 0) {
-    if (mz == 4) return go_z_mode<float, 4>(cc, a, s);
-    if (mz == 8) return go_z_mode<float, 8>(cc, a, s);
-    if (mz == 16) return go_z_mode<float, 16>(cc, a, s);
-  } else {
-    if (mz == 4) return go_z_mode<double, 4>(cc, a, s);
-    if (mz == 8) return go_z_mode<double, 8>(cc, a, s);
-    if (mz == 16) return go_z_mode<double, 16>(cc, a, s);
-  }
-  return hipErrorInvalidValue;
+#define GP_Z_M(R)                                              \
+  do {                                                         \
+    switch (a.m) {                                             \
+      case 2: return go_z_mode<R, 2>(cc, a, s);                \
+      case 4: return go_z_mode<R, 4>(cc, a, s);                \
+      case 6: return go_z_mode<R, 6>(cc, a, s);                \
+      case 7: return go_z_mode<R, 7>(cc, a, s);                \
+      case 8: return go_z_mode<R, 8>(cc, a, s);                \
+      case 12: return go_z_mode<R, 12>(cc, a, s);              \
+      case 16: return go_z_mode<R, 16>(cc, a, s);              \
+      default: return hipErrorInvalidValue;                    \
+    }                                                          \
+  } while (0)
+
+hipError_t launch_sweep_z(int precision, bool cc, const SweepLaunch& a, hipStream_t s) {
+  if (precision == 0) GP_Z_M(float);
+  GP_Z_M(double);
 }
+#undef GP_Z_M
 
 hipError_t launch_finalize_norm(const double* partials, int nb, double dV, double dt, DevState* st,
                                 hipStream_t s) {

@@ -137,16 +137,33 @@ def test_ragged_shapes_match_oracle(shape, prec, imag, split):
 
 
 @pytest.mark.parametrize("prec", [gp.GP_C128, gp.GP_C64])
-@pytest.mark.parametrize("mapping", [(8, 8, 4, 0), (16, 16, 8, 0), (32, 8, 16, 0), (0, 0, 32, 0),
-                                     (0, 0, 64, 0), (16, 32, 0, 0)])
+@pytest.mark.parametrize("imag", [True, False])
+def test_large_dt_long_head_correction(prec, imag):
+    """dt/dx^2 ~ 5-40: c'_inf close to 1, so the constant-pivot solve needs Sherman-Morrison
+    corrections longer than one thread's segment (separate x/y correction pass)."""
+    nx, ny, nz = 70, 45, 33
+    prm = dict(nx=nx, ny=ny, nz=nz, dx=0.1, dy=0.15, dz=0.05, nux=1.0, nuy=1.2, nuz=0.8, g=5.0, dt=0.1)
+    psi0 = inputs.perturbed_psi(nx, ny, nz, 0.1, 0.15, 0.05, 1.0, 1.2, 0.8, seed=12, amp=0.2)
+    say(f"case: large dt prec {prec} imag {imag}")
+    out, _ = run_gpu(prm, psi0, prec, imag, 2)
+    ref = run_ref(prm, psi0, imag, 2).psi
+    err = rel_err(out, ref)
+    say(f"  rel err {err:.2e}")
+    assert err <= (1e-12 if prec == gp.GP_C128 else 5e-6)
+
+
+MAPPINGS = [(8, 1, 8, 1, 4, 0), (16, 1, 16, 2, 8, 0), (32, 2, 8, 4, 16, 0), (0, 4, 0, 1, 32, 0),
+            (16, 4, 32, 1, 64, 0), (8, 2, 16, 4, 0, 0)]
+
+
+@pytest.mark.parametrize("prec", [gp.GP_C128, gp.GP_C64])
+@pytest.mark.parametrize("mapping", MAPPINGS)
 def test_every_line_mapping_agrees(prec, mapping):
     nx, ny, nz = 96, 70, 45
     prm = dict(nx=nx, ny=ny, nz=nz, dx=0.2, dy=0.2, dz=0.2, nux=1.0, nuy=1.4142, nuz=1.7321, g=50.0, dt=0.004)
     psi0 = inputs.perturbed_psi(nx, ny, nz, 0.2, 0.2, 0.2, 1.0, 1.4, 1.7, seed=4, amp=0.1)
-    if prec == gp.GP_C128 and mapping[0] == 32:
-        mapping = (16,) + mapping[1:]
-    if prec == gp.GP_C128 and mapping[1] == 32:
-        mapping = mapping[:1] + (16,) + mapping[2:]
+    if prec == gp.GP_C128:   # complex128 runs at most 16 points per thread
+        mapping = tuple(16 if (i in (0, 2) and v == 32) else v for i, v in enumerate(mapping))
     say(f"case: mapping {mapping} prec {prec}")
     for imag in (True, False):
         out, s = run_gpu(prm, psi0, prec, imag, 2, mapping=mapping)
@@ -161,7 +178,8 @@ def test_invalid_mapping_rejected():
     psi = dev_psi(inputs.gaussian_psi(48, 40, 32, 0.2, 0.2, 0.2, 1, 1, 1), gp.GP_C128)
     with gp.Solver.from_workload(psi, prm) as s:
         before = s.get_mapping()
-        for bad in [(1, 0, 0, 0), (0, 0, 3, 0), (0, 0, 4, 3), (64, 0, 0, 0), (0, 0, 128, 0)]:
+        for bad in [(1, 1, 0, 0, 0, 0), (0, 3, 0, 0, 0, 0), (0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 4, 3),
+                    (64, 0, 0, 0, 0, 0), (0, 0, 0, 0, 128, 0), (0, 0, 32, 8, 0, 0)]:
             with pytest.raises(gp.GPError):
                 s.set_mapping(*bad)
         assert s.get_mapping() == before
