@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--also-c128", action="store_true", default=True)
     ap.add_argument("--no-also-c128", dest="also_c128", action="store_false")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default line mapping")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain device copy of known size (HBM counter calibration)")
@@ -69,6 +70,8 @@ def run_precision(torch, gp, inputs, w, prec, args):
     log(f"[bench] prepared state: mu={mu:.6f} E={e:.6f}")
     s = gp.Solver.from_workload(psi, w)
     s.set_g(w["g_quench"])
+    if not args.no_autotune:
+        log(f"[bench] autotune: {s.autotune('real', steps=4)}")
     n0 = s.norm()
     s.step_real(args.warmup)
     torch.cuda.synchronize()
@@ -123,8 +126,8 @@ def cpu_baseline(inputs, w, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        log("bench.py runs on one GPU only: the multi-GPU decomposition is not built "
-            "(see DESIGN.md, 'Sharding'); use --gpus 1")
+        log("bench.py runs on one GPU only: this library has no multi-GPU decomposition "
+            "(each GPU would hold an x-slab); use --gpus 1")
         sys.exit(2)
     import torch
 

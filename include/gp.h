@@ -121,6 +121,15 @@ int gp_get_timing(gp_ctx* c, double ms_mean[5], int64_t launches[5]);
 int gp_get_mapping(gp_ctx* c, int32_t map[6]);
 int gp_set_mapping(gp_ctx* c, const int32_t map[6]);
 
+/* Project autotuner: times every line mapping the kernels cover on this context's grid
+ * (each axis independently, `steps` steps of kind mode = 0 imaginary / 1 real, HIP-event
+ * kernel durations), keeps the fastest and returns it in map_out (nullable).  psi, the
+ * device state and the step count are restored afterwards (one temporary device copy of
+ * psi).  cache_path (nullable): a text file of earlier results keyed by grid, precision
+ * and step kind; a hit applies the stored mapping without timing, a miss appends the new
+ * result.  Synchronises. */
+int gp_autotune(gp_ctx* c, int32_t mode, int32_t steps, const char* cache_path, int32_t map_out[6]);
+
 const char* gp_strerror(int code);
 const char* gp_last_error(gp_ctx* c);
 

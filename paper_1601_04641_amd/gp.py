@@ -24,8 +24,8 @@ GP_FLAG_NONFINITE, GP_FLAG_ZERO_NORM = 1, 2
 # names declared in include/gp.h (checked against the built library by the tests)
 EXPORTS = ("gp_init", "gp_destroy", "gp_step_imag", "gp_step_real", "gp_norm", "gp_energy_mu",
            "gp_rms", "gp_raw_sums", "gp_set_g", "gp_set_psi", "gp_status", "gp_converge_imag",
-           "gp_set_timing", "gp_get_timing", "gp_get_mapping", "gp_set_mapping", "gp_strerror",
-           "gp_last_error")
+           "gp_set_timing", "gp_get_timing", "gp_get_mapping", "gp_set_mapping", "gp_autotune",
+           "gp_strerror", "gp_last_error")
 
 
 class GPError(RuntimeError):
@@ -75,6 +75,7 @@ def load(path: str = LIB_PATH):
         "gp_get_timing": [vp, P(d), P(i64)],
         "gp_get_mapping": [vp, P(i32)],
         "gp_set_mapping": [vp, P(i32)],
+        "gp_autotune": [vp, i32, i32, ctypes.c_char_p, P(i32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -199,13 +200,21 @@ class Solver:
         return ms, n
 
     def get_mapping(self):
-        out = (ctypes.c_int32 * 4)()
+        """[m_x, sw_x, m_y, sw_y, segments_z, m_z]"""
+        out = (ctypes.c_int32 * 6)()
         self._chk(self._L.gp_get_mapping(self._h, out), "gp_get_mapping")
         return list(out)
 
-    def set_mapping(self, mx=0, my=0, segz=0, mz=0):
-        arr = (ctypes.c_int32 * 4)(int(mx), int(my), int(segz), int(mz))
+    def set_mapping(self, mx=0, swx=0, my=0, swy=0, segz=0, mz=0):
+        arr = (ctypes.c_int32 * 6)(int(mx), int(swx), int(my), int(swy), int(segz), int(mz))
         self._chk(self._L.gp_set_mapping(self._h, arr), "gp_set_mapping")
+
+    def autotune(self, mode="real", steps=5, cache_path=None):
+        """Time every line mapping on this grid and keep the fastest (see gp_autotune)."""
+        out = (ctypes.c_int32 * 6)()
+        cp = cache_path.encode() if cache_path else None
+        self._chk(self._L.gp_autotune(self._h, 0 if mode == "imag" else 1, int(steps), cp, out), "gp_autotune")
+        return list(out)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -358,3 +358,26 @@ def test_converge_imag_reaches_tolerance():
     o = run_ref(w, psi0, True, steps)
     assert conv
     assert abs(mu - o.energy_mu()[1]) <= 1e-10 * abs(mu)
+
+
+@pytest.mark.parametrize("prec", [gp.GP_C64, gp.GP_C128])
+def test_autotune_restores_state_caches_and_stays_exact(prec, tmp_path):
+    nx, ny, nz = 96, 80, 72
+    prm = dict(nx=nx, ny=ny, nz=nz, dx=0.2, dy=0.2, dz=0.2, nux=1.0, nuy=1.4142, nuz=1.7321, g=40.0, dt=0.004)
+    psi0 = inputs.perturbed_psi(nx, ny, nz, 0.2, 0.2, 0.2, 1.0, 1.4, 1.7, seed=8, amp=0.1)
+    psi = dev_psi(psi0, prec)
+    before = psi.cpu().numpy()
+    cache = str(tmp_path / "tune.txt")
+    with gp.Solver.from_workload(psi, prm) as s:
+        m1 = s.autotune("real", steps=2, cache_path=cache)
+        assert np.array_equal(psi.cpu().numpy(), before)
+        assert s.status()[0] == 0
+        m2 = s.autotune("real", steps=2, cache_path=cache)
+        assert m1 == m2 == s.get_mapping()
+        s.step_real(2)
+        torch.cuda.synchronize()
+        out = psi.cpu().numpy().astype(np.complex128)
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and lines[0].startswith(f"gfx950 {nx} {ny} {nz} {prec} 1 :")
+    ref = run_ref(prm, psi0.astype(np.complex64).astype(np.complex128) if prec == gp.GP_C64 else psi0, False, 2).psi
+    assert rel_err(out, ref) <= (1e-13 if prec == gp.GP_C128 else 2e-6)
