@@ -130,6 +130,44 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]);
  * result.  Synchronises. */
 int gp_autotune(gp_ctx* c, int32_t mode, int32_t steps, const char* cache_path, int32_t map_out[6]);
 
+/* ---------------------------------------------------------------------------------------
+ * Batched form: n independent grids (different sizes, traps, g and dt allowed; one
+ * precision and one splitting) advanced by the same launches, four per step whatever n
+ * is.  psi_dev is ONE caller-owned device buffer; instance i occupies
+ * nx_i*ny_i*nz_i complex values from element offsets[i] on (same layout as a single
+ * grid); regions must not overlap.  Each instance's psi must stay below 4 GiB.
+ * `active` (nullable, n bytes): instances with 0 are left untouched by the step calls
+ * (and stay masked until a later call passes them as 1).  Step calls do not
+ * synchronise; the observables, status and convergence calls do.
+ * ------------------------------------------------------------------------------------- */
+typedef struct gp_batch gp_batch;
+
+int gp_batch_init(const gp_params* p, int32_t n, void* psi_dev, const int64_t* offsets,
+                  void* hip_stream, gp_batch** out);
+int gp_batch_destroy(gp_batch* b);
+int gp_batch_step_imag(gp_batch* b, int32_t nsteps, const uint8_t* active);
+int gp_batch_step_real(gp_batch* b, int32_t nsteps, const uint8_t* active);
+/* per instance, arrays of length n (rms4 and raw: 4n and 9n, instance-major) */
+int gp_batch_norm(gp_batch* b, double* norm);
+int gp_batch_energy_mu(gp_batch* b, double* energy, double* mu);
+int gp_batch_rms(gp_batch* b, double* rms4);
+int gp_batch_raw_sums(gp_batch* b, double* raw);
+int gp_batch_status(gp_batch* b, int64_t* steps_done, double* mu_est, int32_t* flags);
+/* Imaginary time until every instance meets |mu_n - mu_{n-K}| <= tol |mu_n| (checked
+ * every K steps, K <= 0 selects ceil(0.25/min dt)); converged instances are masked off
+ * while the rest continue.  Per-instance steps taken, final mu and converged flag. */
+int gp_batch_converge_imag(gp_batch* b, double tol, int32_t check_every, int64_t max_steps,
+                           int64_t* steps_taken, double* mu, int32_t* converged);
+/* Mapping shared by all instances: {m_x, sw_x, m_y, sw_y, m_z}; the z threads per line
+ * follow per instance.  gp_batch_autotune times the candidates on the batch (psi and
+ * state restored) and keeps the fastest. */
+int gp_batch_get_mapping(gp_batch* b, int32_t map[5]);
+int gp_batch_set_mapping(gp_batch* b, const int32_t map[5]);
+int gp_batch_autotune(gp_batch* b, int32_t mode, int32_t steps, int32_t map_out[5]);
+int gp_batch_set_timing(gp_batch* b, int32_t enable);
+int gp_batch_get_timing(gp_batch* b, double ms_mean[5], int64_t launches[5]);
+const char* gp_batch_last_error(gp_batch* b);
+
 const char* gp_strerror(int code);
 const char* gp_last_error(gp_ctx* c);
 

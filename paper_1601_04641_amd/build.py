@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgpsscn.so")
-SOURCES = ["gp_kernels.hip", "gp_api.cpp"]
+SOURCES = ["gp_kernels.hip", "gp_batch.hip", "gp_api.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

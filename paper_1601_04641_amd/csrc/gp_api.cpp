@@ -21,6 +21,66 @@
 using gpk::DevState;
 typedef std::complex<double> cd;
 
+namespace gpk {
+
+// Constant-pivot Crank-Nicolson solve along one axis (see gp_kernels.hip): c'_inf is the
+// root of modulus < 1 of c x^2 + (1+2c) x + c = 0 (taken in the cancellation-free form
+// -2c / ((1+2c) +- sqrt((1+2c)^2 - 4c^2))), gamma = 1/(1 + 2c + c c'_inf), a = c gamma,
+// b = (1-2c) gamma, kappa = c c'_inf.  omega = kappa w / (1 - kappa w_0) with
+// w = A'^{-1} e_0 (forward d_i = gamma a^i, backward w_i = d_i + a w_{i+1}); nw counts
+// the leading omega_i above 1/100 of the storage precision's unit roundoff.
+void cn_axis_constants(int n, double d, double dt, int mode, int m, bool f32, AxisConst* out) {
+  const double k = dt / (4.0 * d * d);
+  const cd cc = mode == 0 ? cd(k, 0) : cd(0, k);
+  const cd s1 = 1.0 + 2.0 * cc;
+  const cd disc = std::sqrt(s1 * s1 - 4.0 * cc * cc);
+  const cd q = std::abs(s1 + disc) >= std::abs(s1 - disc) ? s1 + disc : s1 - disc;
+  const cd cpinf = -2.0 * cc / q;
+  const cd gam = 1.0 / (1.0 + 2.0 * cc + cc * cpinf);
+  const cd a = cc * gam, b = (1.0 - 2.0 * cc) * gam, kappa = cc * cpinf;
+  cd P(1, 0);
+  for (int i = 0; i < m; ++i) P *= a;
+  std::vector<cd> w(n);
+  cd dd = gam;
+  for (int i = 0; i < n; ++i) {
+    w[i] = dd;
+    dd *= a;
+  }
+  for (int i = n - 2; i >= 0; --i) w[i] += a * w[i + 1];
+  const cd beta = kappa / (1.0 - kappa * w[0]);
+  const double thr = 0.01 * (f32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53));
+  int nw = 0;
+  for (int i = 0; i < n; ++i)
+    if (std::abs(beta * w[i]) > thr) nw = i + 1;
+  auto rnd = [&](cd v) { return f32 ? cd((float)v.real(), (float)v.imag()) : v; };
+  const cd rb = rnd(b);
+  const cd vals[4] = {rnd(a), rb, f32 ? rnd(b - rb) : cd(0, 0), rnd(P)};
+  for (int q2 = 0; q2 < 4; ++q2) {
+    out->coef[2 * q2] = vals[q2].real();
+    out->coef[2 * q2 + 1] = vals[q2].imag();
+  }
+  out->nw = nw;
+  out->omega.resize(nw);
+  for (int i = 0; i < nw; ++i) out->omega[i] = beta * w[i];
+}
+
+void pack_complex(const std::vector<std::complex<double>>& v, bool f32, std::vector<unsigned char>& out) {
+  if (f32) {
+    out.resize(v.size() * 2 * sizeof(float));
+    float* f = reinterpret_cast<float*>(out.data());
+    for (size_t i = 0; i < v.size(); ++i) {
+      f[2 * i] = (float)v[i].real();
+      f[2 * i + 1] = (float)v[i].imag();
+    }
+  } else {
+    out.resize(v.size() * sizeof(cd));
+    std::memcpy(out.data(), v.data(), out.size());
+  }
+}
+
+}  // namespace gpk
+
+
 namespace {
 
 constexpr int kGraphSteps = 16;   // steps per captured graph
@@ -165,61 +225,19 @@ bool pick_z(int nz, size_t esize, int* seg_out, int* m_out) {
   return true;
 }
 
-// Constant-pivot Crank-Nicolson solve along one axis (see gp_kernels.hip): c'_inf is the
-// root of modulus < 1 of c x^2 + (1+2c) x + c = 0 (taken in the cancellation-free form
-// -2c / ((1+2c) +- sqrt((1+2c)^2 - 4c^2))), gamma = 1/(1 + 2c + c c'_inf), a = c gamma,
-// b = (1-2c) gamma, kappa = c c'_inf.  omega = kappa w / (1 - kappa w_0) with
-// w = A'^{-1} e_0 (forward d_i = gamma a^i, backward w_i = d_i + a w_{i+1}); nw counts
-// the leading omega_i above 1/100 of the storage precision's unit roundoff.
 int build_axis_table(gp_ctx* c, int mode, int axis) {
   const int n = axis == 0 ? c->p.nx : axis == 1 ? c->p.ny : c->p.nz;
   const double d = axis == 0 ? c->p.dx : axis == 1 ? c->p.dy : c->p.dz;
   const int m = axis == 0 ? c->map.mx : axis == 1 ? c->map.my : c->map.mz;
-  const double k = c->p.dt / (4.0 * d * d);
-  const cd cc = mode == 0 ? cd(k, 0) : cd(0, k);
-  const cd s1 = 1.0 + 2.0 * cc;
-  const cd disc = std::sqrt(s1 * s1 - 4.0 * cc * cc);
-  const cd q = std::abs(s1 + disc) >= std::abs(s1 - disc) ? s1 + disc : s1 - disc;
-  const cd cpinf = -2.0 * cc / q;
-  const cd gam = 1.0 / (1.0 + 2.0 * cc + cc * cpinf);
-  const cd a = cc * gam, b = (1.0 - 2.0 * cc) * gam, kappa = cc * cpinf;
-  cd P(1, 0);
-  for (int i = 0; i < m; ++i) P *= a;
-  std::vector<cd> w(n);
-  cd dd = gam;
-  for (int i = 0; i < n; ++i) {
-    w[i] = dd;
-    dd *= a;
-  }
-  for (int i = n - 2; i >= 0; --i) w[i] += a * w[i + 1];
-  const cd beta = kappa / (1.0 - kappa * w[0]);
   const bool f32 = c->p.precision == GP_C64;
-  const double thr = 0.01 * (f32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53));
-  int nw = 0;
-  for (int i = 0; i < n; ++i)
-    if (std::abs(beta * w[i]) > thr) nw = i + 1;
-  auto rnd = [&](cd v) { return f32 ? cd((float)v.real(), (float)v.imag()) : v; };
-  const cd rb = rnd(b);
-  const cd vals[4] = {rnd(a), rb, f32 ? rnd(b - rb) : cd(0, 0), rnd(P)};
-  for (int q2 = 0; q2 < 4; ++q2) {
-    c->coef[mode][axis][2 * q2] = vals[q2].real();
-    c->coef[mode][axis][2 * q2 + 1] = vals[q2].imag();
-  }
-  c->nw[mode][axis] = nw;
-  if (nw == 0) return GP_OK;
-  if (f32) {
-    std::vector<float> f(2 * (size_t)nw);
-    for (int i = 0; i < nw; ++i) {
-      const cd o = beta * w[i];
-      f[2 * i] = (float)o.real();
-      f[2 * i + 1] = (float)o.imag();
-    }
-    HIPCHK(c, hipMemcpy(c->tab[mode][axis], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
-  } else {
-    std::vector<cd> o(nw);
-    for (int i = 0; i < nw; ++i) o[i] = beta * w[i];
-    HIPCHK(c, hipMemcpy(c->tab[mode][axis], o.data(), o.size() * sizeof(cd), hipMemcpyHostToDevice));
-  }
+  gpk::AxisConst ac;
+  gpk::cn_axis_constants(n, d, c->p.dt, mode, m, f32, &ac);
+  for (int q = 0; q < 8; ++q) c->coef[mode][axis][q] = ac.coef[q];
+  c->nw[mode][axis] = ac.nw;
+  if (ac.nw == 0) return GP_OK;
+  std::vector<unsigned char> bytes;
+  gpk::pack_complex(ac.omega, f32, bytes);
+  HIPCHK(c, hipMemcpy(c->tab[mode][axis], bytes.data(), bytes.size(), hipMemcpyHostToDevice));
   return GP_OK;
 }
 

@@ -1,0 +1,1085 @@
+// Batched split-step Crank-Nicolson: many independent grids of different sizes advanced by
+// the same launches.  One step of a batch is four launches whatever the number of
+// instances: x sweep (+ potential step), y sweep, z sweep (+ norm partials), per-instance
+// finalize.  A per-block work table maps each block to (instance, block within the
+// instance); per-instance descriptors hold the dimensions, the offset of the instance's
+// psi in the caller's concatenated buffer, the Crank-Nicolson constants and the offsets
+// of its potential tables.  The launch boundaries are the instance-wide barriers between
+// the x, y and z phases; converged instances are masked by a flag in their descriptor,
+// so captured graphs stay valid.  The sweep bodies are those of the single-grid kernels.
+#include "../../include/gp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gp_device.h"
+
+namespace gpk {
+
+struct BInst {
+  int nx, ny, nz, active;
+  int64_t off;     // element offset of this instance's psi in the concatenated buffer
+  uint32_t bytes;  // size of this instance's psi in bytes
+  int split;
+  int nseg[3];           // segments per line: x, y (m points each), z (power of two)
+  int nw[2][3];          // Sherman-Morrison correction length [imag, real][axis]
+  int omega_off[2][3];   // element offsets into the omega table
+  int v_off[3];          // element offsets of the x, y, z potential / coordinate tables
+  int zb0, zb1;          // z-sweep blocks of this instance (norm partials)
+  int ob0, ob1;          // observables / scale blocks of this instance
+  double dt, dV;
+  double coef[2][3][8];  // a, b, b_lo, P as (re, im) [imag, real][axis]
+};
+
+struct BWork {
+  int inst;
+  int blk;
+};
+
+constexpr int kChunk = 1024;  // points per block of the pointwise batched kernels
+
+template <typename R> __device__ __forceinline__ typename VecOf<R>::T dval(const double* c) {
+  typename VecOf<R>::T v;
+  v.x = (R)c[0];
+  v.y = (R)c[1];
+  return v;
+}
+
+template <typename R, int M, int SW, bool CC, int NSTEP>
+__global__ void __launch_bounds__(1024)
+kb_sweep_lines(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst,
+               const BWork* __restrict__ work, int axis, const R* __restrict__ vtab,
+               const typename VecOf<R>::T* __restrict__ omega_all, const DevState* __restrict__ st) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const BWork wk = work[blockIdx.x];
+  const BInst& I = inst[wk.inst];
+  if (!I.active) return;
+  constexpr int mode = CC ? 1 : 0;
+  const int n = axis == 0 ? I.nx : I.ny;
+  const int64_t nlines = axis == 0 ? (int64_t)I.ny * I.nz : (int64_t)I.nx * I.nz;
+  const int64_t inner = axis == 0 ? (int64_t)I.ny * I.nz : (int64_t)I.nz;
+  const double* cf = I.coef[mode][axis];
+  R scale = 1, g = 0, tau = 0;
+  if (NSTEP != 0) {
+    scale = (R)st[wk.inst].s;
+    g = (R)st[wk.inst].g;
+    tau = (R)(I.split ? 0.5 * I.dt : I.dt);
+  }
+  const int nw = I.nw[mode][axis];
+  lines_body<R, M, SW, CC, NSTEP>(psi_all + I.off, I.bytes, dval<R>(cf), dval<R>(cf + 2), dval<R>(cf + 4),
+                                  dval<R>(cf + 6), omega_all + I.omega_off[mode][axis], nw <= M ? nw : 0, n,
+                                  I.nseg[axis], nlines, inner, vtab + I.v_off[0], vtab + I.v_off[1],
+                                  vtab + I.v_off[2], I.nz, tau, scale, g, wk.blk, smem_raw);
+}
+
+template <typename R, int MZ, bool CC, bool NORM, int EPI>
+__global__ void __launch_bounds__(256)
+kb_sweep_z(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst, const BWork* __restrict__ work,
+           const R* __restrict__ vtab, const typename VecOf<R>::T* __restrict__ omega_all,
+           const DevState* __restrict__ st, double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[4];
+  const BWork wk = work[blockIdx.x];
+  const BInst& I = inst[wk.inst];
+  if (!I.active) {
+    if (NORM && threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+    return;
+  }
+  constexpr int mode = CC ? 1 : 0;
+  const double* cf = I.coef[mode][2];
+  R g = 0;
+  if (EPI != 0) g = (R)st[wk.inst].g;
+  const double acc = z_body<R, MZ, CC, NORM, EPI>(
+      psi_all + I.off, dval<R>(cf), dval<R>(cf + 2), dval<R>(cf + 4), dval<R>(cf + 6),
+      omega_all + I.omega_off[mode][2], I.nw[mode][2], I.nz, I.nseg[2], (int64_t)I.nx * I.ny, vtab + I.v_off[0],
+      vtab + I.v_off[1], vtab + I.v_off[2], I.ny, (R)(0.5 * I.dt), g, wk.blk, (int64_t)1 << 62, smem_raw);
+  if (NORM) {
+    const double t = block_sum_256(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  }
+}
+
+// Sherman-Morrison head correction of x or y lines for instances whose correction is
+// longer than a segment (m points): one thread per line, lw lines per block (the line
+// blocks of the sweep's work table).
+template <typename R, bool CC>
+__global__ void __launch_bounds__(64)
+kb_head_correction(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst,
+                   const BWork* __restrict__ work, int axis, int lw, int m,
+                   const typename VecOf<R>::T* __restrict__ omega_all) {
+  typedef typename VecOf<R>::T V;
+  const BWork wk = work[blockIdx.x];
+  const BInst& I = inst[wk.inst];
+  constexpr int mode = CC ? 1 : 0;
+  const int nw = I.nw[mode][axis];
+  if (!I.active || nw <= m || (int)threadIdx.x >= lw) return;
+  const int n = axis == 0 ? I.nx : I.ny;
+  const int64_t nlines = axis == 0 ? (int64_t)I.ny * I.nz : (int64_t)I.nx * I.nz;
+  const int64_t inner = axis == 0 ? (int64_t)I.ny * I.nz : (int64_t)I.nz;
+  const int64_t line = (int64_t)wk.blk * lw + threadIdx.x;
+  if (line >= nlines) return;
+  V* psi = psi_all + I.off;
+  const V* omega = omega_all + I.omega_off[mode][axis];
+  const int64_t base = (line / inner) * (inner * n) + (line % inner);
+  const V u0 = psi[base];
+  for (int i = nw - 1; i >= 0; --i) psi[base + i * inner] = cfma<CC>(omega[i], u0, psi[base + i * inner]);
+}
+
+__global__ void __launch_bounds__(256)
+kb_finalize_norm(const double* __restrict__ partials, const BInst* __restrict__ inst, DevState* st) {
+  __shared__ double red[4];
+  const BInst& I = inst[blockIdx.x];
+  if (!I.active) return;
+  double acc = 0.0;
+  for (int q = I.zb0 + threadIdx.x; q < I.zb1; q += 256) acc += partials[q];
+  const double tot = block_sum_256(acc, red);
+  if (threadIdx.x == 0) {
+    DevState& S = st[blockIdx.x];
+    const double npre = tot * I.dV;
+    int f = 0;
+    if (!isfinite(npre)) f = 1;
+    else if (!(npre > 0.0)) f = 2;
+    S.npre = npre;
+    S.mu_est = (f == 0) ? -log(npre) / (2.0 * I.dt) : 0.0;
+    S.flags |= f;
+    S.s = (f == 0) ? 1.0 / sqrt(npre) : 1.0;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+kb_scale(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst, const BWork* __restrict__ work,
+         const DevState* __restrict__ st) {
+  const BWork wk = work[blockIdx.x];
+  const BInst& I = inst[wk.inst];
+  if (!I.active) return;
+  const R s = (R)st[wk.inst].s;
+  const int64_t npts = (int64_t)I.nx * I.ny * I.nz;
+  const int64_t q0 = (int64_t)wk.blk * kChunk, q1 = min(q0 + kChunk, npts);
+  typename VecOf<R>::T* psi = psi_all + I.off;
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
+    typename VecOf<R>::T v = psi[q];
+    v.x *= s;
+    v.y *= s;
+    psi[q] = v;
+  }
+}
+
+__global__ void kb_reset_scale(const BInst* __restrict__ inst, DevState* st, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n && inst[i].active) st[i].s = 1.0;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+kb_observables(const typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst,
+               const BWork* __restrict__ work, const double* __restrict__ a2, const double* __restrict__ vd,
+               double* __restrict__ partials) {
+  __shared__ double red[4];
+  const BWork wk = work[blockIdx.x];
+  const BInst& I = inst[wk.inst];
+  const int nx = I.nx, ny = I.ny, nz = I.nz;
+  const int64_t npts = (int64_t)nx * ny * nz, sx = (int64_t)ny * nz;
+  const typename VecOf<R>::T* psi = psi_all + I.off;
+  const double *x2 = a2 + I.v_off[0], *y2 = a2 + I.v_off[1], *z2 = a2 + I.v_off[2];
+  const double *vx = vd + I.v_off[0], *vy = vd + I.v_off[1], *vz = vd + I.v_off[2];
+  double acc[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+  const int64_t q0 = (int64_t)wk.blk * kChunk, q1 = min(q0 + kChunk, npts);
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
+    const int k = (int)(q % nz);
+    const int64_t r = q / nz;
+    const int j = (int)(r % ny);
+    const int i = (int)(r / ny);
+    const double re = psi[q].x, im = psi[q].y;
+    const double n2 = re * re + im * im;
+    double ex = 0, ey = 0, ez = 0, fx = 0, fy = 0, fz = 0;
+    if (i + 1 < nx) { ex = psi[q + sx].x; fx = psi[q + sx].y; }
+    if (j + 1 < ny) { ey = psi[q + nz].x; fy = psi[q + nz].y; }
+    if (k + 1 < nz) { ez = psi[q + 1].x; fz = psi[q + 1].y; }
+    double lx = (ex - re) * (ex - re) + (fx - im) * (fx - im);
+    double ly = (ey - re) * (ey - re) + (fy - im) * (fy - im);
+    double lz = (ez - re) * (ez - re) + (fz - im) * (fz - im);
+    if (i == 0) lx += n2;  // link from the zero ghost at -1
+    if (j == 0) ly += n2;
+    if (k == 0) lz += n2;
+    acc[0] += n2;
+    acc[1] += lx;
+    acc[2] += ly;
+    acc[3] += lz;
+    acc[4] += (vx[i] + vy[j] + vz[k]) * n2;
+    acc[5] += n2 * n2;
+    acc[6] += x2[i] * n2;
+    acc[7] += y2[j] * n2;
+    acc[8] += z2[k] * n2;
+  }
+  for (int c = 0; c < 9; ++c) {
+    const double t = block_sum_256(acc[c], red);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * 9 + c] = t;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+kb_obs_final(const double* __restrict__ partials, const BInst* __restrict__ inst, double* __restrict__ out) {
+  __shared__ double red[4];
+  const BInst& I = inst[blockIdx.x];
+  for (int c = 0; c < 9; ++c) {
+    double acc = 0.0;
+    for (int q = I.ob0 + threadIdx.x; q < I.ob1; q += 256) acc += partials[(int64_t)q * 9 + c];
+    const double t = block_sum_256(acc, red);
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * 9 + c] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+struct BLaunch {
+  void* psi;
+  const BInst* inst;
+  const BWork* work;
+  int nblocks;
+  int threads;
+  size_t lds;
+  int axis;
+  const void* vtab;
+  const void* omega;
+  const DevState* st;
+  double* partials;
+  int m, sw;
+  int nstep;  // 0 none, 1 imaginary, 2 real
+};
+
+template <typename R, int M, int SW, bool CC, int NSTEP>
+static hipError_t gob_lines(const BLaunch& a, hipStream_t s) {
+  typedef typename VecOf<R>::T V;
+  hipLaunchKernelGGL((kb_sweep_lines<R, M, SW, CC, NSTEP>), dim3(a.nblocks), dim3(a.threads), a.lds, s, (V*)a.psi,
+                     a.inst, a.work, a.axis, (const R*)a.vtab, (const V*)a.omega, a.st);
+  return hipGetLastError();
+}
+template <typename R, int M, int SW>
+static hipError_t gob_lines_mode(bool cc, const BLaunch& a, hipStream_t s) {
+  if (!cc) return a.nstep ? gob_lines<R, M, SW, false, 1>(a, s) : gob_lines<R, M, SW, false, 0>(a, s);
+  return a.nstep ? gob_lines<R, M, SW, true, 2>(a, s) : gob_lines<R, M, SW, true, 0>(a, s);
+}
+#define GPB_LINES_SW(R, M)                                 \
+  do {                                                     \
+    if (a.sw == 1) return gob_lines_mode<R, M, 1>(cc, a, s); \
+    if (a.sw == 2) return gob_lines_mode<R, M, 2>(cc, a, s); \
+    if (a.sw == 4) return gob_lines_mode<R, M, 4>(cc, a, s); \
+  } while (0)
+static hipError_t launch_b_lines(int prec, bool cc, const BLaunch& a, hipStream_t s) {
+  if (prec == 0) {
+    if (a.m == 8) GPB_LINES_SW(float, 8);
+    if (a.m == 16) GPB_LINES_SW(float, 16);
+    if (a.m == 32) GPB_LINES_SW(float, 32);
+  } else {
+    if (a.m == 8) GPB_LINES_SW(double, 8);
+    if (a.m == 16) GPB_LINES_SW(double, 16);
+  }
+  return hipErrorInvalidValue;
+}
+#undef GPB_LINES_SW
+
+template <typename R, int MZ, bool CC, bool NORM, int EPI>
+static hipError_t gob_z(const BLaunch& a, hipStream_t s) {
+  typedef typename VecOf<R>::T V;
+  hipLaunchKernelGGL((kb_sweep_z<R, MZ, CC, NORM, EPI>), dim3(a.nblocks), dim3(256), a.lds, s, (V*)a.psi, a.inst,
+                     a.work, (const R*)a.vtab, (const V*)a.omega, a.st, a.partials);
+  return hipGetLastError();
+}
+template <typename R, int MZ>
+static hipError_t gob_z_mode(bool cc, const BLaunch& a, hipStream_t s) {
+  if (!cc) return a.nstep ? gob_z<R, MZ, false, true, 1>(a, s) : gob_z<R, MZ, false, true, 0>(a, s);
+  return a.nstep ? gob_z<R, MZ, true, false, 2>(a, s) : gob_z<R, MZ, true, false, 0>(a, s);
+}
+#define GPB_Z(R)                                   \
+  do {                                             \
+    switch (a.m) {                                 \
+      case 4: return gob_z_mode<R, 4>(cc, a, s);   \
+      case 6: return gob_z_mode<R, 6>(cc, a, s);   \
+      case 8: return gob_z_mode<R, 8>(cc, a, s);   \
+      case 12: return gob_z_mode<R, 12>(cc, a, s); \
+      default: return hipErrorInvalidValue;        \
+    }                                              \
+  } while (0)
+static hipError_t launch_b_z(int prec, bool cc, const BLaunch& a, hipStream_t s) {
+  if (prec == 0) GPB_Z(float);
+  GPB_Z(double);
+}
+#undef GPB_Z
+
+static bool b_lines_supported(int prec, int m, int sw) {
+  if (sw != 1 && sw != 2 && sw != 4) return false;
+  return prec == 0 ? (m == 8 || m == 16 || m == 32) : (m == 8 || m == 16);
+}
+static bool b_z_supported(int m) { return m == 4 || m == 6 || m == 8 || m == 12; }
+
+}  // namespace gpk
+
+// ---------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------
+using gpk::BInst;
+using gpk::BWork;
+using gpk::DevState;
+
+namespace {
+constexpr int kBGraphSteps = 16;
+constexpr int kBKinds = 5;  // x, y, z, finalize, other
+}  // namespace
+
+struct gp_batch {
+  int n = 0;
+  int prec = 0;
+  size_t esize = 8;
+  std::vector<gp_params> p;
+  std::vector<int64_t> off;
+  void* psi = nullptr;
+  hipStream_t stream = nullptr, cap = nullptr;
+  int device = 0;
+  int map[5] = {16, 1, 16, 1, 8};  // m_x, sw_x, m_y, sw_y, m_z
+
+  std::vector<BInst> hinst;
+  BInst* dinst = nullptr;
+  DevState* st = nullptr;
+  void* vtab = nullptr;    // storage precision potentials, per instance x | y | z
+  double* vd = nullptr;    // FP64 potentials, same layout
+  double* a2 = nullptr;    // FP64 coordinate squares, same layout
+  void* omega = nullptr;   // storage precision, per instance [mode][axis]
+  BWork *wx = nullptr, *wy = nullptr, *wz = nullptr, *wo = nullptr;
+  int nbx = 0, nby = 0, nbz = 0, nbo = 0;
+  int thrx = 64, thry = 64;
+  bool need_hc[2][2] = {{false, false}, {false, false}};  // [mode][axis]: nw > m somewhere
+  size_t ldsx = 0, ldsy = 0, ldsz = 0;
+  double* zpart = nullptr;
+  double* opart = nullptr;
+  double* oout = nullptr;
+  double* host = nullptr;  // pinned, 9n doubles
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::vector<uint8_t> active;
+  std::vector<int64_t> steps;
+
+  bool timing = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  double tsum[kBKinds] = {0};
+  int64_t tcnt[kBKinds] = {0};
+  char err[256] = {0};
+};
+
+namespace {
+
+int bfail(gp_batch* b, hipError_t e, const char* where) {
+  if (b) snprintf(b->err, sizeof(b->err), "%s: %s", where, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? GP_ERR_OOM : GP_ERR_HIP;
+}
+#define BCHK(b, expr)                                 \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return bfail(b, e_, #expr); \
+  } while (0)
+
+int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+bool bad_inst(const gp_params& p) {
+  if (p.nx < 3 || p.ny < 3 || p.nz < 3 || p.nx > 1024 || p.ny > 1024 || p.nz > 1024) return true;
+  if (!(p.dx > 0) || !(p.dy > 0) || !(p.dz > 0) || !(p.dt > 0)) return true;
+  if (!std::isfinite(p.dx) || !std::isfinite(p.dy) || !std::isfinite(p.dz) || !std::isfinite(p.dt)) return true;
+  if (!(p.nux >= 0) || !(p.nuy >= 0) || !(p.nuz >= 0) || !std::isfinite(p.g)) return true;
+  if (!std::isfinite(p.nux) || !std::isfinite(p.nuy) || !std::isfinite(p.nuz)) return true;
+  if (p.split != GP_SPLIT_LIE && p.split != GP_SPLIT_STRANG) return true;
+  return false;
+}
+
+void bfree(gp_batch* b) {
+  for (auto& g : b->gexec)
+    if (g) (void)hipGraphExecDestroy(g), g = nullptr;
+  for (auto& r : b->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  b->recs.clear();
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  (void)hipFree(b->dinst);
+  (void)hipFree(b->st);
+  (void)hipFree(b->vtab);
+  (void)hipFree(b->vd);
+  (void)hipFree(b->a2);
+  (void)hipFree(b->omega);
+  (void)hipFree(b->wx);
+  (void)hipFree(b->wy);
+  (void)hipFree(b->wz);
+  (void)hipFree(b->wo);
+  (void)hipFree(b->zpart);
+  (void)hipFree(b->opart);
+  (void)hipFree(b->oout);
+  if (b->host) (void)hipHostFree(b->host);
+}
+
+template <typename T>
+int bdalloc(gp_batch* b, T** ptr, size_t bytes) {
+  hipError_t e = hipMalloc((void**)ptr, bytes > 0 ? bytes : 16);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return bfail(b, e, "hipMalloc");
+  }
+  return GP_OK;
+}
+
+template <typename T>
+int upload(gp_batch* b, T** dptr, const std::vector<T>& v) {
+  (void)hipFree(*dptr);
+  *dptr = nullptr;
+  int rc = bdalloc(b, dptr, v.size() * sizeof(T));
+  if (rc) return rc;
+  if (!v.empty()) BCHK(b, hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return GP_OK;
+}
+
+// Lay out descriptors, constants, work tables and scratch for the current mapping.
+int configure(gp_batch* b) {
+  for (auto& g : b->gexec)
+    if (g) (void)hipGraphExecDestroy(g), g = nullptr;
+  const int mx = b->map[0], swx = b->map[1], my = b->map[2], swy = b->map[3], mz = b->map[4];
+  if (!gpk::b_lines_supported(b->prec, mx, swx) || !gpk::b_lines_supported(b->prec, my, swy) ||
+      !gpk::b_z_supported(mz))
+    return GP_ERR_INVALID;
+  const bool f32 = b->prec == GP_C64;
+  std::vector<BInst> hi(b->n);
+  std::vector<BWork> wx, wy, wz, wo;
+  std::vector<unsigned char> omega;
+  bool need_hc[2][2] = {{false, false}, {false, false}};
+  int wavesx = 1, wavesy = 1;
+  size_t ldsz = 0;
+  int voff = 0;
+  for (int i = 0; i < b->n; ++i) {
+    const gp_params& p = b->p[i];
+    BInst& I = hi[i];
+    I.nx = p.nx;
+    I.ny = p.ny;
+    I.nz = p.nz;
+    I.active = b->active[i];
+    I.off = b->off[i];
+    I.bytes = (uint32_t)((int64_t)p.nx * p.ny * p.nz * b->esize);
+    I.split = p.split;
+    I.dt = p.dt;
+    I.dV = p.dx * p.dy * p.dz;
+    const int n[3] = {p.nx, p.ny, p.nz};
+    const double d[3] = {p.dx, p.dy, p.dz};
+    I.nseg[0] = cdiv(p.nx, mx);
+    I.nseg[1] = cdiv(p.ny, my);
+    int seg = 2;
+    while (seg < 64 && (int64_t)seg * mz < p.nz) seg <<= 1;
+    if ((int64_t)seg * mz < p.nz) return GP_ERR_UNSUPPORTED;
+    I.nseg[2] = seg;
+    if (cdiv(I.nseg[0], swx) > 16 || cdiv(I.nseg[1], swy) > 16) return GP_ERR_UNSUPPORTED;
+    const size_t lz = (size_t)4 * (64 / seg) * p.nz * b->esize;
+    if (lz + 512 > 65536) return GP_ERR_UNSUPPORTED;
+    ldsz = std::max(ldsz, lz);
+    wavesx = std::max(wavesx, cdiv(I.nseg[0], swx));
+    wavesy = std::max(wavesy, cdiv(I.nseg[1], swy));
+    const int m[3] = {mx, my, mz};
+    for (int mode = 0; mode < 2; ++mode)
+      for (int a = 0; a < 3; ++a) {
+        gpk::AxisConst ac;
+        gpk::cn_axis_constants(n[a], d[a], p.dt, mode, m[a], f32, &ac);
+        if (a < 2 && ac.nw > m[a]) need_hc[mode][a] = true;  // separate correction pass
+        for (int q = 0; q < 8; ++q) I.coef[mode][a][q] = ac.coef[q];
+        I.nw[mode][a] = ac.nw;
+        I.omega_off[mode][a] = (int)(omega.size() / b->esize);
+        std::vector<unsigned char> bytes;
+        gpk::pack_complex(ac.omega, f32, bytes);
+        omega.insert(omega.end(), bytes.begin(), bytes.end());
+      }
+    for (int a = 0; a < 3; ++a) {
+      I.v_off[a] = voff;
+      voff += n[a];
+    }
+    const int bx = cdiv((int64_t)p.ny * p.nz, 64 / swx), by = cdiv((int64_t)p.nx * p.nz, 64 / swy);
+    const int bz = cdiv((int64_t)p.nx * p.ny, 4 * (64 / seg));
+    const int bo = cdiv((int64_t)p.nx * p.ny * p.nz, gpk::kChunk);
+    for (int k = 0; k < bx; ++k) wx.push_back({i, k});
+    for (int k = 0; k < by; ++k) wy.push_back({i, k});
+    I.zb0 = (int)wz.size();
+    for (int k = 0; k < bz; ++k) wz.push_back({i, k});
+    I.zb1 = (int)wz.size();
+    I.ob0 = (int)wo.size();
+    for (int k = 0; k < bo; ++k) wo.push_back({i, k});
+    I.ob1 = (int)wo.size();
+  }
+  // potential and coordinate tables
+  std::vector<double> vd(voff), a2(voff);
+  std::vector<float> vf(voff);
+  for (int i = 0; i < b->n; ++i) {
+    const gp_params& p = b->p[i];
+    const int n[3] = {p.nx, p.ny, p.nz};
+    const double d[3] = {p.dx, p.dy, p.dz}, nu[3] = {p.nux, p.nuy, p.nuz};
+    for (int a = 0; a < 3; ++a)
+      for (int k = 0; k < n[a]; ++k) {
+        const double x = (k - 0.5 * (n[a] - 1)) * d[a];
+        a2[hi[i].v_off[a] + k] = x * x;
+        vd[hi[i].v_off[a] + k] = 0.5 * nu[a] * nu[a] * x * x;
+        vf[hi[i].v_off[a] + k] = (float)(0.5 * nu[a] * nu[a] * x * x);
+      }
+  }
+  int rc;
+  if ((rc = upload(b, &b->vd, vd)) || (rc = upload(b, &b->a2, a2))) return rc;
+  (void)hipFree(b->vtab);
+  b->vtab = nullptr;
+  if (f32) {
+    float* t = nullptr;
+    if ((rc = upload(b, &t, vf))) return rc;
+    b->vtab = t;
+  } else {
+    double* t = nullptr;
+    if ((rc = upload(b, &t, vd))) return rc;
+    b->vtab = t;
+  }
+  unsigned char* om = nullptr;
+  if ((rc = upload(b, &om, omega))) return rc;
+  (void)hipFree(b->omega);
+  b->omega = om;
+  if ((rc = upload(b, &b->wx, wx)) || (rc = upload(b, &b->wy, wy)) || (rc = upload(b, &b->wz, wz)) ||
+      (rc = upload(b, &b->wo, wo)) || (rc = upload(b, &b->dinst, hi)))
+    return rc;
+  b->hinst = hi;
+  for (int mode = 0; mode < 2; ++mode)
+    for (int a = 0; a < 2; ++a) b->need_hc[mode][a] = need_hc[mode][a];
+  b->nbx = (int)wx.size();
+  b->nby = (int)wy.size();
+  b->nbz = (int)wz.size();
+  b->nbo = (int)wo.size();
+  b->thrx = wavesx * 64;
+  b->thry = wavesy * 64;
+  b->ldsx = (size_t)3 * wavesx * swx * (64 / swx) * b->esize;
+  b->ldsy = (size_t)3 * wavesy * swy * (64 / swy) * b->esize;
+  b->ldsz = ldsz;
+  (void)hipFree(b->zpart);
+  (void)hipFree(b->opart);
+  b->zpart = b->opart = nullptr;
+  if ((rc = bdalloc(b, &b->zpart, (size_t)b->nbz * sizeof(double)))) return rc;
+  if ((rc = bdalloc(b, &b->opart, (size_t)b->nbo * 9 * sizeof(double)))) return rc;
+  return GP_OK;
+}
+
+template <typename F>
+int btimed(gp_batch* b, hipStream_t s, int kind, F fn) {
+  if (!b->timing || s != b->stream) {
+    hipError_t e = fn(s);
+    return e == hipSuccess ? GP_OK : bfail(b, e, "kernel launch");
+  }
+  hipEvent_t e0, e1;
+  BCHK(b, hipEventCreate(&e0));
+  BCHK(b, hipEventCreate(&e1));
+  BCHK(b, hipEventRecord(e0, s));
+  hipError_t e = fn(s);
+  if (e != hipSuccess) return bfail(b, e, "kernel launch");
+  BCHK(b, hipEventRecord(e1, s));
+  b->recs.push_back({kind, e0, e1});
+  return GP_OK;
+}
+
+int bharvest(gp_batch* b) {
+  if (b->recs.empty()) return GP_OK;
+  BCHK(b, hipStreamSynchronize(b->stream));
+  for (auto& r : b->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      b->tsum[r.kind] += ms;
+      b->tcnt[r.kind] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  b->recs.clear();
+  return GP_OK;
+}
+
+int benqueue_step(gp_batch* b, int mode, hipStream_t s) {
+  const bool cc = mode == 1;
+  const int strang = b->p[0].split == GP_SPLIT_STRANG;
+  gpk::BLaunch ax{b->psi, b->dinst, b->wx, b->nbx, b->thrx, b->ldsx, 0, b->vtab, b->omega, b->st, nullptr,
+                  b->map[0], b->map[1], mode == 0 ? 1 : 2};
+  gpk::BLaunch ay{b->psi, b->dinst, b->wy, b->nby, b->thry, b->ldsy, 1, b->vtab, b->omega, b->st, nullptr,
+                  b->map[2], b->map[3], 0};
+  gpk::BLaunch az{b->psi, b->dinst, b->wz, b->nbz, 256, b->ldsz, 2, b->vtab, b->omega, b->st, b->zpart,
+                  b->map[4], 0, strang ? (mode == 0 ? 1 : 2) : 0};
+  auto head = [&](const gpk::BLaunch& l, hipStream_t t) {
+    const int lw = 64 / l.sw;
+    if (b->prec == GP_C64) {
+      if (cc)
+        hipLaunchKernelGGL((gpk::kb_head_correction<float, true>), dim3(l.nblocks), dim3(64), 0, t, (float2*)b->psi,
+                           b->dinst, l.work, l.axis, lw, l.m, (const float2*)b->omega);
+      else
+        hipLaunchKernelGGL((gpk::kb_head_correction<float, false>), dim3(l.nblocks), dim3(64), 0, t,
+                           (float2*)b->psi, b->dinst, l.work, l.axis, lw, l.m, (const float2*)b->omega);
+    } else {
+      if (cc)
+        hipLaunchKernelGGL((gpk::kb_head_correction<double, true>), dim3(l.nblocks), dim3(64), 0, t,
+                           (double2*)b->psi, b->dinst, l.work, l.axis, lw, l.m, (const double2*)b->omega);
+      else
+        hipLaunchKernelGGL((gpk::kb_head_correction<double, false>), dim3(l.nblocks), dim3(64), 0, t,
+                           (double2*)b->psi, b->dinst, l.work, l.axis, lw, l.m, (const double2*)b->omega);
+    }
+    return hipGetLastError();
+  };
+  int rc = btimed(b, s, 0, [&](hipStream_t t) {
+    hipError_t e = gpk::launch_b_lines(b->prec, cc, ax, t);
+    if (e == hipSuccess && b->need_hc[mode][0]) e = head(ax, t);
+    return e;
+  });
+  if (rc) return rc;
+  rc = btimed(b, s, 1, [&](hipStream_t t) {
+    hipError_t e = gpk::launch_b_lines(b->prec, cc, ay, t);
+    if (e == hipSuccess && b->need_hc[mode][1]) e = head(ay, t);
+    return e;
+  });
+  if (rc) return rc;
+  rc = btimed(b, s, 2, [&](hipStream_t t) { return gpk::launch_b_z(b->prec, cc, az, t); });
+  if (rc) return rc;
+  if (mode == 0) {
+    rc = btimed(b, s, 3, [&](hipStream_t t) {
+      hipLaunchKernelGGL(gpk::kb_finalize_norm, dim3(b->n), dim3(256), 0, t, b->zpart, b->dinst, b->st);
+      return hipGetLastError();
+    });
+    if (rc) return rc;
+  }
+  return GP_OK;
+}
+
+int bensure_graph(gp_batch* b, int mode) {
+  if (b->gexec[mode]) return GP_OK;
+  if (!b->cap) BCHK(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  BCHK(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  int rc = GP_OK;
+  for (int k = 0; k < kBGraphSteps && rc == GP_OK; ++k) rc = benqueue_step(b, mode, b->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return bfail(b, e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&b->gexec[mode], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->gexec[mode] = nullptr;
+    return bfail(b, e, "hipGraphInstantiate");
+  }
+  return GP_OK;
+}
+
+int bset_active(gp_batch* b, const uint8_t* active) {
+  if (!active) return GP_OK;
+  bool changed = false;
+  for (int i = 0; i < b->n; ++i) {
+    const int a = active[i] ? 1 : 0;
+    if (b->hinst[i].active != a) {
+      b->hinst[i].active = a;
+      b->active[i] = (uint8_t)a;
+      changed = true;
+    }
+  }
+  if (!changed) return GP_OK;
+  BCHK(b, hipStreamSynchronize(b->stream));
+  BCHK(b, hipMemcpy(b->dinst, b->hinst.data(), b->hinst.size() * sizeof(BInst), hipMemcpyHostToDevice));
+  return GP_OK;
+}
+
+int brun(gp_batch* b, int mode, int32_t n) {
+  int32_t left = n;
+  if (!b->timing && n >= kBGraphSteps) {
+    int rc = bensure_graph(b, mode);
+    if (rc) return rc;
+    while (left >= kBGraphSteps) {
+      BCHK(b, hipGraphLaunch(b->gexec[mode], b->stream));
+      left -= kBGraphSteps;
+    }
+  }
+  for (int32_t k = 0; k < left; ++k) {
+    int rc = benqueue_step(b, mode, b->stream);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < b->n; ++i)
+    if (b->active[i]) b->steps[i] += n;
+  return GP_OK;
+}
+
+int bobserve(gp_batch* b) {
+  int rc = btimed(b, b->stream, 4, [&](hipStream_t t) {
+    if (b->prec == GP_C64)
+      hipLaunchKernelGGL(gpk::kb_observables<float>, dim3(b->nbo), dim3(256), 0, t, (const float2*)b->psi, b->dinst,
+                         b->wo, b->a2, b->vd, b->opart);
+    else
+      hipLaunchKernelGGL(gpk::kb_observables<double>, dim3(b->nbo), dim3(256), 0, t, (const double2*)b->psi,
+                         b->dinst, b->wo, b->a2, b->vd, b->opart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gpk::kb_obs_final, dim3(b->n), dim3(256), 0, t, b->opart, b->dinst, b->oout);
+    return hipGetLastError();
+  });
+  if (rc) return rc;
+  BCHK(b, hipMemcpyAsync(b->host, b->oout, (size_t)b->n * 9 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  BCHK(b, hipStreamSynchronize(b->stream));
+  // scale to raw sums: N, Tx, Ty, Tz, U, I, X2, Y2, Z2
+  int status = GP_OK;
+  for (int i = 0; i < b->n; ++i) {
+    const gp_params& p = b->p[i];
+    double* r = b->host + (size_t)9 * i;
+    const double dV = p.dx * p.dy * p.dz;
+    const double d2[3] = {p.dx * p.dx, p.dy * p.dy, p.dz * p.dz};
+    r[0] *= dV;
+    for (int a = 0; a < 3; ++a) r[1 + a] *= 0.5 * dV / d2[a];
+    for (int q = 4; q < 9; ++q) r[q] *= dV;
+    for (int q = 0; q < 9; ++q)
+      if (!std::isfinite(r[q])) status = GP_ERR_NONFINITE;
+    if (status == GP_OK && !(r[0] > 0)) status = GP_ERR_ZERO_NORM;
+  }
+  return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gp_batch_init(const gp_params* p, int32_t n, void* psi_dev, const int64_t* offsets, void* hip_stream,
+                  gp_batch** out) {
+  if (!out) return GP_ERR_INVALID;
+  *out = nullptr;
+  if (!p || n < 1 || !psi_dev || !offsets) return GP_ERR_INVALID;
+  const int prec = p[0].precision;
+  if (prec != GP_C64 && prec != GP_C128) return GP_ERR_INVALID;
+  for (int i = 0; i < n; ++i) {
+    if (bad_inst(p[i]) || p[i].precision != prec || p[i].split != p[0].split) return GP_ERR_INVALID;
+    if (offsets[i] < 0) return GP_ERR_INVALID;
+    if ((int64_t)p[i].nx * p[i].ny * p[i].nz * (prec == GP_C128 ? 16 : 8) >= (int64_t)1 << 32)
+      return GP_ERR_UNSUPPORTED;
+  }
+  gp_batch* b = new (std::nothrow) gp_batch;
+  if (!b) return GP_ERR_OOM;
+  b->n = n;
+  b->prec = prec;
+  b->esize = prec == GP_C128 ? 16 : 8;
+  b->p.assign(p, p + n);
+  b->off.assign(offsets, offsets + n);
+  b->psi = psi_dev;
+  b->stream = (hipStream_t)hip_stream;
+  b->active.assign(n, 1);
+  b->steps.assign(n, 0);
+  if (prec == GP_C128) {
+    b->map[0] = 8;
+    b->map[2] = 8;
+  }
+  int rc = GP_OK;
+  hipPointerAttribute_t attr;
+  if (hipGetDevice(&b->device) != hipSuccess || hipPointerGetAttributes(&attr, psi_dev) != hipSuccess ||
+      (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
+    (void)hipGetLastError();
+    rc = GP_ERR_INVALID;
+  }
+  if (rc == GP_OK) rc = configure(b);
+  if (rc == GP_OK) rc = bdalloc(b, &b->st, (size_t)n * sizeof(DevState));
+  if (rc == GP_OK) rc = bdalloc(b, &b->oout, (size_t)n * 9 * sizeof(double));
+  if (rc == GP_OK) {
+    if (hipHostMalloc((void**)&b->host, (size_t)n * 9 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+      rc = GP_ERR_OOM;
+  }
+  if (rc == GP_OK) {
+    std::vector<DevState> s0(n);
+    for (int i = 0; i < n; ++i) {
+      s0[i] = DevState{};
+      s0[i].s = 1.0;
+      s0[i].g = p[i].g;
+      s0[i].npre = 1.0;
+    }
+    if (hipMemcpy(b->st, s0.data(), n * sizeof(DevState), hipMemcpyHostToDevice) != hipSuccess) rc = GP_ERR_HIP;
+  }
+  if (rc != GP_OK) {
+    bfree(b);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return GP_OK;
+}
+
+int gp_batch_destroy(gp_batch* b) {
+  if (!b) return GP_ERR_INVALID;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  else (void)hipDeviceSynchronize();
+  bfree(b);
+  delete b;
+  return GP_OK;
+}
+
+int gp_batch_step_imag(gp_batch* b, int32_t nsteps, const uint8_t* active) {
+  if (!b || nsteps < 0) return GP_ERR_INVALID;
+  int rc = bset_active(b, active);
+  if (rc || nsteps == 0) return rc;
+  if ((rc = brun(b, 0, nsteps))) return rc;
+  return btimed(b, b->stream, 4, [&](hipStream_t t) {
+    if (b->prec == GP_C64)
+      hipLaunchKernelGGL(gpk::kb_scale<float>, dim3(b->nbo), dim3(256), 0, t, (float2*)b->psi, b->dinst, b->wo, b->st);
+    else
+      hipLaunchKernelGGL(gpk::kb_scale<double>, dim3(b->nbo), dim3(256), 0, t, (double2*)b->psi, b->dinst, b->wo,
+                         b->st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gpk::kb_reset_scale, dim3((b->n + 255) / 256), dim3(256), 0, t, b->dinst, b->st, b->n);
+    return hipGetLastError();
+  });
+}
+
+int gp_batch_step_real(gp_batch* b, int32_t nsteps, const uint8_t* active) {
+  if (!b || nsteps < 0) return GP_ERR_INVALID;
+  int rc = bset_active(b, active);
+  if (rc || nsteps == 0) return rc;
+  return brun(b, 1, nsteps);
+}
+
+int gp_batch_raw_sums(gp_batch* b, double* raw) {
+  if (!b || !raw) return GP_ERR_INVALID;
+  int rc = bobserve(b);
+  std::memcpy(raw, b->host, (size_t)b->n * 9 * sizeof(double));
+  return rc;
+}
+
+int gp_batch_norm(gp_batch* b, double* norm) {
+  if (!b || !norm) return GP_ERR_INVALID;
+  int rc = bobserve(b);
+  for (int i = 0; i < b->n; ++i) norm[i] = b->host[(size_t)9 * i];
+  return rc;
+}
+
+int gp_batch_energy_mu(gp_batch* b, double* energy, double* mu) {
+  if (!b || !energy || !mu) return GP_ERR_INVALID;
+  int rc = bobserve(b);
+  for (int i = 0; i < b->n; ++i) {
+    const double* r = b->host + (size_t)9 * i;
+    const double N = r[0];
+    const double lin = (r[1] + r[2] + r[3] + r[4]) / N;
+    const double nl = b->p[i].g * r[5] / (N * N);
+    energy[i] = lin + 0.5 * nl;
+    mu[i] = lin + nl;
+  }
+  return rc;
+}
+
+int gp_batch_rms(gp_batch* b, double* rms4) {
+  if (!b || !rms4) return GP_ERR_INVALID;
+  int rc = bobserve(b);
+  for (int i = 0; i < b->n; ++i) {
+    const double* r = b->host + (size_t)9 * i;
+    rms4[4 * i] = std::sqrt(r[6] / r[0]);
+    rms4[4 * i + 1] = std::sqrt(r[7] / r[0]);
+    rms4[4 * i + 2] = std::sqrt(r[8] / r[0]);
+    rms4[4 * i + 3] = std::sqrt((r[6] + r[7] + r[8]) / r[0]);
+  }
+  return rc;
+}
+
+int gp_batch_status(gp_batch* b, int64_t* steps_done, double* mu_est, int32_t* flags) {
+  if (!b) return GP_ERR_INVALID;
+  std::vector<DevState> s(b->n);
+  BCHK(b, hipStreamSynchronize(b->stream));
+  BCHK(b, hipMemcpy(s.data(), b->st, b->n * sizeof(DevState), hipMemcpyDeviceToHost));
+  for (int i = 0; i < b->n; ++i) {
+    if (steps_done) steps_done[i] = b->steps[i];
+    if (mu_est) mu_est[i] = s[i].mu_est;
+    if (flags) flags[i] = s[i].flags;
+  }
+  return GP_OK;
+}
+
+int gp_batch_converge_imag(gp_batch* b, double tol, int32_t check_every, int64_t max_steps, int64_t* steps_taken,
+                           double* mu, int32_t* converged) {
+  if (!b || !(tol > 0) || max_steps < 0 || check_every < 0) return GP_ERR_INVALID;
+  int32_t K = check_every;
+  if (K == 0) {
+    double dtmin = b->p[0].dt;
+    for (auto& q : b->p) dtmin = std::min(dtmin, q.dt);
+    K = std::max(1, (int32_t)std::ceil(0.25 / dtmin));
+  }
+  const int n = b->n;
+  std::vector<double> prev(n, NAN), cur(n, NAN), e(n);
+  std::vector<uint8_t> act(n, 1);
+  std::vector<int64_t> taken(n, 0);
+  std::vector<int32_t> conv(n, 0);
+  int rc = bset_active(b, act.data());
+  if (rc) return rc;
+  int64_t done = 0;
+  int remaining = n;
+  while (done < max_steps && remaining > 0) {
+    const int32_t k = (int32_t)std::min<int64_t>(K, max_steps - done);
+    if ((rc = gp_batch_step_imag(b, k, act.data()))) break;
+    done += k;
+    for (int i = 0; i < n; ++i)
+      if (act[i]) taken[i] += k;
+    if ((rc = gp_batch_energy_mu(b, e.data(), cur.data())) && rc != GP_ERR_NONFINITE && rc != GP_ERR_ZERO_NORM)
+      break;
+    rc = GP_OK;
+    for (int i = 0; i < n; ++i) {
+      if (!act[i]) continue;
+      if (std::isfinite(prev[i]) && std::fabs(cur[i] - prev[i]) <= tol * std::fabs(cur[i])) {
+        conv[i] = 1;
+        act[i] = 0;
+        --remaining;
+      } else if (!std::isfinite(cur[i])) {
+        act[i] = 0;  // diverged: stop it, report not converged
+        --remaining;
+      }
+      prev[i] = cur[i];
+    }
+  }
+  std::vector<uint8_t> all(n, 1);
+  int rc2 = bset_active(b, all.data());
+  if (rc == GP_OK) rc = rc2;
+  for (int i = 0; i < n; ++i) {
+    if (steps_taken) steps_taken[i] = taken[i];
+    if (mu) mu[i] = cur[i];
+    if (converged) converged[i] = conv[i];
+  }
+  return rc;
+}
+
+int gp_batch_get_mapping(gp_batch* b, int32_t map[5]) {
+  if (!b || !map) return GP_ERR_INVALID;
+  for (int q = 0; q < 5; ++q) map[q] = b->map[q];
+  return GP_OK;
+}
+
+int gp_batch_set_mapping(gp_batch* b, const int32_t map[5]) {
+  if (!b || !map) return GP_ERR_INVALID;
+  BCHK(b, hipStreamSynchronize(b->stream));
+  int old[5];
+  for (int q = 0; q < 5; ++q) {
+    old[q] = b->map[q];
+    if (map[q] > 0) b->map[q] = map[q];
+  }
+  int rc = configure(b);
+  if (rc) {
+    for (int q = 0; q < 5; ++q) b->map[q] = old[q];
+    int rc2 = configure(b);
+    (void)rc2;
+    return rc == GP_ERR_UNSUPPORTED ? GP_ERR_INVALID : rc;
+  }
+  return GP_OK;
+}
+
+int gp_batch_set_timing(gp_batch* b, int32_t enable) {
+  if (!b) return GP_ERR_INVALID;
+  int rc = bharvest(b);
+  if (rc) return rc;
+  b->timing = enable != 0;
+  for (int k = 0; k < kBKinds; ++k) {
+    b->tsum[k] = 0;
+    b->tcnt[k] = 0;
+  }
+  return GP_OK;
+}
+
+int gp_batch_get_timing(gp_batch* b, double ms_mean[5], int64_t launches[5]) {
+  if (!b) return GP_ERR_INVALID;
+  int rc = bharvest(b);
+  if (rc) return rc;
+  for (int k = 0; k < kBKinds; ++k) {
+    if (ms_mean) ms_mean[k] = b->tcnt[k] ? b->tsum[k] / b->tcnt[k] : 0.0;
+    if (launches) launches[k] = b->tcnt[k];
+  }
+  return GP_OK;
+}
+
+int gp_batch_autotune(gp_batch* b, int32_t mode, int32_t steps, int32_t map_out[5]) {
+  if (!b || (mode != 0 && mode != 1) || steps < 1) return GP_ERR_INVALID;
+  // tune on a copy of psi; restore psi, state and step counts afterwards
+  int64_t total = 0;
+  for (int i = 0; i < b->n; ++i)
+    total = std::max<int64_t>(total, b->off[i] + (int64_t)b->p[i].nx * b->p[i].ny * b->p[i].nz);
+  const size_t bytes = (size_t)total * b->esize;
+  void* saved = nullptr;
+  int rc = bdalloc(b, &saved, bytes);
+  if (rc) return rc;
+  std::vector<DevState> st0(b->n);
+  BCHK(b, hipStreamSynchronize(b->stream));
+  BCHK(b, hipMemcpy(st0.data(), b->st, b->n * sizeof(DevState), hipMemcpyDeviceToHost));
+  BCHK(b, hipMemcpy(saved, b->psi, bytes, hipMemcpyDeviceToDevice));
+  const std::vector<int64_t> steps0 = b->steps;
+  int best[5];
+  for (int q = 0; q < 5; ++q) best[q] = b->map[q];
+  double best_ms[3] = {1e300, 1e300, 1e300};
+  auto trial = [&](int kind, const int* cand, double* ms) -> int {
+    int rc2 = gp_batch_set_mapping(b, cand);
+    if (rc2) return rc2;
+    if ((rc2 = brun(b, mode, 1))) return rc2;
+    if ((rc2 = gp_batch_set_timing(b, 1))) return rc2;
+    if ((rc2 = brun(b, mode, steps))) return rc2;
+    double mean[5];
+    int64_t cnt[5];
+    if ((rc2 = gp_batch_get_timing(b, mean, cnt))) return rc2;
+    *ms = mean[kind];
+    return gp_batch_set_timing(b, 0);
+  };
+  const int ms_lines[] = {8, 16, 32};
+  for (int axis = 0; axis < 2 && rc == GP_OK; ++axis)
+    for (int m : ms_lines)
+      for (int sw : {1, 2, 4}) {
+        if (!gpk::b_lines_supported(b->prec, m, sw)) continue;
+        int cand[5];
+        for (int q = 0; q < 5; ++q) cand[q] = best[q];
+        cand[2 * axis] = m;
+        cand[2 * axis + 1] = sw;
+        double ms = 0;
+        int r2 = trial(axis, cand, &ms);
+        if (r2 == GP_ERR_INVALID) continue;  // mapping does not fit every instance
+        if (r2) {
+          rc = r2;
+          break;
+        }
+        if (ms < best_ms[axis]) {
+          best_ms[axis] = ms;
+          best[2 * axis] = m;
+          best[2 * axis + 1] = sw;
+        }
+      }
+  for (int m : {4, 6, 8, 12}) {
+    if (rc) break;
+    int cand[5];
+    for (int q = 0; q < 5; ++q) cand[q] = best[q];
+    cand[4] = m;
+    double ms = 0;
+    int r2 = trial(2, cand, &ms);
+    if (r2 == GP_ERR_INVALID) continue;
+    if (r2) {
+      rc = r2;
+      break;
+    }
+    if (ms < best_ms[2]) {
+      best_ms[2] = ms;
+      best[4] = m;
+    }
+  }
+  if (rc == GP_OK) rc = gp_batch_set_mapping(b, best);
+  (void)hipMemcpy(b->psi, saved, bytes, hipMemcpyDeviceToDevice);
+  (void)hipMemcpy(b->st, st0.data(), b->n * sizeof(DevState), hipMemcpyHostToDevice);
+  (void)hipFree(saved);
+  b->steps = steps0;
+  if (rc) return rc;
+  if (map_out)
+    for (int q = 0; q < 5; ++q) map_out[q] = best[q];
+  return GP_OK;
+}
+
+const char* gp_batch_last_error(gp_batch* b) { return b ? b->err : "null batch"; }
+
+}  // extern "C"

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <complex>
+#include <vector>
+
 namespace gpk {
 
 // Device-resident solver state, read by the kernels through a pointer so that captured
@@ -68,6 +71,15 @@ struct ObsLaunch {
   double* out;
 };
 hipError_t launch_observables(int precision, const ObsLaunch& a, hipStream_t s);
+
+// Host: constants of the constant-pivot CN solve along one axis (computed in FP64).
+struct AxisConst {
+  double coef[8];                             // a, b, b_lo, P = a^m as (re, im), rounded
+  int nw;                                     // Sherman-Morrison correction length
+  std::vector<std::complex<double>> omega;    // FP64 correction coefficients
+};
+void cn_axis_constants(int n, double d, double dt, int mode, int m, bool f32, AxisConst* out);
+void pack_complex(const std::vector<std::complex<double>>& v, bool f32, std::vector<unsigned char>& out);
 
 // Supported line mappings (x/y kernels: points per thread and segments per wavefront)
 bool sweep_lines_supported(int precision, int m, int sw);

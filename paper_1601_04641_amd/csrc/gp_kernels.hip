@@ -29,209 +29,12 @@
 // running products.  This is algebraically the same elimination as the
 // serial Thomas sweep (only rounding order differs) and needs no d' storage beyond the
 // segment held in registers, so psi is read once and written once per sweep.
-#include "gp_internal.h"
+#include "gp_device.h"
 
 namespace gpk {
 
-template <typename R> struct VecOf;
-template <> struct VecOf<float> { typedef float2 T; };
-template <> struct VecOf<double> { typedef double2 T; };
-
-template <typename V> __device__ __forceinline__ V vmake(decltype(V::x) x, decltype(V::x) y) {
-  V r;
-  r.x = x;
-  r.y = y;
-  return r;
-}
-template <typename V> __device__ __forceinline__ V vzero() { return vmake<V>(0, 0); }
-template <typename V> __device__ __forceinline__ V vone() { return vmake<V>(1, 0); }
-template <typename V> __device__ __forceinline__ V vadd(V a, V b) { return vmake<V>(a.x + b.x, a.y + b.y); }
-
-// coefficient * value; with real coefficients (CC = false) only a.x is used
-template <bool CC, typename V> __device__ __forceinline__ V cmul(V a, V b) {
-  if (CC) return vmake<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-  return vmake<V>(a.x * b.x, a.x * b.y);
-}
-// a * b + c
-template <bool CC, typename V> __device__ __forceinline__ V cfma(V a, V b, V c) {
-  if (CC) return vmake<V>(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
-  return vmake<V>(fma(a.x, b.x, c.x), fma(a.x, b.y, c.y));
-}
-
-__device__ __forceinline__ float dexp(float v) { return expf(v); }
-__device__ __forceinline__ double dexp(double v) { return exp(v); }
-
-// sin and cos for the real-time phase factor.  Cody and Waite's additive reduction
-// x = k pi/2 + r with pi/2 split into three parts (each k * part exact inside an FMA),
-// |r| <= pi/4, then the Taylor series of sin and cos in r (through r^9 / r^10 in FP32,
-// r^17 / r^18 in FP64; truncation below 1e-10 resp. 1e-20 on [-pi/4, pi/4]), and the
-// quadrant k mod 4.  Worst error found on a dense sample of |x| <= 1e4 against the C
-// library: 1.4 ulp (FP32), 1.0 ulp (FP64).  Larger |x| take the library routine, kept
-// out of line so that it does not occupy registers in the unrolled sweep.  The phase of
-// one real-time step is usually far below 1/8; there the series is used directly.
-__device__ __noinline__ void sincos_far(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __noinline__ void sincos_far(double x, double* s, double* c) { sincos(x, s, c); }
-
-__device__ __forceinline__ void quadrant(int q, float sp, float cp, float* s, float* c) {
-  float ss = (q & 1) ? cp : sp, cc = (q & 1) ? sp : cp;
-  *s = (q & 2) ? -ss : ss;
-  *c = ((q + 1) & 2) ? -cc : cc;
-}
-__device__ __forceinline__ void quadrant(int q, double sp, double cp, double* s, double* c) {
-  double ss = (q & 1) ? cp : sp, cc = (q & 1) ? sp : cp;
-  *s = (q & 2) ? -ss : ss;
-  *c = ((q + 1) & 2) ? -cc : cc;
-}
-
-__device__ __forceinline__ void dsincos(float x, float* s, float* c) {
-  if (fabsf(x) < 0.125f) {  // typical step: no reduction, series through x^5 / x^6
-    const float x2 = x * x;  // truncation < (1/8)^7/7! / (1/8) = 7.6e-10 (sin), 1.5e-12 (cos)
-    *s = fmaf(x * x2, fmaf(x2, 1.0f / 120.0f, -1.0f / 6.0f), x);
-    *c = fmaf(x2, fmaf(x2, fmaf(x2, -1.0f / 720.0f, 1.0f / 24.0f), -0.5f), 1.0f);
-    return;
-  }
-  if (fabsf(x) > 1.0e4f) {
-    sincos_far(x, s, c);
-    return;
-  }
-  const float k = rintf(x * 0.636619772f);  // 2/pi
-  float r = fmaf(-k, 1.57079637f, x);       // pi/2 = 1.57079637 - 4.37113883e-8 - 1.71512451e-15
-  r = fmaf(-k, -4.37113883e-08f, r);
-  r = fmaf(-k, -1.71512451e-15f, r);
-  const float r2 = r * r;
-  const float ps = fmaf(r2, fmaf(r2, fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f), -1.0f / 6.0f);
-  const float sp = fmaf(r * r2, ps, r);
-  const float pc = fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -1.0f / 3628800.0f, 1.0f / 40320.0f), -1.0f / 720.0f),
-                             1.0f / 24.0f), -0.5f);
-  const float cp = fmaf(r2, pc, 1.0f);
-  quadrant((int)k & 3, sp, cp, s, c);
-}
-
-__device__ __forceinline__ void dsincos(double x, double* s, double* c) {
-  if (fabs(x) < 0.125) {  // typical step: series through x^11 / x^12, truncation < 1e-20
-    const double x2 = x * x;
-    double ps = fma(x2, -1.0 / 39916800.0, 1.0 / 362880.0);  // sin: -1/11!, 1/9!, ...
-    ps = fma(x2, ps, -1.0 / 5040.0);
-    ps = fma(x2, ps, 1.0 / 120.0);
-    ps = fma(x2, ps, -1.0 / 6.0);
-    *s = fma(x * x2, ps, x);
-    double pc = fma(x2, 1.0 / 479001600.0, -1.0 / 3628800.0);  // cos: 1/12!, -1/10!, ...
-    pc = fma(x2, pc, 1.0 / 40320.0);
-    pc = fma(x2, pc, -1.0 / 720.0);
-    pc = fma(x2, pc, 1.0 / 24.0);
-    pc = fma(x2, pc, -0.5);
-    *c = fma(x2, pc, 1.0);
-    return;
-  }
-  if (fabs(x) > 1.0e9) {
-    sincos_far(x, s, c);
-    return;
-  }
-  const double k = rint(x * 0.6366197723675814);  // 2/pi
-  double r = fma(-k, 1.5707963267948966, x);       // pi/2 in three parts
-  r = fma(-k, 6.123233995736766e-17, r);
-  r = fma(-k, -1.4973849048591698e-33, r);
-  const double r2 = r * r;
-  // ps = 1/3! - r^2/5! + ... - r^14/17!, sin r = r - r^3 ps; pc likewise, cos r = 1 - r^2 pc
-  double ps = -1.0 / 355687428096000.0;               // -1/17!
-  ps = fma(r2, ps, 1.0 / 1307674368000.0);            //  1/15!
-  ps = fma(r2, ps, -1.0 / 6227020800.0);              // -1/13!
-  ps = fma(r2, ps, 1.0 / 39916800.0);                 //  1/11!
-  ps = fma(r2, ps, -1.0 / 362880.0);                  // -1/9!
-  ps = fma(r2, ps, 1.0 / 5040.0);                     //  1/7!
-  ps = fma(r2, ps, -1.0 / 120.0);                     // -1/5!
-  ps = fma(r2, ps, 1.0 / 6.0);
-  const double sp = fma(r * r2, -ps, r);
-  double pc = 1.0 / 6402373705728000.0;               //  1/18!
-  pc = fma(r2, pc, -1.0 / 20922789888000.0);          // -1/16!
-  pc = fma(r2, pc, 1.0 / 87178291200.0);              //  1/14!
-  pc = fma(r2, pc, -1.0 / 479001600.0);               // -1/12!
-  pc = fma(r2, pc, 1.0 / 3628800.0);                  //  1/10!
-  pc = fma(r2, pc, -1.0 / 40320.0);                   // -1/8!
-  pc = fma(r2, pc, 1.0 / 720.0);                      //  1/6!
-  pc = fma(r2, pc, -1.0 / 24.0);                      // -1/4!
-  pc = fma(r2, pc, 0.5);
-  const double cp = fma(r2, -pc, 1.0);
-  quadrant((int)k & 3, sp, cp, s, c);
-}
-
-// Potential + nonlinear step on one value (calcnu): p <- scale p, then
-// imaginary time p <- exp(-tau (V + g|p|^2)) p, real time p <- exp(-i tau (V + g|p|^2)) p.
-template <int MODE, typename R, typename V>
-__device__ __forceinline__ V nstep(V v, R scale, R pot, R g, R tau) {
-  const R re = v.x * scale, im = v.y * scale;
-  const R w = fma(g, fma(re, re, im * im), pot);
-  if (MODE == 1) {
-    const R f = dexp(-tau * w);
-    return vmake<V>(f * re, f * im);
-  }
-  R sn, cs;
-  dsincos(-tau * w, &sn, &cs);
-  return vmake<V>(cs * re - sn * im, fma(cs, im, sn * re));
-}
-
-// Raw buffer access: an SGPR resource for the whole array, a 32-bit per-lane byte offset
-// (VGPR) and a uniform per-row byte offset (SGPR), so a strided line costs one VGPR of
-// addressing instead of a 64-bit address per element.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
-}
-typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
-typedef unsigned int u32x4 __attribute__((__vector_size__(16)));
-__device__ __forceinline__ void bload(float2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
-}
-__device__ __forceinline__ void bload(double2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
-}
-__device__ __forceinline__ void bstore(const float2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vo, (int)so, 0);
-}
-__device__ __forceinline__ void bstore(const double2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)vo, (int)so, 0);
-}
-
-template <typename V> __device__ __forceinline__ V shfl_up_v(V v, int off, int width) {
-  return vmake<V>(__shfl_up(v.x, off, width), __shfl_up(v.y, off, width));
-}
-template <typename V> __device__ __forceinline__ V shfl_down_v(V v, int off, int width) {
-  return vmake<V>(__shfl_down(v.x, off, width), __shfl_down(v.y, off, width));
-}
-
 // ---------------------------------------------------------------------------------------
-// Constant-pivot form of the solve.  The Thomas pivots of A = tridiag(-c, 1+2c, -c)
-// converge to gamma_inf = 1/(1 + 2c + c c'_inf), c'_inf the root of modulus < 1 of
-// c x^2 + (1+2c) x + c = 0.  Running the elimination with gamma_inf from the first row on
-// solves A' = A + kappa e_0 e_0^T, kappa = c c'_inf, exactly; the solution of A follows
-// from the Sherman-Morrison identity u = u' + omega u'_0 with
-// omega = kappa A'^{-1} e_0 / (1 - kappa (A'^{-1} e_0)_0), which decays like c'_inf^i,
-// so only the first nw points of a line are corrected (nw: last |omega_i| above the
-// storage precision's rounding level).  The sweeps therefore use three constants:
-//   a = c gamma_inf, b = (1-2c) gamma_inf (complex64 storage: b as an FP32 hi+lo pair)
-// and P = a^M, the product of a over a full segment.  Points past the end of a line
-// (padding of a last segment) are forced to zero in the backward recurrence, which is
-// all the exact solve needs (their forward values never reach a stored point).
-// ---------------------------------------------------------------------------------------
-template <typename V> struct Coef {
-  V a, b, bl;
-};
-
-// one forward-recurrence point: d = a (prev + next + d) + (b + b_lo) p
-template <bool CC, typename R, typename V>
-__device__ __forceinline__ V fwd_point(const Coef<V>& c, V prev, V nxt, V d, V p) {
-  const V sum = vadd(vadd(prev, nxt), d);
-  V dn = cmul<CC>(c.a, sum);
-  if (sizeof(R) == 4) dn = cfma<CC>(c.bl, p, dn);  // low part of b (complex64 storage)
-  return cfma<CC>(c.b, p, dn);
-}
-
-// ---------------------------------------------------------------------------------------
-// x / y sweep.  Block = ceil(nseg/SW) wavefronts; a wavefront holds SW segments of
-// LW = 64/SW consecutive lines (lane = segment-in-wave * LW + line).  Lines l of a block
-// are blockIdx.x*LW + [0, LW) (lanes past the last line repeat it: they compute and store
-// identical values); element i of line l sits at base(l) + i*inner.  Each thread holds M
-// consecutive points of one line in registers.  nwi > 0: the omega correction is applied
-// here (nwi <= M, so it stays inside segment 0); otherwise k_head_correction follows.
+// single-grid kernels (bodies in gp_device.h)
 // ---------------------------------------------------------------------------------------
 template <typename R, int M, int SW, bool CC, int NSTEP>
 __global__ void __launch_bounds__(1024)
@@ -240,321 +43,37 @@ k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, uint32_t psi_bytes, typena
               const typename VecOf<R>::T* __restrict__ omega, int nwi, int n, int nseg, int64_t nlines,
               int64_t inner, const R* __restrict__ vline, const R* __restrict__ vy, const R* __restrict__ vz, int nz,
               R tau, const DevState* __restrict__ st) {
-  typedef typename VecOf<R>::T V;
-  constexpr int LW = 64 / SW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int nslot = (int)(blockDim.x >> 6) * SW;  // segment slots in this block
-  V* sh_first = reinterpret_cast<V*>(smem_raw);  // reused for the backward exchange
-  V* sh_last = sh_first + nslot * LW;
-  V* sh_B = sh_last + nslot * LW;
-  V* sh_U = sh_first;
-
-  const int lane = threadIdx.x & 63;
-  const int li = lane % LW;
-  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int p = (SW == 1) ? w : w * SW + lane / LW;
-  const int64_t line = min((int64_t)blockIdx.x * LW + li, nlines - 1);
-  const int64_t base = (line / inner) * (inner * n) + (line % inner);
-  const int s = p * M;
-  const int len = max(0, min(M, n - s));
-  Coef<V> cf;
-  cf.a = ca;
-  cf.b = cb;
-  cf.bl = cbl;
-
-  const __amdgpu_buffer_rsrc_t rs = make_rsrc(psi, psi_bytes);
-  const uint32_t voff = (uint32_t)((base + (int64_t)s * inner) * (int64_t)sizeof(V));
-  const uint32_t srow = (uint32_t)(inner * (int64_t)sizeof(V));
-  V v[M];
-#pragma unroll
-  for (int t = 0; t < M; ++t) {
-    v[t] = vzero<V>();
-    if (t < len) bload(v[t], rs, voff, (uint32_t)t * srow);
-  }
+  R scale = 1, g = 0;
   if (NSTEP != 0) {
-    const R scale = (R)st->s;
-    const R g = (R)st->g;
-    const R vyz = vy[line / nz] + vz[line % nz];  // x-sweep line index = j*nz + k
-#pragma unroll
-    for (int t = 0; t < M; ++t) {
-      const int pos = min(s + t, n - 1);
-      v[t] = nstep<NSTEP, R, V>(v[t], scale, vline[pos] + vyz, g, tau);  // padding stays 0
-    }
+    scale = (R)st->s;
+    g = (R)st->g;
   }
-
-  // neighbours across segment boundaries (right-hand side of the first and last rows);
-  // a segment that ends early is the line's last, so nobody reads its last value
-  sh_first[p * LW + li] = v[0];
-  sh_last[p * LW + li] = v[M - 1];
-  __syncthreads();
-  const V left = (p > 0 && p < nseg) ? sh_last[(p - 1) * LW + li] : vzero<V>();
-  const V right = (p < nseg - 1) ? sh_first[(p + 1) * LW + li] : vzero<V>();
-
-  // forward recurrence over the segment from d_{s-1} = 0
-  {
-    V prev = left, d = vzero<V>();
-#pragma unroll
-    for (int t = 0; t < M; ++t) {
-      V nxt = right;
-      if (t + 1 < M) nxt = v[t + 1];
-      const V dn = fwd_point<CC, R, V>(cf, prev, nxt, d, v[t]);
-      prev = v[t];
-      v[t] = dn;
-      d = dn;
-    }
-    sh_B[p * LW + li] = d;
-  }
-  __syncthreads();
-  // incoming d_{s-1}: compose the earlier segments' maps D -> P D + B_q, then add
-  // a^(t+1) D_in as a running product
-  {
-    V D = vzero<V>();
-    for (int q = 0; q < p && q < nseg; ++q) D = cfma<CC>(cP, D, sh_B[q * LW + li]);
-    V r = D;
-#pragma unroll
-    for (int t = 0; t < M; ++t) {
-      r = cmul<CC>(ca, r);
-      v[t] = vadd(v[t], r);
-    }
-  }
-  // backward recurrence over the segment from u_e = 0 (u = 0 past the end of the line)
-  {
-    V u = vzero<V>();
-#pragma unroll
-    for (int t = M - 1; t >= 0; --t) {
-      u = cfma<CC>(ca, u, v[t]);
-      if (t >= len) u = vzero<V>();
-      v[t] = u;
-    }
-    sh_U[p * LW + li] = u;  // every halo read of sh_first precedes the barrier above
-  }
-  __syncthreads();
-  {
-    V U = vzero<V>();
-    for (int q = nseg - 1; q > p; --q) U = cfma<CC>(cP, U, sh_U[q * LW + li]);
-    V r = U;
-#pragma unroll
-    for (int t = M - 1; t >= 0; --t) {
-      r = cmul<CC>(ca, r);
-      v[t] = vadd(v[t], r);
-    }
-  }
-  // Sherman-Morrison head correction of segment 0
-  if (w == 0 && nwi > 0) {
-    const bool mine = (SW == 1) || (lane < LW);
-    const V u0 = v[0];
-#pragma unroll
-    for (int t = 0; t < M; ++t) {
-      if (t < nwi) {
-        const V c = cfma<CC>(omega[t], u0, v[t]);
-        if (mine) v[t] = c;
-      }
-    }
-  }
-
-#pragma unroll
-  for (int t = 0; t < M; ++t)
-    if (t < len) bstore(v[t], rs, voff, (uint32_t)t * srow);
+  lines_body<R, M, SW, CC, NSTEP>(psi, psi_bytes, ca, cb, cbl, cP, omega, nwi, n, nseg, nlines, inner, vline, vy, vz,
+                                  nz, tau, scale, g, blockIdx.x, smem_raw);
 }
 
-// Sherman-Morrison head correction u_i += omega_i u_0, i < nw, one thread per line, for
-// x/y lines when the correction reaches past the first segment (large c).  Lines as in
-// k_sweep_lines.
-template <typename R, bool CC>
-__global__ void __launch_bounds__(256)
-k_head_correction(typename VecOf<R>::T* __restrict__ psi, const typename VecOf<R>::T* __restrict__ omega, int nw,
-                  int n, int64_t nlines, int64_t inner) {
-  typedef typename VecOf<R>::T V;
-  for (int64_t line = (int64_t)blockIdx.x * 256 + threadIdx.x; line < nlines; line += (int64_t)gridDim.x * 256) {
-    const int64_t base = (line / inner) * (inner * n) + (line % inner);
-    const V u0 = psi[base];
-    for (int i = nw - 1; i >= 0; --i) psi[base + i * inner] = cfma<CC>(omega[i], u0, psi[base + i * inner]);
-  }
-}
-
-// ---------------------------------------------------------------------------------------
-// z sweep.  Block = 4 wavefronts; a wavefront holds L = 64/nseg z lines, lane =
-// line-in-wave * nseg + segment, MZ points per thread.  Each iteration copies 4L
-// consecutive lines (contiguous in memory) into LDS, solves them, and copies them back.
-// The omega correction runs here (any nw), u'_0 broadcast along the line by a shuffle.
-// ---------------------------------------------------------------------------------------
 template <typename R, int MZ, bool CC, bool NORM, int EPI>
 __global__ void __launch_bounds__(256)
 k_sweep_z(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typename VecOf<R>::T cb,
           typename VecOf<R>::T cbl, typename VecOf<R>::T cP, const typename VecOf<R>::T* __restrict__ omega, int nwi,
           int nz, int nseg, int64_t nlines, double* __restrict__ partials, const R* __restrict__ vx,
           const R* __restrict__ vy, const R* __restrict__ vz, int ny, R tau, const DevState* __restrict__ st) {
-  typedef typename VecOf<R>::T V;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  V* sdata = reinterpret_cast<V*>(smem_raw);
   __shared__ double red[4];
-
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int L = 64 / nseg;
-  const int l = lane / nseg, p = lane % nseg;
-  const int lines_per_grp = 4 * L;
-  const int64_t ngrp = (nlines + lines_per_grp - 1) / lines_per_grp;
-  const int s = p * MZ;
-  const int len = max(0, min(MZ, nz - s));
-  Coef<V> cf;
-  cf.a = ca;
-  cf.b = cb;
-  cf.bl = cbl;
   R g = 0;
   if (EPI != 0) g = (R)st->g;
-  double acc = 0.0;
-
-  for (int64_t grp = blockIdx.x; grp < ngrp; grp += gridDim.x) {
-    const int64_t line0 = grp * lines_per_grp;
-    const int nl = (int)min((int64_t)lines_per_grp, nlines - line0);
-    const int cnt = nl * nz;
-    const V* src = psi + line0 * nz;
-    if (sizeof(V) == 8 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {  // 16-byte copies
-      const float4* s4 = reinterpret_cast<const float4*>(src);
-      float4* d4 = reinterpret_cast<float4*>(sdata);
-      for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];
-    } else {
-      for (int q = tid; q < cnt; q += 256) sdata[q] = src[q];
-    }
-    __syncthreads();
-
-    const int ll = w * L + l;
-    const bool act = (ll < nl) && (len > 0);
-    V* row = sdata + (act ? ll * nz : 0);
-    V v[MZ];
-#pragma unroll
-    for (int t = 0; t < MZ; ++t) {
-      v[t] = vzero<V>();
-      if (act && t < len) v[t] = row[s + t];
-    }
-    const V left = (act && s > 0) ? row[s - 1] : vzero<V>();
-    const V right = (act && s + len < nz) ? row[s + len] : vzero<V>();
-
-    V d = vzero<V>();
-    {
-      V prev = left;
-#pragma unroll
-      for (int t = 0; t < MZ; ++t) {
-        V nxt = right;
-        if (t + 1 < MZ) nxt = v[t + 1];
-        const V dn = fwd_point<CC, R, V>(cf, prev, nxt, d, v[t]);
-        prev = v[t];
-        v[t] = dn;
-        d = dn;
-      }
-    }
-    // inclusive scan of the segment maps x -> P x + B along the line.  Every segment
-    // before an active lane is full, so a span of `off` segments multiplies by P^off:
-    // the products are powers of P and only B travels between lanes.
-    V B = act ? d : vzero<V>();
-    {
-      V Apow = cP;
-      for (int off = 1; off < nseg; off <<= 1) {
-        const V Bp = shfl_up_v(B, off, nseg);
-        if (p >= off) B = cfma<CC>(Apow, Bp, B);
-        Apow = cmul<CC>(Apow, Apow);
-      }
-    }
-    V D = shfl_up_v(B, 1, nseg);
-    if (p == 0) D = vzero<V>();
-    {
-      V r = D;
-#pragma unroll
-      for (int t = 0; t < MZ; ++t) {
-        r = cmul<CC>(ca, r);
-        v[t] = vadd(v[t], r);
-      }
-    }
-    V u = vzero<V>();
-#pragma unroll
-    for (int t = MZ - 1; t >= 0; --t) {
-      u = cfma<CC>(ca, u, v[t]);
-      if (t >= len) u = vzero<V>();
-      v[t] = u;
-    }
-    // backward scan likewise; a span reaching into the empty lanes past the line's last
-    // segment gets P^off instead of the true product, but it only ever multiplies the
-    // zero contribution of those lanes
-    V Bu = act ? u : vzero<V>();
-    {
-      V Apow = cP;
-      for (int off = 1; off < nseg; off <<= 1) {
-        const V Bp = shfl_down_v(Bu, off, nseg);
-        if (p + off < nseg) Bu = cfma<CC>(Apow, Bp, Bu);
-        Apow = cmul<CC>(Apow, Apow);
-      }
-    }
-    V U = shfl_down_v(Bu, 1, nseg);
-    if (p == nseg - 1) U = vzero<V>();
-    {
-      V r = U;
-#pragma unroll
-      for (int t = MZ - 1; t >= 0; --t) {
-        r = cmul<CC>(ca, r);
-        v[t] = vadd(v[t], r);
-      }
-    }
-    // Sherman-Morrison head correction: u_i += omega_i u_0 for i < nwi
-    if (nwi > 0) {
-      const V u0 = vmake<V>(__shfl(v[0].x, l * nseg, 64), __shfl(v[0].y, l * nseg, 64));
-#pragma unroll
-      for (int t = 0; t < MZ; ++t) {
-        if (t < nwi) {  // uniform: segment-0 lanes need it whenever t < nwi
-          const int pos = s + t;
-          const V om = omega[min(pos, nwi - 1)];
-          const V c = cfma<CC>(om, u0, v[t]);
-          if (pos < nwi) v[t] = c;
-        }
-      }
-    }
-
-    if (act) {
-      R vxy = 0;
-      if (EPI != 0) {
-        const int64_t zl = line0 + ll;  // z line index = i*ny + j
-        vxy = vx[zl / ny] + vy[zl % ny];
-      }
-#pragma unroll
-      for (int t = 0; t < MZ; ++t) {
-        if (t < len) {
-          if (EPI != 0) v[t] = nstep<EPI, R, V>(v[t], (R)1, vxy + vz[s + t], g, tau);
-          if (NORM) acc = fma((double)v[t].x, (double)v[t].x, fma((double)v[t].y, (double)v[t].y, acc));
-          row[s + t] = v[t];
-        }
-      }
-    }
-    __syncthreads();
-    V* dst = psi + line0 * nz;
-    if (sizeof(V) == 8 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {
-      float4* d4 = reinterpret_cast<float4*>(dst);
-      const float4* s4 = reinterpret_cast<const float4*>(sdata);
-      for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];
-    } else {
-      for (int q = tid; q < cnt; q += 256) dst[q] = sdata[q];
-    }
-    __syncthreads();
-  }
+  const double acc = z_body<R, MZ, CC, NORM, EPI>(psi, ca, cb, cbl, cP, omega, nwi, nz, nseg, nlines, vx, vy, vz, ny,
+                                                  tau, g, blockIdx.x, gridDim.x, smem_raw);
   if (NORM) {
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) red[w] = acc;
-    __syncthreads();
-    if (tid == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    const double t = block_sum_256(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
   }
 }
 
 // ---------------------------------------------------------------------------------------
 // reductions and small kernels
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum_256(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  const double r = (red[0] + red[1]) + (red[2] + red[3]);
-  __syncthreads();
-  return r;
-}
-
 __global__ void __launch_bounds__(256)
 k_finalize_norm(const double* __restrict__ partials, int nb, double dV, double dt, DevState* st) {
   __shared__ double red[4];

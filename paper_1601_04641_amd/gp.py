@@ -25,7 +25,12 @@ GP_FLAG_NONFINITE, GP_FLAG_ZERO_NORM = 1, 2
 EXPORTS = ("gp_init", "gp_destroy", "gp_step_imag", "gp_step_real", "gp_norm", "gp_energy_mu",
            "gp_rms", "gp_raw_sums", "gp_set_g", "gp_set_psi", "gp_status", "gp_converge_imag",
            "gp_set_timing", "gp_get_timing", "gp_get_mapping", "gp_set_mapping", "gp_autotune",
-           "gp_strerror", "gp_last_error")
+           "gp_strerror", "gp_last_error",
+           "gp_batch_init", "gp_batch_destroy", "gp_batch_step_imag", "gp_batch_step_real",
+           "gp_batch_norm", "gp_batch_energy_mu", "gp_batch_rms", "gp_batch_raw_sums",
+           "gp_batch_status", "gp_batch_converge_imag", "gp_batch_get_mapping",
+           "gp_batch_set_mapping", "gp_batch_autotune", "gp_batch_set_timing",
+           "gp_batch_get_timing", "gp_batch_last_error")
 
 
 class GPError(RuntimeError):
@@ -76,6 +81,21 @@ def load(path: str = LIB_PATH):
         "gp_get_mapping": [vp, P(i32)],
         "gp_set_mapping": [vp, P(i32)],
         "gp_autotune": [vp, i32, i32, ctypes.c_char_p, P(i32)],
+        "gp_batch_init": [P(gp_params), i32, vp, P(i64), vp, P(vp)],
+        "gp_batch_destroy": [vp],
+        "gp_batch_step_imag": [vp, i32, vp],
+        "gp_batch_step_real": [vp, i32, vp],
+        "gp_batch_norm": [vp, P(d)],
+        "gp_batch_energy_mu": [vp, P(d), P(d)],
+        "gp_batch_rms": [vp, P(d)],
+        "gp_batch_raw_sums": [vp, P(d)],
+        "gp_batch_status": [vp, P(i64), P(d), P(i32)],
+        "gp_batch_converge_imag": [vp, d, i32, i64, P(i64), P(d), P(i32)],
+        "gp_batch_get_mapping": [vp, P(i32)],
+        "gp_batch_set_mapping": [vp, P(i32)],
+        "gp_batch_autotune": [vp, i32, i32, P(i32)],
+        "gp_batch_set_timing": [vp, i32],
+        "gp_batch_get_timing": [vp, P(d), P(i64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -85,6 +105,8 @@ def load(path: str = LIB_PATH):
     L.gp_strerror.restype = ctypes.c_char_p
     L.gp_last_error.argtypes = [vp]
     L.gp_last_error.restype = ctypes.c_char_p
+    L.gp_batch_last_error.argtypes = [vp]
+    L.gp_batch_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -219,6 +241,134 @@ class Solver:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._L.gp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Batch:
+    """One gp_batch over a caller-owned 1D complex torch tensor holding every instance's
+    grid back to back (instance i: elements offsets[i] .. offsets[i] + nx*ny*nz)."""
+
+    def __init__(self, psi, params, offsets, split=GP_SPLIT_LIE, stream=None):
+        import torch
+        if not psi.is_cuda or not psi.is_contiguous() or psi.dim() != 1:
+            raise ValueError("psi must be a contiguous 1D device tensor")
+        prec = GP_C128 if psi.dtype == torch.complex128 else GP_C64 if psi.dtype == torch.complex64 else None
+        if prec is None:
+            raise ValueError("psi must be complex64 or complex128")
+        self.n = len(params)
+        arr = (gp_params * self.n)()
+        for i, w in enumerate(params):
+            arr[i] = make_params(w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"],
+                                 w["nuz"], w["g"], w["dt"], prec, split)
+        self._params = arr
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.psi = psi
+        self.stream = stream if stream is not None else torch.cuda.current_stream(psi.device)
+        self._L = load()
+        h = ctypes.c_void_p()
+        with torch.cuda.device(psi.device):
+            rc = self._L.gp_batch_init(arr, self.n, ctypes.c_void_p(psi.data_ptr()),
+                                       self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != GP_OK:
+            raise GPError(rc, "gp_batch_init")
+        self._h = h
+
+    def _chk(self, rc, name):
+        if rc != GP_OK:
+            raise GPError(rc, name, self._L.gp_batch_last_error(self._h).decode(errors="replace"))
+
+    def _act(self, active):
+        if active is None:
+            return None
+        a = np.ascontiguousarray(active, dtype=np.uint8)
+        self._active_keep = a
+        return a.ctypes.data_as(ctypes.c_void_p)
+
+    def step_imag(self, n, active=None):
+        self._chk(self._L.gp_batch_step_imag(self._h, int(n), self._act(active)), "gp_batch_step_imag")
+
+    def step_real(self, n, active=None):
+        self._chk(self._L.gp_batch_step_real(self._h, int(n), self._act(active)), "gp_batch_step_real")
+
+    def norm(self):
+        out = np.zeros(self.n)
+        self._chk(self._L.gp_batch_norm(self._h, _dp(out)), "gp_batch_norm")
+        return out
+
+    def energy_mu(self):
+        e, m = np.zeros(self.n), np.zeros(self.n)
+        self._chk(self._L.gp_batch_energy_mu(self._h, _dp(e), _dp(m)), "gp_batch_energy_mu")
+        return e, m
+
+    def rms(self):
+        out = np.zeros(4 * self.n)
+        self._chk(self._L.gp_batch_rms(self._h, _dp(out)), "gp_batch_rms")
+        return out.reshape(self.n, 4)
+
+    def raw_sums(self):
+        out = np.zeros(9 * self.n)
+        self._chk(self._L.gp_batch_raw_sums(self._h, _dp(out)), "gp_batch_raw_sums")
+        return out.reshape(self.n, 9)
+
+    def status(self):
+        s = np.zeros(self.n, dtype=np.int64)
+        m = np.zeros(self.n)
+        f = np.zeros(self.n, dtype=np.int32)
+        self._chk(self._L.gp_batch_status(self._h, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(m),
+                                          f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "gp_batch_status")
+        return s, m, f
+
+    def converge_imag(self, tol=1e-7, check_every=0, max_steps=10 ** 6):
+        s = np.zeros(self.n, dtype=np.int64)
+        m = np.zeros(self.n)
+        c = np.zeros(self.n, dtype=np.int32)
+        self._chk(self._L.gp_batch_converge_imag(self._h, float(tol), int(check_every), int(max_steps),
+                                                 s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(m),
+                                                 c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+                  "gp_batch_converge_imag")
+        return s, m, c.astype(bool)
+
+    def get_mapping(self):
+        out = (ctypes.c_int32 * 5)()
+        self._chk(self._L.gp_batch_get_mapping(self._h, out), "gp_batch_get_mapping")
+        return list(out)
+
+    def set_mapping(self, mx=0, swx=0, my=0, swy=0, mz=0):
+        arr = (ctypes.c_int32 * 5)(int(mx), int(swx), int(my), int(swy), int(mz))
+        self._chk(self._L.gp_batch_set_mapping(self._h, arr), "gp_batch_set_mapping")
+
+    def autotune(self, mode="imag", steps=4):
+        out = (ctypes.c_int32 * 5)()
+        self._chk(self._L.gp_batch_autotune(self._h, 0 if mode == "imag" else 1, int(steps), out),
+                  "gp_batch_autotune")
+        return list(out)
+
+    def set_timing(self, on):
+        self._chk(self._L.gp_batch_set_timing(self._h, int(bool(on))), "gp_batch_set_timing")
+
+    def get_timing(self):
+        ms = np.zeros(5)
+        n = np.zeros(5, dtype=np.int64)
+        self._chk(self._L.gp_batch_get_timing(self._h, _dp(ms), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+                  "gp_batch_get_timing")
+        return ms, n
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.gp_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -1,0 +1,197 @@
+"""GPU tests of the batched form: uneven instances advanced by the same launches.
+
+Each instance is checked against the CPU FP64 oracle and against a single-grid context
+given the same line mapping (real time: bitwise identical; imaginary time differs only in
+the grouping of the FP64 norm sums).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_04641_amd import gp, inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gp.load()
+    yield
+
+
+def instances():
+    """Uneven grids, traps, g and dt (dims include non-multiples of 8)."""
+    out = []
+    shapes = [(32, 40, 48), (96, 80, 64), (45, 33, 70), (64, 64, 32), (17, 90, 21), (72, 48, 96)]
+    rng = np.random.default_rng(3)
+    for k, (nx, ny, nz) in enumerate(shapes):
+        d = 0.2 if k % 2 == 0 else 0.17
+        out.append(dict(nx=nx, ny=ny, nz=nz, dx=d, dy=d * 1.1, dz=d * 0.9, nux=float(rng.uniform(0.5, 4)),
+                        nuy=float(rng.uniform(0.5, 4)), nuz=float(rng.uniform(0.5, 4)),
+                        g=float(np.exp(rng.uniform(0, np.log(1000)))), dt=0.1 * d * d))
+    return out
+
+
+def pack(ws, prec, seed=0):
+    """Seeded generic initial states packed back to back; returns (host states, offsets)."""
+    states, offs, off = [], [], 0
+    for i, w in enumerate(ws):
+        s = inputs.perturbed_psi(w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"], w["nuz"],
+                                 seed=seed + i, amp=0.2)
+        if prec == gp.GP_C64:
+            s = s.astype(np.complex64).astype(np.complex128)
+        states.append(s)
+        offs.append(off)
+        off += s.size
+    return states, np.array(offs, dtype=np.int64), off
+
+
+def to_dev(states, total, prec):
+    dt = torch.complex64 if prec == gp.GP_C64 else torch.complex128
+    flat = np.concatenate([s.reshape(-1) for s in states])
+    assert flat.size == total
+    return torch.from_numpy(flat).to(device="cuda", dtype=dt)
+
+
+def unpack(psi, ws, offs):
+    h = psi.cpu().numpy().astype(np.complex128)
+    return [h[o:o + w["nx"] * w["ny"] * w["nz"]].reshape(w["nx"], w["ny"], w["nz"]) for w, o in zip(ws, offs)]
+
+
+def c64_tolerance(w, s0, ref, imag, steps=20):
+    """complex64 tolerance from the problem's own conditioning: the oracle is rerun from
+    the initial state perturbed by FP32-sized relative noise (6e-8); the FP32 path commits
+    such an error at every step, so 40x the resulting deviation (floor 5e-6) bounds it.
+    Strongly nonlinear real-time cases (g ~ 10^3) amplify input noise ~70x in 20 steps."""
+    rng = np.random.default_rng(12345)
+    o = oracle.Oracle.from_params(w, s0 * (1 + 6e-8 * rng.standard_normal(s0.shape)))
+    (o.step_imag if imag else o.step_real)(steps)
+    sens = float(np.max(np.abs(o.psi - ref)) / np.max(np.abs(ref)))
+    return max(5e-6, 40 * sens)
+
+
+@pytest.mark.parametrize("prec", [gp.GP_C64, gp.GP_C128])
+@pytest.mark.parametrize("imag", [True, False])
+def test_batch_matches_oracle_per_instance(prec, imag):
+    ws = instances()
+    states, offs, total = pack(ws, prec)
+    psi = to_dev(states, total, prec)
+    say(f"case: batch of {len(ws)} prec {prec} imag {imag}")
+    with gp.Batch(psi, ws, offs) as b:
+        (b.step_imag if imag else b.step_real)(20)
+        torch.cuda.synchronize()
+        outs = unpack(psi, ws, offs)
+        raw = b.raw_sums()
+    for i, (w, s0, out) in enumerate(zip(ws, states, outs)):
+        o = oracle.Oracle.from_params(w, s0)
+        (o.step_imag if imag else o.step_real)(20)
+        err = float(np.max(np.abs(out - o.psi)) / np.max(np.abs(o.psi)))
+        tol = 1e-12 if prec == gp.GP_C128 else c64_tolerance(w, s0, o.psi, imag)
+        say(f"  instance {i} {w['nx']}x{w['ny']}x{w['nz']} g {w['g']:.1f}: rel err {err:.2e} (tol {tol:.1e})")
+        assert err <= tol
+        want = oracle.Oracle.from_params(w, out).raw_sums()
+        assert np.max(np.abs(raw[i] - want) / np.abs(want)) <= 1e-12
+
+
+def test_batch_real_time_bitwise_equals_single_grid_with_same_mapping():
+    ws = instances()
+    prec = gp.GP_C64
+    states, offs, total = pack(ws, prec, seed=10)
+    psi = to_dev(states, total, prec)
+    with gp.Batch(psi, ws, offs) as b:
+        mx, swx, my, swy, mz = b.get_mapping()
+        b.step_real(7)
+        torch.cuda.synchronize()
+        outs = unpack(psi, ws, offs)
+    for w, s0, out in zip(ws, states, outs):
+        seg = 2
+        while seg < 64 and seg * mz < w["nz"]:
+            seg *= 2
+        single = to_dev([s0], s0.size, prec).reshape(w["nx"], w["ny"], w["nz"])
+        with gp.Solver.from_workload(single, w) as s:
+            s.set_mapping(mx, swx, my, swy, seg, mz)
+            s.step_real(7)
+            torch.cuda.synchronize()
+        assert np.array_equal(single.cpu().numpy().astype(np.complex128), out)
+
+
+def test_batch_masking_leaves_inactive_instances_untouched():
+    ws = instances()
+    prec = gp.GP_C64
+    states, offs, total = pack(ws, prec, seed=20)
+    psi = to_dev(states, total, prec)
+    active = np.array([1, 0, 1, 0, 1, 1], dtype=np.uint8)
+    with gp.Batch(psi, ws, offs) as b:
+        b.step_imag(5, active=active)
+        b.step_real(3)                      # stays masked: same instances untouched
+        torch.cuda.synchronize()
+        outs = unpack(psi, ws, offs)
+        steps, _, flags = b.status()
+    for i in range(len(ws)):
+        if active[i]:
+            assert not np.array_equal(outs[i], states[i])
+            assert steps[i] == 8
+        else:
+            assert np.array_equal(outs[i], states[i])
+            assert steps[i] == 0
+    assert np.all(flags == 0)
+
+
+def test_batch_converges_each_instance():
+    ws = [dict(w, g=min(w["g"], 50.0)) for w in instances()[:4]]
+    prec = gp.GP_C128
+    states = [inputs.gaussian_psi(w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"], w["nuz"])
+              for w in ws]
+    offs = np.cumsum([0] + [s.size for s in states[:-1]]).astype(np.int64)
+    psi = to_dev(states, sum(s.size for s in states), prec)
+    with gp.Batch(psi, ws, offs) as b:
+        steps, mu, conv = b.converge_imag(tol=1e-8, check_every=50, max_steps=20000)
+    say(f"steps {steps}, mu {mu}")
+    assert np.all(conv)
+    for w, s0, n, m in zip(ws, states, steps, mu):
+        o = oracle.Oracle.from_params(w, s0)
+        o.step_imag(int(n))
+        assert abs(o.energy_mu()[1] - m) <= 1e-10 * abs(m)
+
+
+def test_batch_autotune_restores_state():
+    ws = instances()
+    prec = gp.GP_C64
+    states, offs, total = pack(ws, prec, seed=30)
+    psi = to_dev(states, total, prec)
+    before = psi.cpu().numpy()
+    with gp.Batch(psi, ws, offs) as b:
+        m = b.autotune("imag", steps=2)
+        assert m == b.get_mapping()
+        assert np.array_equal(psi.cpu().numpy(), before)
+        assert np.all(b.status()[0] == 0)
+        b.step_imag(3)
+        torch.cuda.synchronize()
+        outs = unpack(psi, ws, offs)
+    for w, s0, out in zip(ws, states, outs):
+        o = oracle.Oracle.from_params(w, s0)
+        o.step_imag(3)
+        assert float(np.max(np.abs(out - o.psi)) / np.max(np.abs(o.psi))) <= 5e-6
+
+
+def test_batch_rejects_bad_arguments():
+    ws = instances()[:2]
+    states, offs, total = pack(ws, gp.GP_C64)
+    psi = to_dev(states, total, gp.GP_C64)
+    bad = [dict(ws[0], nx=2), ws[1]]
+    with pytest.raises(gp.GPError):
+        gp.Batch(psi, bad, offs)
+    with gp.Batch(psi, ws, offs) as b:
+        with pytest.raises(gp.GPError):
+            b.set_mapping(mx=5)
+        with pytest.raises(gp.GPError):
+            b.set_mapping(mz=7)
