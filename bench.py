@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--batch-n", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--batch-serial-steps", type=int, default=400)
     return ap.parse_args()
 
 
@@ -99,6 +103,75 @@ def run_precision(torch, gp, inputs, w, prec, args):
                                     algorithmic_GBps=2 * esz * npts / (ms[k] * 1e-3) / 1e9)
     return dict(npts=npts, wall=wall, ms=ms, n=n, per_kernel=per_kernel, esz=esz,
                 norm_drift=abs(n1 - n0) / n0, rms=rms.tolist(), mapping=mapping)
+
+
+def run_batch(torch, gp, inputs, args):
+    """Batched form: 256 instances drawn by inputs.draw_batch(seed 0) (dims over
+    {32, 40, ..., 96} per axis, dx = 0.2, nu ~ U[0.5, 4]^3, g log-uniform [1, 1000],
+    dt = 0.004), complex64 with FP64 reductions, Gaussian starts, `batch_steps`
+    imaginary-time steps through the batched launches (graph-captured), against the
+    same instances advanced one after another by single-grid contexts."""
+    ws = inputs.draw_batch(0, args.batch_n)
+    sizes = [w["nx"] * w["ny"] * w["nz"] for w in ws]
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    total = int(sum(sizes))
+    host = np.empty(total, dtype=np.complex64)
+    for w, o, n in zip(ws, offs, sizes):
+        host[o:o + n] = inputs.gaussian_psi(w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"], w["nux"],
+                                            w["nuy"], w["nuz"], dtype=np.complex64).reshape(-1)
+    psi0 = torch.from_numpy(host).to("cuda")
+    del host
+    psi = psi0.clone()
+    b = gp.Batch(psi, ws, offs)
+    tuned = None
+    if not args.no_autotune:
+        tuned = b.autotune("imag", steps=4)
+        log(f"[bench] batch autotune: {tuned}")
+    b.step_imag(args.warmup)
+    torch.cuda.synchronize()
+    log(f"[bench] batch timed: {args.batch_steps} imaginary steps, {len(ws)} instances, {total} points")
+    t0 = time.perf_counter()
+    b.step_imag(args.batch_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    e, mu = b.energy_mu()
+    # per-kernel durations in a short separate eager run
+    b.set_timing(True)
+    b.step_imag(20)
+    ms, nl = b.get_timing()
+    b.set_timing(False)
+    mapping = b.get_mapping()
+    b.close()
+    # serial per-instance launches: one single-grid context per instance, default mapping
+    psi.copy_(psi0)
+    views = [psi[o:o + n].view(w["nx"], w["ny"], w["nz"]) for w, o, n in zip(ws, offs, sizes)]
+    solvers = [gp.Solver.from_workload(v, w) for v, w in zip(views, ws)]
+    for s in solvers:
+        s.step_imag(args.warmup)
+    torch.cuda.synchronize()
+    log(f"[bench] serial timed: {args.batch_serial_steps} imaginary steps per instance")
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step_imag(args.batch_serial_steps)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    for s in solvers:
+        s.close()
+    del psi, psi0, views
+    torch.cuda.empty_cache()
+    rate_b = total * args.batch_steps / wall
+    rate_s = total * args.batch_serial_steps / wall_s
+    kern = {}
+    for k, name in enumerate(KINDS[:4]):
+        if nl[k]:
+            kern[name] = dict(ms=float(ms[k]), launches=int(nl[k]),
+                              algorithmic_GBps=(2 * 8 * total / (ms[k] * 1e-3) / 1e9) if k < 3 else None)
+    return {"workload": f"batch{len(ws)}_imag_dims32-96_dx0.2_seed0", "instances": len(ws), "points": total,
+            "steps": args.batch_steps, "value": rate_b, "unit": "grid-point updates/s",
+            "ms_per_step": wall / args.batch_steps * 1e3, "serial_value": rate_s,
+            "serial_steps": args.batch_serial_steps, "speedup_vs_serial": rate_b / rate_s,
+            "algorithmic_frac_of_hbm_peak": rate_b * 3 * 2 * 8 / PEAK_HBM, "mapping": mapping,
+            "kernels": kern, "mu_range": [float(np.min(mu)), float(np.max(mu))]}
 
 
 def cpu_baseline(inputs, w, seconds):
@@ -192,6 +265,8 @@ def main():
         r = res[gp.GP_C128]
         out["complex128"] = {"value": r["npts"] * K / r["wall"], "ms_per_step": r["wall"] / K * 1e3,
                              "kernels": r["per_kernel"], "norm_drift": r["norm_drift"]}
+    if not args.no_batch:
+        out["batched"] = run_batch(torch, gp, inputs, args)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(inputs, w, args.cpu_seconds)
