@@ -1,0 +1,67 @@
+"""Precision form on the 384^3 workload (dx = 0.08, trap and g drawn by seed 0):
+complex64 storage and FP32 sweeps with FP64 reductions, and the complex128 path, both
+compared with the FP64 CPU oracle over steps from a shared partly converged state (the
+oracle cannot afford the full 20000-step run at 5.7e7 points inside a test)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_04641_amd import gp, inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N, DX = 384, 0.08
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def shared_state():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gp.load()
+    (nux, nuy, nuz), g = inputs.draw_trap(0)
+    w = dict(nx=N, ny=N, nz=N, dx=DX, dy=DX, dz=DX, nux=nux, nuy=nuy, nuz=nuz, g=g, dt=0.1 * DX * DX)
+    say(f"case: precision 384^3 seed 0, g {g:.3f}: 1500 complex128 imaginary steps on the GPU")
+    psi = torch.from_numpy(inputs.gaussian_psi(N, N, N, DX, DX, DX, nux, nuy, nuz)).to("cuda")
+    with gp.Solver.from_workload(psi, w) as s:
+        s.step_imag(1500)
+        torch.cuda.synchronize()
+    host = psi.cpu().numpy()
+    del psi
+    torch.cuda.empty_cache()
+    say("  oracle: 10 imaginary steps")
+    t0 = time.time()
+    o = oracle.Oracle.from_params(w, host)
+    o.step_imag(10)
+    e, mu = o.energy_mu()
+    say(f"  oracle done ({time.time() - t0:.1f} s), mu {mu:.12f}")
+    yield w, host, o.psi.copy(), e, mu
+    o.close()
+
+
+@pytest.mark.parametrize("prec", [gp.GP_C128, gp.GP_C64])
+def test_precision_form_384_against_oracle(shared_state, prec):
+    w, host, ref, e_ref, mu_ref = shared_state
+    dt = torch.complex64 if prec == gp.GP_C64 else torch.complex128
+    psi = torch.from_numpy(host).to("cuda", dtype=dt)
+    with gp.Solver.from_workload(psi, w) as s:
+        s.step_imag(10)
+        e, mu = s.energy_mu()
+        out = psi.cpu().numpy().astype(np.complex128)
+    del psi
+    torch.cuda.empty_cache()
+    err = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
+    mu_rel, e_rel = abs(mu - mu_ref) / abs(mu_ref), abs(e - e_ref) / abs(e_ref)
+    say(f"  prec {prec}: max|dpsi|/max|psi| {err:.2e}, mu rel {mu_rel:.2e}, E rel {e_rel:.2e}")
+    if prec == gp.GP_C128:
+        assert err <= 1e-12 and mu_rel <= 1e-12 and e_rel <= 1e-12
+    else:
+        # the precision-form targets: 1e-5 relative mu, 1e-4 max|dpsi| (relative to max|psi|)
+        assert err <= 1e-5 and mu_rel <= 1e-6 and e_rel <= 1e-6
