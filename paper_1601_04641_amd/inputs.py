@@ -92,3 +92,30 @@ def draw_batch(seed: int, n: int, dims=tuple(range(32, 97, 8)), dx=0.2):
         out.append(dict(nx=nx, ny=ny, nz=nz, dx=dx, dy=dx, dz=dx, nux=float(nu[0]),
                         nuy=float(nu[1]), nuz=float(nu[2]), g=float(g), dt=0.1 * dx * dx))
     return out
+
+
+def nn_init_weights(shapes, seed: int):
+    """Initial network weights for a list of (name, shape): uniform He-style for weight
+    tensors (fan-in = last dim, x27 for 3D convolution kernels named 'C...'), zero for
+    biases (names starting with 'b' or 'c') and for the head ('wh', 'bh'), so that an
+    untrained network returns exactly its analytic prior."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for name, shp in shapes:
+        if name in ("wh", "bh") or name[0] in "bc":
+            out[name] = np.zeros(shp)
+            continue
+        fan_in = shp[-1] * (27 if name[0] == "C" else 1)
+        lim = math.sqrt(6.0 / fan_in)
+        out[name] = rng.uniform(-lim, lim, size=shp)
+    return out
+
+
+def draw_nn_params(seed: int, n: int):
+    """n problems (nu_x, nu_y, nu_z, g) distributed as the batched workload:
+    nu ~ U[0.5, 4]^3, g log-uniform on [1, 1000]."""
+    rng = np.random.default_rng(seed)
+    nu = rng.uniform(0.5, 4.0, size=(n, 3))
+    g = np.exp(rng.uniform(0.0, math.log(1000.0), size=(n, 1)))
+    return np.concatenate([nu, g], axis=1)
+
