@@ -153,6 +153,13 @@ int gp_batch_energy_mu(gp_batch* b, double* energy, double* mu);
 int gp_batch_rms(gp_batch* b, double* rms4);
 int gp_batch_raw_sums(gp_batch* b, double* raw);
 int gp_batch_status(gp_batch* b, int64_t* steps_done, double* mu_est, int32_t* flags);
+/* Residual of the stationary equation for the normalised state phi = psi / sqrt(N):
+ * res[i] = || H[phi] phi - mu phi || with H[phi] = -1/2 lap_h + V + g |phi|^2 (lap_h the
+ * 3-point Laplacian with zero ghosts, the operator whose energy gp_batch_energy_mu
+ * evaluates), mu = <phi, H[phi] phi> (returned in mu, nullable), norms dx dy dz sum|.|^2.
+ * Zero exactly at a discrete ground state; used to judge a starting state before
+ * imaginary-time propagation.  Synchronises. */
+int gp_batch_residual(gp_batch* b, double* res, double* mu);
 /* Imaginary time until every instance meets |mu_n - mu_{n-K}| <= tol |mu_n| (checked
  * every K steps, K <= 0 selects ceil(0.25/min dt)); converged instances are masked off
  * while the rest continue.  Per-instance steps taken, final mu and converged flag. */

@@ -9,12 +9,13 @@ import os
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgpsscn.so")
-SOURCES = ["gp_kernels.hip", "gp_batch.hip", "gp_api.cpp"]
+SOURCES = ["gp_kernels.hip", "gp_batch.hip", "gp_api.cpp", "gpnn.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -24,16 +25,16 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
     with tempfile.TemporaryDirectory(prefix="gpsscn_") as tmp:
-        for src in SOURCES:
-            obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
-            lang = ["-x", "hip"]
-            cmd = [HIPCC, *lang, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-            if verbose:
+        objs = [os.path.join(tmp, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+        cmds = [[HIPCC, "-x", "hip", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+                for src, obj in zip(SOURCES, objs)]
+        if verbose:
+            for cmd in cmds:
                 print(" ".join(cmd), flush=True)
-            subprocess.run(cmd, check=True)
-            objs.append(obj)
+        with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+            for f in [ex.submit(subprocess.run, cmd, check=True) for cmd in cmds]:
+                f.result()
         out = LIB + ".tmp"
         cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out]
         subprocess.run(cmd, check=True)

@@ -34,6 +34,7 @@ struct BInst {
   int zb0, zb1;          // z-sweep blocks of this instance (norm partials)
   int ob0, ob1;          // observables / scale blocks of this instance
   double dt, dV;
+  double id2[3];         // 1 / dx^2, 1 / dy^2, 1 / dz^2
   double coef[2][3][8];  // a, b, b_lo, P as (re, im) [imag, real][axis]
 };
 
@@ -235,6 +236,73 @@ kb_obs_final(const double* __restrict__ partials, const BInst* __restrict__ inst
     for (int q = I.ob0 + threadIdx.x; q < I.ob1; q += 256) acc += partials[(int64_t)q * 9 + c];
     const double t = block_sum_256(acc, red);
     if (threadIdx.x == 0) out[(int64_t)blockIdx.x * 9 + c] = t;
+  }
+}
+
+// Residual sums of the stationary equation, per block: with L = -1/2 lap_h psi + V psi
+// (3-point Laplacian, zero ghosts) and Q = |psi|^2 psi:
+// { sum|psi|^2, sum|L|^2, sum Re(L* Q), sum|Q|^2, sum Re(psi* L), sum|psi|^4 }.
+constexpr int kResSums = 6;
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+kb_residual(const typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst,
+            const BWork* __restrict__ work, const double* __restrict__ vd, double* __restrict__ partials) {
+  __shared__ double red[4];
+  const BWork wk = work[blockIdx.x];
+  const BInst& I = inst[wk.inst];
+  const int nx = I.nx, ny = I.ny, nz = I.nz;
+  const int64_t npts = (int64_t)nx * ny * nz, sx = (int64_t)ny * nz;
+  const typename VecOf<R>::T* psi = psi_all + I.off;
+  const double *vx = vd + I.v_off[0], *vy = vd + I.v_off[1], *vz = vd + I.v_off[2];
+  double acc[kResSums];
+#pragma unroll
+  for (int c = 0; c < kResSums; ++c) acc[c] = 0.0;
+  const int64_t q0 = (int64_t)wk.blk * kChunk, q1 = min(q0 + kChunk, npts);
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
+    const int k = (int)(q % nz);
+    const int64_t r = q / nz;
+    const int j = (int)(r % ny);
+    const int i = (int)(r / ny);
+    const double re = psi[q].x, im = psi[q].y;
+    double sr[3] = {0, 0, 0}, si[3] = {0, 0, 0};  // neighbour sums per axis
+    if (i > 0) { sr[0] += psi[q - sx].x; si[0] += psi[q - sx].y; }
+    if (i + 1 < nx) { sr[0] += psi[q + sx].x; si[0] += psi[q + sx].y; }
+    if (j > 0) { sr[1] += psi[q - nz].x; si[1] += psi[q - nz].y; }
+    if (j + 1 < ny) { sr[1] += psi[q + nz].x; si[1] += psi[q + nz].y; }
+    if (k > 0) { sr[2] += psi[q - 1].x; si[2] += psi[q - 1].y; }
+    if (k + 1 < nz) { sr[2] += psi[q + 1].x; si[2] += psi[q + 1].y; }
+    const double v = vx[i] + vy[j] + vz[k];
+    double lr = v * re, li = v * im;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lr -= 0.5 * I.id2[a] * (sr[a] - 2.0 * re);
+      li -= 0.5 * I.id2[a] * (si[a] - 2.0 * im);
+    }
+    const double n2 = re * re + im * im;
+    const double qr = n2 * re, qi = n2 * im;
+    acc[0] += n2;
+    acc[1] += lr * lr + li * li;
+    acc[2] += lr * qr + li * qi;
+    acc[3] += qr * qr + qi * qi;
+    acc[4] += re * lr + im * li;
+    acc[5] += n2 * n2;
+  }
+  for (int c = 0; c < kResSums; ++c) {
+    const double t = block_sum_256(acc[c], red);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * kResSums + c] = t;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+kb_res_final(const double* __restrict__ partials, const BInst* __restrict__ inst, double* __restrict__ out) {
+  __shared__ double red[4];
+  const BInst& I = inst[blockIdx.x];
+  for (int c = 0; c < kResSums; ++c) {
+    double acc = 0.0;
+    for (int q = I.ob0 + threadIdx.x; q < I.ob1; q += 256) acc += partials[(int64_t)q * kResSums + c];
+    const double t = block_sum_256(acc, red);
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * kResSums + c] = t;
   }
 }
 
@@ -475,6 +543,9 @@ int configure(gp_batch* b) {
     I.split = p.split;
     I.dt = p.dt;
     I.dV = p.dx * p.dy * p.dz;
+    I.id2[0] = 1.0 / (p.dx * p.dx);
+    I.id2[1] = 1.0 / (p.dy * p.dy);
+    I.id2[2] = 1.0 / (p.dz * p.dz);
     const int n[3] = {p.nx, p.ny, p.nz};
     const double d[3] = {p.dx, p.dy, p.dz};
     I.nseg[0] = cdiv(p.nx, mx);
@@ -874,6 +945,41 @@ int gp_batch_energy_mu(gp_batch* b, double* energy, double* mu) {
     mu[i] = lin + nl;
   }
   return rc;
+}
+
+int gp_batch_residual(gp_batch* b, double* res, double* mu) {
+  if (!b || !res) return GP_ERR_INVALID;
+  int rc = btimed(b, b->stream, 4, [&](hipStream_t t) {
+    if (b->prec == GP_C64)
+      hipLaunchKernelGGL(gpk::kb_residual<float>, dim3(b->nbo), dim3(256), 0, t, (const float2*)b->psi, b->dinst,
+                         b->wo, b->vd, b->opart);
+    else
+      hipLaunchKernelGGL(gpk::kb_residual<double>, dim3(b->nbo), dim3(256), 0, t, (const double2*)b->psi, b->dinst,
+                         b->wo, b->vd, b->opart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gpk::kb_res_final, dim3(b->n), dim3(256), 0, t, b->opart, b->dinst, b->oout);
+    return hipGetLastError();
+  });
+  if (rc) return rc;
+  BCHK(b, hipMemcpyAsync(b->host, b->oout, (size_t)b->n * gpk::kResSums * sizeof(double), hipMemcpyDeviceToHost,
+                         b->stream));
+  BCHK(b, hipStreamSynchronize(b->stream));
+  int status = GP_OK;
+  for (int i = 0; i < b->n; ++i) {
+    const double* r = b->host + (size_t)gpk::kResSums * i;
+    const double g = b->p[i].g, dV = b->p[i].dx * b->p[i].dy * b->p[i].dz;
+    const double N = dV * r[0];
+    // phi = psi / sqrt(N):  H phi = L / sqrt(N) + g Q / N^{3/2}
+    const double hh = dV * (r[1] / N + 2.0 * g * r[2] / (N * N) + g * g * r[3] / (N * N * N));
+    const double m = dV * (r[4] / N + g * r[5] / (N * N));
+    const double r2 = hh - m * m;
+    res[i] = std::sqrt(r2 > 0.0 ? r2 : 0.0);
+    if (mu) mu[i] = m;
+    if (!std::isfinite(res[i]) || !std::isfinite(m)) status = GP_ERR_NONFINITE;
+    else if (!(N > 0)) status = GP_ERR_ZERO_NORM;
+  }
+  return status;
 }
 
 int gp_batch_rms(gp_batch* b, double* rms4) {

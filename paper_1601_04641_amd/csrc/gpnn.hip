@@ -1,0 +1,833 @@
+// Warm-start network on gfx950: BF16 MFMA convolutions (implicit GEMM) with FP32
+// accumulation, split-K weight gradients through LDS, fused pointwise layers and Adam.
+//
+// Matrix-core tiles (wave64): v_mfma_f32_16x16x32_bf16 (cin multiple of 32) and
+// v_mfma_f32_16x16x16_bf16 (cin multiple of 16).  For the 16x16xK tile, lane l holds
+// A[row l%16][k (l/16)*K/4 ...] and B[k (l/16)*K/4 ...][col l%16] (K/4 consecutive
+// values each) and receives D[row (l/16)*4 + i][col l%16], i = 0..3.
+//
+// Convolution as GEMM: rows = output positions, columns = output channels,
+// K = taps x input channels.  Channels-last storage makes every A fragment (K/4
+// consecutive input channels of one position) and every B fragment (K/4 consecutive
+// input channels of one output channel, weights [tap][cout][cin]) one 16- or 8-byte
+// load.  The backward pass with respect to the input is the same kernel applied to the
+// output gradient with the weights transposed and the taps mirrored
+// (W'[26 - t][i][o] = W[t][o][i]), so one kernel serves both.
+#include "../../include/gpnn.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kFMax = 10.0f;   // psi = exp(min(f, kFMax))
+constexpr int kChunk = 2048;     // positions per split-K block of the weight gradient
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// round to nearest even; NaN stays NaN
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + __expf(-x)); }
+__device__ __forceinline__ float silu(float x) { return x * sigm(x); }
+__device__ __forceinline__ float silu_d(float x) {
+  const float s = sigm(x);
+  return s * (1.0f + x * (1.0f - s));
+}
+
+template <int KC> struct Frag;
+template <> struct Frag<32> {
+  typedef bf16x8 T;
+  static __device__ __forceinline__ T load(const uint16_t* p) { return *reinterpret_cast<const T*>(p); }
+  static __device__ __forceinline__ T zero() { return T{}; }
+  static __device__ __forceinline__ f32x4 mma(T a, T b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Frag<16> {
+  typedef bf16x4 T;
+  static __device__ __forceinline__ T load(const uint16_t* p) { return *reinterpret_cast<const T*>(p); }
+  static __device__ __forceinline__ T zero() { return T{}; }
+  static __device__ __forceinline__ f32x4 mma(T a, T b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+
+// y[p, o] = epilogue(sum_t sum_i w[t][o][i] x[nbr_t(p)][i]).  Block: 4 waves, 64 positions
+// (16 per wave) x 64 output channels (blockIdx.y selects the 64-channel slice).
+template <int KS, int KC>
+__global__ void __launch_bounds__(256)
+k_conv(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const float* __restrict__ bias,
+       int64_t P, int D, int cin, int cout, int act, const uint16_t* __restrict__ gate,
+       uint16_t* __restrict__ y, uint16_t* __restrict__ pre) {
+  typedef Frag<KC> F;
+  constexpr int KQ = KC / 4;  // consecutive K values per lane
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, kq = lane >> 4;
+  const int64_t p0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int co0 = blockIdx.y * 64;
+  const int nb = min(4, (cout - co0) >> 4);
+  const int64_t p = p0 + r;
+  const bool pv = p < P;
+  int pi = 0, pj = 0, pk = 0;
+  if (KS == 3 && pv) {
+    int64_t q = p;
+    pk = (int)(q % D);
+    q /= D;
+    pj = (int)(q % D);
+    q /= D;
+    pi = (int)(q % D);
+  }
+  f32x4 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < KS * KS * KS; ++t) {
+    bool ok = pv;
+    int64_t nbr = p;
+    if (KS == 3) {
+      const int a = t / 9 - 1, b = (t / 3) % 3 - 1, c = t % 3 - 1;
+      ok = ok && (unsigned)(pi + a) < (unsigned)D && (unsigned)(pj + b) < (unsigned)D &&
+           (unsigned)(pk + c) < (unsigned)D;
+      nbr = p + ((int64_t)a * D + b) * D + c;
+    }
+    const uint16_t* xr = x + (ok ? nbr : 0) * (int64_t)cin + kq * KQ;
+    const uint16_t* wt = w + ((int64_t)t * cout + co0 + r) * cin + kq * KQ;
+    for (int k0 = 0; k0 < cin; k0 += KC) {
+      const typename F::T av = ok ? F::load(xr + k0) : F::zero();
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < nb) acc[j] = F::mma(av, F::load(wt + (int64_t)j * 16 * cin + k0), acc[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j >= nb) continue;
+    const int co = co0 + j * 16 + r;
+    const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t pos = p0 + kq * 4 + i;
+      if (pos >= P) continue;
+      const int64_t o = pos * cout + co;
+      float v = acc[j][i] + bv;
+      if (pre) pre[o] = f2bf(v);
+      if (gate) v *= silu_d(bf2f(gate[o]));
+      else if (act) v = silu(v);
+      y[o] = f2bf(v);
+    }
+  }
+}
+
+// Split-K weight gradient: block (chunk, tap, 64x64 tile of (cout, cin)); partial sums
+// over the chunk's positions written to part[chunk][tap][cout][cin].  Each 64-position
+// sub-tile of dy and of x (shifted by the tap, zero outside the grid) is staged in LDS
+// transposed ([channel][position]), so both MFMA operands are 16-byte LDS reads.
+template <int KS>
+__global__ void __launch_bounds__(256)
+k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, int64_t P, int D, int cin, int cout,
+        float* __restrict__ part) {
+  constexpr int LD = 72;  // 64 positions + 8 pad (row = 144 B, 16-byte aligned)
+  __shared__ __align__(16) uint16_t sdy[64 * LD];
+  __shared__ __align__(16) uint16_t sx[64 * LD];
+  constexpr int T = KS * KS * KS;
+  const int t = blockIdx.y;
+  const int cot = (cout + 63) / 64;
+  const int co0 = (blockIdx.z % cot) * 64, ci0 = (blockIdx.z / cot) * 64;
+  const int nco = min(64, cout - co0), nci = min(64, cin - ci0);
+  const int a = KS == 3 ? t / 9 - 1 : 0, b = KS == 3 ? (t / 3) % 3 - 1 : 0, c = KS == 3 ? t % 3 - 1 : 0;
+  const int64_t q0 = (int64_t)blockIdx.x * kChunk;
+  const int64_t q1 = min(P, q0 + kChunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, kq = lane >> 4;
+  f32x4 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int pp = threadIdx.x >> 2;          // staged position of this thread
+  const int cg = (threadIdx.x & 3) * 8;     // first channel group of this thread
+  for (int64_t s0 = q0; s0 < q1; s0 += 64) {
+    __syncthreads();
+    {
+      const int64_t pos = s0 + pp;
+      const bool pv = pos < q1;
+      for (int c8 = cg; c8 < 64; c8 += 32) {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (pv && c8 < nco) v = *reinterpret_cast<const uint4*>(dy + pos * cout + co0 + c8);
+        const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sdy[(c8 + q) * LD + pp] = e[q];
+      }
+      bool ok = pv;
+      int64_t nbr = pos;
+      if (KS == 3 && pv) {
+        int64_t q = pos;
+        const int pk = (int)(q % D);
+        q /= D;
+        const int pj = (int)(q % D);
+        q /= D;
+        const int pi = (int)(q % D);
+        ok = (unsigned)(pi + a) < (unsigned)D && (unsigned)(pj + b) < (unsigned)D && (unsigned)(pk + c) < (unsigned)D;
+        nbr = pos + ((int64_t)a * D + b) * D + c;
+      }
+      for (int c8 = cg; c8 < 64; c8 += 32) {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (ok && c8 < nci) v = *reinterpret_cast<const uint4*>(x + nbr * cin + ci0 + c8);
+        const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sx[(c8 + q) * LD + pp] = e[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) {
+        const int blk = wave + bi * 4;
+        const int bco = blk & 3, bci = blk >> 2;
+        if (bco * 16 >= nco || bci * 16 >= nci) continue;
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(sdy + (bco * 16 + r) * LD + ks * 32 + kq * 8);
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sx + (bci * 16 + r) * LD + ks * 32 + kq * 8);
+        acc[bi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[bi], 0, 0, 0);
+      }
+    }
+  }
+  float* out = part + ((int64_t)blockIdx.x * T + t) * (int64_t)cout * cin;
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi) {
+    const int blk = wave + bi * 4;
+    const int bco = blk & 3, bci = blk >> 2;
+    if (bco * 16 >= nco || bci * 16 >= nci) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      out[(int64_t)(co0 + bco * 16 + kq * 4 + i) * cin + ci0 + bci * 16 + r] = acc[bi][i];
+  }
+}
+
+// out[(t * rows + o) * keep + i] = sum_chunks part[chunk][t][o][i], i < keep (fixed order)
+__global__ void __launch_bounds__(256)
+k_reduce_chunks(const float* __restrict__ part, int nchunk, int64_t per_chunk, int cols, int keep,
+                float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= per_chunk) return;
+  const int i = (int)(e % cols);
+  if (i >= keep) return;
+  float s = 0.0f;
+  for (int k = 0; k < nchunk; ++k) s += part[(int64_t)k * per_chunk + e];
+  out[(e / cols) * keep + i] = s;
+}
+
+// per-chunk column sums of dy [P][C] -> part[chunk][C]
+__global__ void __launch_bounds__(256)
+k_colsum(const uint16_t* __restrict__ dy, int64_t P, int C, float* __restrict__ part) {
+  __shared__ float red[256];
+  const int64_t q0 = (int64_t)blockIdx.x * kChunk, q1 = min(P, q0 + kChunk);
+  if (C >= 256) {
+    for (int ch = threadIdx.x; ch < C; ch += 256) {
+      float s = 0.0f;
+      for (int64_t q = q0; q < q1; ++q) s += bf2f(dy[q * C + ch]);
+      part[(int64_t)blockIdx.x * C + ch] = s;
+    }
+    return;
+  }
+  const int ns = 256 / C;  // position stripes
+  const int ch = threadIdx.x % C, st = threadIdx.x / C;
+  float s = 0.0f;
+  if (st < ns)
+    for (int64_t q = q0 + st; q < q1; q += ns) s += bf2f(dy[q * C + ch]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < C) {
+    float tot = 0.0f;
+    for (int k = 0; k < ns; ++k) tot += red[k * C + threadIdx.x];
+    part[(int64_t)blockIdx.x * C + threadIdx.x] = tot;
+  }
+}
+
+// nearest x2 upsampling, channels last, 8 channels (16 B) per thread
+__global__ void __launch_bounds__(256)
+k_up2(const uint16_t* __restrict__ a, int n, int D, int C, uint16_t* __restrict__ u) {
+  const int D2 = 2 * D, c8n = C / 8;
+  const int64_t tot = (int64_t)n * D2 * D2 * D2 * c8n;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= tot) return;
+  int64_t q = e;
+  const int c8 = (int)(q % c8n);
+  q /= c8n;
+  const int k = (int)(q % D2);
+  q /= D2;
+  const int j = (int)(q % D2);
+  q /= D2;
+  const int i = (int)(q % D2);
+  const int64_t s = q / D2;
+  const int64_t src = (((s * D + (i >> 1)) * D + (j >> 1)) * D + (k >> 1)) * C + c8 * 8;
+  reinterpret_cast<uint4*>(u)[e] = *reinterpret_cast<const uint4*>(a + src);
+}
+
+// dh[coarse] = silu'(pre[coarse]) * sum of the 8 fine children of du (adjoint of k_up2,
+// then the activation's derivative)
+__global__ void __launch_bounds__(256)
+k_pool2_gate(const uint16_t* __restrict__ du, int n, int D, int C, const uint16_t* __restrict__ pre,
+             uint16_t* __restrict__ dh) {
+  const int D2 = 2 * D, c8n = C / 8;
+  const int64_t tot = (int64_t)n * D * D * D * c8n;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= tot) return;
+  int64_t q = e;
+  const int c8 = (int)(q % c8n);
+  q /= c8n;
+  const int k = (int)(q % D);
+  q /= D;
+  const int j = (int)(q % D);
+  q /= D;
+  const int i = (int)(q % D);
+  const int64_t s = q / D;
+  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int di = 0; di < 2; ++di)
+    for (int dj = 0; dj < 2; ++dj)
+      for (int dk = 0; dk < 2; ++dk) {
+        const int64_t f = (((s * D2 + 2 * i + di) * D2 + 2 * j + dj) * D2 + 2 * k + dk) * C + c8 * 8;
+        const uint4 v = *reinterpret_cast<const uint4*>(du + f);
+        const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+        for (int q2 = 0; q2 < 8; ++q2) acc[q2] += bf2f(h[q2]);
+      }
+  const uint4 pv = reinterpret_cast<const uint4*>(pre)[e];
+  const uint16_t* ph = reinterpret_cast<const uint16_t*>(&pv);
+  uint4 o;
+  uint16_t* oh = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+  for (int q2 = 0; q2 < 8; ++q2) oh[q2] = f2bf(acc[q2] * silu_d(bf2f(ph[q2])));
+  reinterpret_cast<uint4*>(dh)[e] = o;
+}
+
+// standardised features, zero-padded to 32 channels
+__global__ void k_features(const float* __restrict__ prm, int n, const float* __restrict__ mean_std,
+                           uint16_t* __restrict__ z0) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * 32) return;
+  const int s = e / 32, f = e % 32;
+  float v = 0.0f;
+  if (f < 4) {
+    float q = prm[s * 4 + f];
+    if (f == 3) q = logf(q);
+    v = (q - mean_std[f]) / mean_std[4 + f];
+  }
+  z0[e] = f2bf(v);
+}
+
+__device__ __forceinline__ float log_prior(const float* prm, int s, int i, int j, int k, int N, float dx) {
+  const float nx = prm[s * 4], ny = prm[s * 4 + 1], nz = prm[s * 4 + 2];
+  const float h = 0.5f * (float)(N - 1);
+  const float x = ((float)i - h) * dx, y = ((float)j - h) * dx, z = ((float)k - h) * dx;
+  return 0.25f * (logf(nx * 0.31830988618379067f) + logf(ny * 0.31830988618379067f) +
+                  logf(nz * 0.31830988618379067f)) -
+         0.5f * (nx * x * x + ny * y * y + nz * z * z);
+}
+
+// psi = exp(min(wh . a + bh + ln G, FMAX)); C multiple of 8
+__global__ void __launch_bounds__(256)
+k_head_fwd(const uint16_t* __restrict__ aL, int64_t P, int N, int C, const float* __restrict__ whb,
+           const float* __restrict__ prm, float dx, void* __restrict__ out, int cplx) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  int64_t q = p;
+  const int k = (int)(q % N);
+  q /= N;
+  const int j = (int)(q % N);
+  q /= N;
+  const int i = (int)(q % N);
+  const int s = (int)(q / N);
+  float f = whb[C];
+  for (int c8 = 0; c8 < C; c8 += 8) {
+    const uint4 v = *reinterpret_cast<const uint4*>(aL + p * C + c8);
+    const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f += whb[c8 + e] * bf2f(h[e]);
+  }
+  f += log_prior(prm, s, i, j, k, N, dx);
+  const float psi = __expf(fminf(f, kFMax));
+  if (cplx) reinterpret_cast<float2*>(out)[p] = make_float2(psi, 0.0f);
+  else reinterpret_cast<float*>(out)[p] = psi;
+}
+
+// loss and the head's backward: df = dL/dpsi * psi (zero where clamped);
+// dh[p][c] = df wh[c] silu'(pre[p][c]); per-block partials of sum (psi - t)^2, of
+// df a[p][c] and of df (wave shuffles, then the 4 waves in fixed order).
+template <int C>
+__global__ void __launch_bounds__(256)
+k_head_bwd(const float* __restrict__ psi, const float* __restrict__ tgt, const uint16_t* __restrict__ aL,
+           const uint16_t* __restrict__ preL, int64_t P, const float* __restrict__ whb, float scale,
+           uint16_t* __restrict__ dh, float* __restrict__ gpart, double* __restrict__ lpart) {
+  __shared__ float sred[4][C + 1];
+  __shared__ double dred[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float df = 0.0f;
+  double d2 = 0.0;
+  float ga[C];
+  const bool pv = p < P;
+  if (pv) {
+    const float ps = psi[p], d = ps - tgt[p];
+    d2 = (double)d * (double)d;
+    df = ps < __expf(kFMax) ? 2.0f * d * scale * ps : 0.0f;
+  }
+#pragma unroll
+  for (int c8 = 0; c8 < C; c8 += 8) {
+    uint4 av = make_uint4(0, 0, 0, 0), hv = make_uint4(0, 0, 0, 0);
+    if (pv) {
+      av = *reinterpret_cast<const uint4*>(aL + p * C + c8);
+      hv = *reinterpret_cast<const uint4*>(preL + p * C + c8);
+    }
+    const uint16_t* ah = reinterpret_cast<const uint16_t*>(&av);
+    const uint16_t* hh = reinterpret_cast<const uint16_t*>(&hv);
+    uint4 o;
+    uint16_t* oh = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      ga[c8 + e] = df * bf2f(ah[e]);
+      oh[e] = f2bf(df * whb[c8 + e] * silu_d(bf2f(hh[e])));
+    }
+    if (pv) *reinterpret_cast<uint4*>(dh + p * C + c8) = o;
+  }
+#pragma unroll
+  for (int c = 0; c <= C; ++c) {
+    float v = c < C ? ga[c] : df;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) sred[wave][c] = v;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) d2 += __shfl_xor(d2, off);
+  if (lane == 0) dred[wave] = d2;
+  __syncthreads();
+  if ((int)threadIdx.x <= C)
+    gpart[(int64_t)blockIdx.x * (C + 1) + threadIdx.x] =
+        ((sred[0][threadIdx.x] + sred[1][threadIdx.x]) + sred[2][threadIdx.x]) + sred[3][threadIdx.x];
+  if (threadIdx.x == 0) lpart[blockIdx.x] = ((dred[0] + dred[1]) + dred[2]) + dred[3];
+}
+
+__global__ void k_sum_double(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) s += part[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// BF16 copies of a weight [T][rows][cols]: dst [T][rows][cpad] (zero padded columns) and,
+// if dst_t, the mirrored transpose dst_t[T-1-t][cols][rows]
+__global__ void k_pack(const float* __restrict__ src, int T, int rows, int cols, int cpad, uint16_t* __restrict__ dst,
+                       uint16_t* __restrict__ dst_t) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t tot = (int64_t)T * rows * cpad;
+  if (e >= tot) return;
+  const int i = (int)(e % cpad);
+  const int64_t q = e / cpad;
+  const int o = (int)(q % rows);
+  const int t = (int)(q / rows);
+  const float v = i < cols ? src[((int64_t)t * rows + o) * cols + i] : 0.0f;
+  dst[e] = f2bf(v);
+  if (dst_t && i < cols) dst_t[((int64_t)(T - 1 - t) * cols + i) * rows + o] = f2bf(v);
+}
+
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const float gv = g[e];
+  const float mv = b1 * m[e] + (1.0f - b1) * gv;
+  const float vv = b2 * v[e] + (1.0f - b2) * gv * gv;
+  m[e] = mv;
+  v[e] = vv;
+  w[e] -= lr * (mv * c1) / (sqrtf(vv * c2) + eps);
+}
+
+}  // namespace nn
+
+using namespace nn;
+
+// ------------------------------------------------------------------------------- host
+namespace {
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_conv(int ks, int64_t P, int D, int cin, int cout, const uint16_t* x, const uint16_t* w,
+                       const float* bias, int act, const uint16_t* gate, uint16_t* y, uint16_t* pre,
+                       hipStream_t st) {
+  dim3 grid((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64));
+  const bool k32 = cin % 32 == 0;
+  if (ks == 3) {
+    if (k32) hipLaunchKernelGGL((k_conv<3, 32>), grid, dim3(256), 0, st, x, w, bias, P, D, cin, cout, act, gate, y, pre);
+    else hipLaunchKernelGGL((k_conv<3, 16>), grid, dim3(256), 0, st, x, w, bias, P, D, cin, cout, act, gate, y, pre);
+  } else {
+    if (k32) hipLaunchKernelGGL((k_conv<1, 32>), grid, dim3(256), 0, st, x, w, bias, P, 1, cin, cout, act, gate, y, pre);
+    else hipLaunchKernelGGL((k_conv<1, 16>), grid, dim3(256), 0, st, x, w, bias, P, 1, cin, cout, act, gate, y, pre);
+  }
+  return hipGetLastError();
+}
+
+int64_t wgrad_part_floats(int ks, int64_t P, int cin, int cout) {
+  const int64_t nch = (P + kChunk - 1) / kChunk;
+  return nch * (int64_t)ks * ks * ks * cout * cin;
+}
+
+// dw[t][o][i < keep] (row stride keep) and db[o] (nullable) from dy [P][cout], x [P][cin]
+hipError_t launch_wgrad(int ks, int64_t P, int D, int cin, int cout, int keep, const uint16_t* dy, const uint16_t* x,
+                        float* part, float* dw, float* cpart, float* db, hipStream_t st) {
+  const int nch = (int)((P + kChunk - 1) / kChunk);
+  const int T = ks * ks * ks;
+  dim3 grid((unsigned)nch, (unsigned)T, (unsigned)(((cout + 63) / 64) * ((cin + 63) / 64)));
+  if (ks == 3) hipLaunchKernelGGL((k_wgrad<3>), grid, dim3(256), 0, st, dy, x, P, D, cin, cout, part);
+  else hipLaunchKernelGGL((k_wgrad<1>), grid, dim3(256), 0, st, dy, x, P, 1, cin, cout, part);
+  const int64_t per = (int64_t)T * cout * cin;
+  hipLaunchKernelGGL(k_reduce_chunks, dim3(nblk(per)), dim3(256), 0, st, part, nch, per, cin, keep, dw);
+  if (db) {
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nch), dim3(256), 0, st, dy, P, cout, cpart);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(nblk(cout)), dim3(256), 0, st, cpart, nch, (int64_t)cout, cout, cout, db);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+struct gpnn {
+  gpnn_arch a{};
+  hipStream_t st = nullptr;
+  std::string err;
+  int S = 0, N = 0, F2 = 0;
+  int64_t np = 0;
+  // offsets into the FP32 parameter vector
+  int64_t oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oC[7] = {}, oc[7] = {}, owh = 0;
+  float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *ms = nullptr;
+  uint16_t *W1p = nullptr, *W2 = nullptr, *W2t = nullptr, *Cb[7] = {}, *Ct[7] = {};
+  // activations
+  uint16_t *z0 = nullptr, *h1 = nullptr, *a1 = nullptr, *h2 = nullptr, *a2 = nullptr;
+  uint16_t *u[7] = {}, *h[7] = {}, *act[7] = {};
+  uint16_t *dA = nullptr, *dB = nullptr, *dU = nullptr;
+  float *part = nullptr, *cpart = nullptr, *gpart = nullptr;
+  double *lpart = nullptr, *lsum = nullptr;
+  std::vector<void*> allocs;
+  // last forward
+  int n = 0;
+  const float* prm = nullptr;
+  const void* out = nullptr;
+  int out_cplx = 0;
+};
+
+namespace {
+
+int set_err(gpnn* m, int code, const std::string& s) {
+  if (m) m->err = s;
+  return code;
+}
+
+int hip_chk(gpnn* m, hipError_t e, const char* what) {
+  if (e == hipSuccess) return GPNN_OK;
+  return set_err(m, GPNN_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T> int alloc(gpnn* m, T** p, int64_t count) {
+  void* q = nullptr;
+  if (hipMalloc(&q, (size_t)count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(m, GPNN_ERR_OOM, "device allocation failed");
+  }
+  m->allocs.push_back(q);
+  *p = (T*)q;
+  return GPNN_OK;
+}
+
+int64_t vol(int D) { return (int64_t)D * D * D; }
+
+hipError_t refresh_bf16(gpnn* m) {
+  const gpnn_arch& a = m->a;
+  hipStream_t st = m->st;
+  hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)a.hidden * 32)), dim3(256), 0, st, m->w + m->oW1, 1, a.hidden, 4, 32,
+                     m->W1p, (uint16_t*)nullptr);
+  hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)m->F2 * a.hidden)), dim3(256), 0, st, m->w + m->oW2, 1, m->F2,
+                     a.hidden, a.hidden, m->W2, m->W2t);
+  for (int s = 1; s <= m->S; ++s)
+    hipLaunchKernelGGL(k_pack, dim3(nblk((int64_t)27 * a.ch[s] * a.ch[s - 1])), dim3(256), 0, st, m->w + m->oC[s], 27,
+                       a.ch[s], a.ch[s - 1], a.ch[s - 1], m->Cb[s], m->Ct[s]);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+int gpnn_create(const gpnn_arch* a, void* hip_stream, gpnn** out) {
+  if (!a || !out) return GPNN_ERR_INVALID;
+  *out = nullptr;
+  const int S = a->nstage;
+  if (S < 1 || S > 6 || a->base < 1 || a->max_batch < 1 || a->hidden < 16 || a->hidden % 16 || !(a->dx > 0))
+    return GPNN_ERR_INVALID;
+  for (int s = 0; s <= S; ++s)
+    if (a->ch[s] < 16 || a->ch[s] % 16) return GPNN_ERR_INVALID;
+  if (a->ch[S] != 16 && a->ch[S] != 32 && a->ch[S] != 64) return GPNN_ERR_INVALID;
+  for (int f = 0; f < 4; ++f)
+    if (!(a->in_std[f] > 0)) return GPNN_ERR_INVALID;
+  const int64_t N = (int64_t)a->base << S;
+  if (N > 1024 || (int64_t)a->max_batch * vol((int)N) * a->ch[S - 1] > ((int64_t)1 << 34)) return GPNN_ERR_INVALID;
+  gpnn* m = new (std::nothrow) gpnn();
+  if (!m) return GPNN_ERR_OOM;
+  m->a = *a;
+  m->st = (hipStream_t)hip_stream;
+  m->S = S;
+  m->N = (int)N;
+  m->F2 = a->base * a->base * a->base * a->ch[0];
+  int64_t o = 0;
+  m->oW1 = o; o += (int64_t)a->hidden * 4;
+  m->ob1 = o; o += a->hidden;
+  m->oW2 = o; o += (int64_t)m->F2 * a->hidden;
+  m->ob2 = o; o += m->F2;
+  for (int s = 1; s <= S; ++s) {
+    m->oC[s] = o; o += (int64_t)27 * a->ch[s] * a->ch[s - 1];
+    m->oc[s] = o; o += a->ch[s];
+  }
+  m->owh = o; o += a->ch[S] + 1;
+  m->np = o;
+  const int B = a->max_batch;
+  int rc = GPNN_OK;
+  auto A = [&](auto** p, int64_t cnt) { if (rc == GPNN_OK) rc = alloc(m, p, cnt); };
+  A(&m->w, o); A(&m->g, o); A(&m->m, o); A(&m->v, o); A(&m->ms, 8);
+  A(&m->W1p, (int64_t)a->hidden * 32);
+  A(&m->W2, (int64_t)m->F2 * a->hidden);
+  A(&m->W2t, (int64_t)m->F2 * a->hidden);
+  A(&m->z0, (int64_t)B * 32);
+  A(&m->h1, (int64_t)B * a->hidden); A(&m->a1, (int64_t)B * a->hidden);
+  A(&m->h2, (int64_t)B * m->F2); A(&m->a2, (int64_t)B * m->F2);
+  int64_t maxd = (int64_t)B * std::max(m->F2, a->hidden), maxu = 0, maxpart = 0, maxc = 0;
+  maxpart = std::max(wgrad_part_floats(1, B, a->hidden, m->F2), wgrad_part_floats(1, B, 32, a->hidden));
+  maxc = std::max<int64_t>(m->F2, a->hidden);
+  for (int s = 1; s <= S; ++s) {
+    const int D = a->base << s;
+    const int64_t P = (int64_t)B * vol(D);
+    A(&m->Cb[s], (int64_t)27 * a->ch[s] * a->ch[s - 1]);
+    A(&m->Ct[s], (int64_t)27 * a->ch[s] * a->ch[s - 1]);
+    A(&m->u[s], P * a->ch[s - 1]);
+    A(&m->h[s], P * a->ch[s]);
+    A(&m->act[s], P * a->ch[s]);
+    maxd = std::max(maxd, P * a->ch[s]);
+    maxd = std::max(maxd, (int64_t)B * vol(D / 2) * a->ch[s - 1]);
+    maxu = std::max(maxu, P * a->ch[s - 1]);
+    maxpart = std::max(maxpart, wgrad_part_floats(3, P, a->ch[s - 1], a->ch[s]));
+    maxc = std::max(maxc, ((P + kChunk - 1) / kChunk) * a->ch[s]);
+  }
+  const int64_t PS = (int64_t)B * vol(m->N);
+  const int64_t hblocks = (PS + 255) / 256;
+  A(&m->dA, maxd); A(&m->dB, maxd); A(&m->dU, maxu);
+  A(&m->part, maxpart); A(&m->cpart, maxc);
+  A(&m->gpart, hblocks * (a->ch[S] + 1));
+  A(&m->lpart, hblocks); A(&m->lsum, 1);
+  if (rc == GPNN_OK) {
+    float hms[8];
+    for (int f = 0; f < 4; ++f) {
+      hms[f] = (float)a->in_mean[f];
+      hms[4 + f] = (float)a->in_std[f];
+    }
+    rc = hip_chk(m, hipMemcpyAsync(m->ms, hms, sizeof(hms), hipMemcpyHostToDevice, m->st), "copy");
+    if (rc == GPNN_OK) rc = hip_chk(m, hipStreamSynchronize(m->st), "sync");
+  }
+  if (rc != GPNN_OK) {
+    gpnn_destroy(m);
+    return rc;
+  }
+  *out = m;
+  return GPNN_OK;
+}
+
+int gpnn_destroy(gpnn* m) {
+  if (!m) return GPNN_ERR_INVALID;
+  if (m->st) (void)hipStreamSynchronize(m->st);
+  else (void)hipDeviceSynchronize();
+  for (void* p : m->allocs) (void)hipFree(p);
+  delete m;
+  return GPNN_OK;
+}
+
+int gpnn_param_count(gpnn* m, int64_t* n) {
+  if (!m || !n) return GPNN_ERR_INVALID;
+  *n = m->np;
+  return GPNN_OK;
+}
+
+int gpnn_set_params(gpnn* m, const float* host, int64_t n) {
+  if (!m || !host || n != m->np) return set_err(m, GPNN_ERR_INVALID, "parameter count mismatch");
+  int rc = hip_chk(m, hipMemcpyAsync(m->w, host, n * sizeof(float), hipMemcpyHostToDevice, m->st), "copy");
+  if (!rc) rc = hip_chk(m, hipMemsetAsync(m->m, 0, n * sizeof(float), m->st), "memset");
+  if (!rc) rc = hip_chk(m, hipMemsetAsync(m->v, 0, n * sizeof(float), m->st), "memset");
+  if (!rc) rc = hip_chk(m, hipMemsetAsync(m->g, 0, n * sizeof(float), m->st), "memset");
+  if (!rc) rc = hip_chk(m, refresh_bf16(m), "pack");
+  if (!rc) rc = hip_chk(m, hipStreamSynchronize(m->st), "sync");
+  return rc;
+}
+
+static int get_vec(gpnn* m, const float* src, float* host, int64_t n) {
+  if (!m || !host || n != m->np) return set_err(m, GPNN_ERR_INVALID, "parameter count mismatch");
+  int rc = hip_chk(m, hipMemcpyAsync(host, src, n * sizeof(float), hipMemcpyDeviceToHost, m->st), "copy");
+  if (!rc) rc = hip_chk(m, hipStreamSynchronize(m->st), "sync");
+  return rc;
+}
+
+int gpnn_get_params(gpnn* m, float* host, int64_t n) { return m ? get_vec(m, m->w, host, n) : GPNN_ERR_INVALID; }
+int gpnn_get_grads(gpnn* m, float* host, int64_t n) { return m ? get_vec(m, m->g, host, n) : GPNN_ERR_INVALID; }
+
+int gpnn_forward(gpnn* m, const float* prm, int32_t n, void* out, int32_t out_complex64) {
+  if (!m || !prm || !out || n < 1 || n > m->a.max_batch) return set_err(m, GPNN_ERR_INVALID, "bad forward arguments");
+  const gpnn_arch& a = m->a;
+  hipStream_t st = m->st;
+  hipLaunchKernelGGL(k_features, dim3(nblk((int64_t)n * 32)), dim3(256), 0, st, prm, n, m->ms, m->z0);
+  hipError_t e = launch_conv(1, n, 1, 32, a.hidden, m->z0, m->W1p, m->w + m->ob1, 1, nullptr, m->a1, m->h1, st);
+  if (e == hipSuccess)
+    e = launch_conv(1, n, 1, a.hidden, m->F2, m->a1, m->W2, m->w + m->ob2, 1, nullptr, m->a2, m->h2, st);
+  const uint16_t* prev = m->a2;
+  for (int s = 1; s <= m->S && e == hipSuccess; ++s) {
+    const int Dc = a.base << (s - 1), D = a.base << s;
+    const int64_t tot = (int64_t)n * vol(D) * (a.ch[s - 1] / 8);
+    hipLaunchKernelGGL(k_up2, dim3(nblk(tot)), dim3(256), 0, st, prev, n, Dc, a.ch[s - 1], m->u[s]);
+    e = launch_conv(3, (int64_t)n * vol(D), D, a.ch[s - 1], a.ch[s], m->u[s], m->Cb[s], m->w + m->oc[s], 1, nullptr,
+                    m->act[s], m->h[s], st);
+    prev = m->act[s];
+  }
+  if (e == hipSuccess) {
+    const int64_t P = (int64_t)n * vol(m->N);
+    hipLaunchKernelGGL(k_head_fwd, dim3(nblk(P)), dim3(256), 0, st, prev, P, m->N, a.ch[m->S], m->w + m->owh, prm,
+                       (float)a.dx, out, out_complex64 ? 1 : 0);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return hip_chk(m, e, "forward");
+  m->n = n;
+  m->prm = prm;
+  m->out = out;
+  m->out_cplx = out_complex64 ? 1 : 0;
+  return GPNN_OK;
+}
+
+int gpnn_loss_backward(gpnn* m, const float* tgt, double* loss) {
+  if (!m || !tgt) return set_err(m, GPNN_ERR_INVALID, "bad backward arguments");
+  if (m->n < 1 || m->out_cplx) return set_err(m, GPNN_ERR_STATE, "no FP32 forward pass to differentiate");
+  const gpnn_arch& a = m->a;
+  hipStream_t st = m->st;
+  const int n = m->n, S = m->S;
+  const int64_t P = (int64_t)n * vol(m->N);
+  const unsigned hb = nblk(P);
+  const float scale = (float)(a.dx * a.dx * a.dx / n);
+  const float* psi = (const float*)m->out;
+  if (a.ch[S] == 16)
+    hipLaunchKernelGGL((k_head_bwd<16>), dim3(hb), dim3(256), 0, st, psi, tgt, m->act[S], m->h[S], P, m->w + m->owh,
+                       scale, m->dA, m->gpart, m->lpart);
+  else if (a.ch[S] == 32)
+    hipLaunchKernelGGL((k_head_bwd<32>), dim3(hb), dim3(256), 0, st, psi, tgt, m->act[S], m->h[S], P, m->w + m->owh,
+                       scale, m->dA, m->gpart, m->lpart);
+  else
+    hipLaunchKernelGGL((k_head_bwd<64>), dim3(hb), dim3(256), 0, st, psi, tgt, m->act[S], m->h[S], P, m->w + m->owh,
+                       scale, m->dA, m->gpart, m->lpart);
+  hipLaunchKernelGGL(k_reduce_chunks, dim3(nblk(a.ch[S] + 1)), dim3(256), 0, st, m->gpart, (int)hb,
+                     (int64_t)(a.ch[S] + 1), a.ch[S] + 1, a.ch[S] + 1, m->g + m->owh);
+  hipLaunchKernelGGL(k_sum_double, dim3(1), dim3(256), 0, st, m->lpart, (int)hb, m->lsum);
+  hipError_t e = hipGetLastError();
+  uint16_t* dh = m->dA;  // gradient w.r.t. the pre-activation of the current layer
+  uint16_t* other = m->dB;
+  for (int s = S; s >= 1 && e == hipSuccess; --s) {
+    const int D = a.base << s, Dc = a.base << (s - 1);
+    const int64_t Ps = (int64_t)n * vol(D);
+    e = launch_wgrad(3, Ps, D, a.ch[s - 1], a.ch[s], a.ch[s - 1], dh, m->u[s], m->part, m->g + m->oC[s], m->cpart,
+                     m->g + m->oc[s], st);
+    if (e != hipSuccess) break;
+    e = launch_conv(3, Ps, D, a.ch[s], a.ch[s - 1], dh, m->Ct[s], nullptr, 0, nullptr, m->dU, nullptr, st);
+    if (e != hipSuccess) break;
+    const uint16_t* pre_prev = s > 1 ? m->h[s - 1] : m->h2;
+    const int64_t tot = (int64_t)n * vol(Dc) * (a.ch[s - 1] / 8);
+    hipLaunchKernelGGL(k_pool2_gate, dim3(nblk(tot)), dim3(256), 0, st, m->dU, n, Dc, a.ch[s - 1], pre_prev, other);
+    e = hipGetLastError();
+    std::swap(dh, other);
+  }
+  // dense layers: dh = dL/dh2 [n][F2]
+  if (e == hipSuccess)
+    e = launch_wgrad(1, n, 1, a.hidden, m->F2, a.hidden, dh, m->a1, m->part, m->g + m->oW2, m->cpart, m->g + m->ob2,
+                     st);
+  if (e == hipSuccess)
+    e = launch_conv(1, n, 1, m->F2, a.hidden, dh, m->W2t, nullptr, 0, m->h1, other, nullptr, st);
+  if (e == hipSuccess)
+    e = launch_wgrad(1, n, 1, 32, a.hidden, 4, other, m->z0, m->part, m->g + m->oW1, m->cpart, m->g + m->ob1, st);
+  if (e != hipSuccess) return hip_chk(m, e, "backward");
+  if (loss) {
+    int rc = hip_chk(m, hipMemcpyAsync(loss, m->lsum, sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+    if (!rc) rc = hip_chk(m, hipStreamSynchronize(st), "sync");
+    if (rc) return rc;
+    *loss *= a.dx * a.dx * a.dx / n;
+  }
+  return GPNN_OK;
+}
+
+int gpnn_adam_step(gpnn* m, float lr, float b1, float b2, float eps, int64_t t) {
+  if (!m || t < 1 || !(lr >= 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps >= 0))
+    return set_err(m, GPNN_ERR_INVALID, "bad Adam arguments");
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, (double)t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, (double)t)));
+  hipLaunchKernelGGL(k_adam, dim3(nblk(m->np)), dim3(256), 0, m->st, m->w, m->g, m->m, m->v, m->np, lr, b1, b2, eps,
+                     c1, c2);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = refresh_bf16(m);
+  return hip_chk(m, e, "adam");
+}
+
+int gpnn_conv(int32_t ks, int32_t n, int32_t d, int32_t cin, int32_t cout, const void* x, const void* w,
+              const float* bias, int32_t act, const void* gate, void* y, void* pre, void* hip_stream) {
+  if ((ks != 1 && ks != 3) || n < 1 || (ks == 3 && (d < 1 || d > 1024)) || cin < 16 || cin % 16 || cout < 16 ||
+      cout % 16 || !x || !w || !y)
+    return GPNN_ERR_INVALID;
+  const int64_t P = ks == 3 ? (int64_t)n * vol(d) : n;
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = launch_conv(ks, P, ks == 3 ? d : 1, cin, cout, (const uint16_t*)x, (const uint16_t*)w, bias, act,
+                             (const uint16_t*)gate, (uint16_t*)y, (uint16_t*)pre, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? GPNN_OK : GPNN_ERR_HIP;
+}
+
+int gpnn_conv_wgrad(int32_t ks, int32_t n, int32_t d, int32_t cin, int32_t cout, const void* dy, const void* x,
+                    float* dw, float* db, void* hip_stream) {
+  if ((ks != 1 && ks != 3) || n < 1 || (ks == 3 && (d < 1 || d > 1024)) || cin < 16 || cin % 16 || cout < 16 ||
+      cout % 16 || !dy || !x || !dw)
+    return GPNN_ERR_INVALID;
+  const int64_t P = ks == 3 ? (int64_t)n * vol(d) : n;
+  hipStream_t st = (hipStream_t)hip_stream;
+  float *part = nullptr, *cpart = nullptr;
+  const int64_t nch = (P + kChunk - 1) / kChunk;
+  if (hipMalloc((void**)&part, (size_t)wgrad_part_floats(ks, P, cin, cout) * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&cpart, (size_t)nch * cout * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    if (part) (void)hipFree(part);
+    return GPNN_ERR_OOM;
+  }
+  hipError_t e = launch_wgrad(ks, P, ks == 3 ? d : 1, cin, cout, cin, (const uint16_t*)dy, (const uint16_t*)x, part,
+                              dw, cpart, db, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(part);
+  (void)hipFree(cpart);
+  return e == hipSuccess ? GPNN_OK : GPNN_ERR_HIP;
+}
+
+const char* gpnn_last_error(gpnn* m) { return m ? m->err.c_str() : "null model"; }
+
+}  // extern "C"

@@ -28,7 +28,7 @@ EXPORTS = ("gp_init", "gp_destroy", "gp_step_imag", "gp_step_real", "gp_norm", "
            "gp_strerror", "gp_last_error",
            "gp_batch_init", "gp_batch_destroy", "gp_batch_step_imag", "gp_batch_step_real",
            "gp_batch_norm", "gp_batch_energy_mu", "gp_batch_rms", "gp_batch_raw_sums",
-           "gp_batch_status", "gp_batch_converge_imag", "gp_batch_get_mapping",
+           "gp_batch_status", "gp_batch_residual", "gp_batch_converge_imag", "gp_batch_get_mapping",
            "gp_batch_set_mapping", "gp_batch_autotune", "gp_batch_set_timing",
            "gp_batch_get_timing", "gp_batch_last_error")
 
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
         "gp_batch_rms": [vp, P(d)],
         "gp_batch_raw_sums": [vp, P(d)],
         "gp_batch_status": [vp, P(i64), P(d), P(i32)],
+        "gp_batch_residual": [vp, P(d), P(d)],
         "gp_batch_converge_imag": [vp, d, i32, i64, P(i64), P(d), P(i32)],
         "gp_batch_get_mapping": [vp, P(i32)],
         "gp_batch_set_mapping": [vp, P(i32)],
@@ -317,6 +318,12 @@ class Batch:
         out = np.zeros(4 * self.n)
         self._chk(self._L.gp_batch_rms(self._h, _dp(out)), "gp_batch_rms")
         return out.reshape(self.n, 4)
+
+    def residual(self):
+        """(res, mu) per instance: || H[phi] phi - mu phi || and mu of phi = psi / sqrt(N)."""
+        r, m = np.zeros(self.n), np.zeros(self.n)
+        self._chk(self._L.gp_batch_residual(self._h, _dp(r), _dp(m)), "gp_batch_residual")
+        return r, m
 
     def raw_sums(self):
         out = np.zeros(9 * self.n)

@@ -50,6 +50,20 @@ def gaussian_psi(nx, ny, nz, dx, dy, dz, nux, nuy, nuz, dtype=np.complex128) -> 
     return psi.astype(dtype)
 
 
+def gaussian_cube_batch(prm, n: int, d: float, out: np.ndarray | None = None, dtype=np.complex64) -> np.ndarray:
+    """gaussian_psi for many problems on one n^3 grid of spacing d: prm rows are
+    (nu_x, nu_y, nu_z, g); returns [len(prm), n, n, n], each normalised on the grid."""
+    prm = np.asarray(prm, dtype=np.float64)
+    a = axis(n, d)
+    if out is None:
+        out = np.empty((len(prm), n, n, n), dtype=dtype)
+    for i, (nux, nuy, nuz, _) in enumerate(prm):
+        f = [np.exp(-0.5 * nu * a * a) for nu in (nux, nuy, nuz)]
+        f = [v / math.sqrt(float(np.sum(v * v)) * d) for v in f]
+        out[i] = (f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :]).astype(dtype)
+    return out
+
+
 def perturbed_psi(nx, ny, nz, dx, dy, dz, nux, nuy, nuz, seed: int, amp=0.05,
                   dtype=np.complex128) -> np.ndarray:
     """Gaussian times a seeded complex perturbation (breaks every symmetry, including

@@ -79,3 +79,43 @@ def test_missing_library_fails_loudly(tmp_path):
             gp.load(str(tmp_path / "nope.so"))
         finally:
             gp._lib = gp._lib_backup
+
+
+# ---------------------------------------------------------------- warm-start network (gpnn.h)
+def test_gpnn_header_declares_the_binding_names():
+    from paper_1601_04641_amd import nn
+    assert set(declared("gpnn.h")) == set(nn.EXPORTS)
+
+
+def test_library_exports_every_gpnn_symbol(lib):
+    for name in declared("gpnn.h"):
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("field,value", [("hidden", 24), ("base", 0), ("max_batch", 0), ("dx", 0.0),
+                                         ("last_ch", 48), ("nstage", 0), ("nstage", 7), ("first_ch", 8),
+                                         ("base", 512)])
+def test_gpnn_create_rejects_bad_arch_without_device(lib, field, value):
+    from paper_1601_04641_amd import nn
+    nn.load()
+    a = nn.make_arch(base=2, hidden=32, ch=(32, 32, 16), dx=0.5, max_batch=2)
+    if field == "last_ch":
+        a.ch[a.nstage] = value
+    elif field == "first_ch":
+        a.ch[0] = value
+    else:
+        setattr(a, field, value)
+    h = ctypes.c_void_p()
+    assert lib.gpnn_create(ctypes.byref(a), None, ctypes.byref(h)) == nn.GPNN_ERR_INVALID
+    assert not h.value
+
+
+@pytest.mark.parametrize("args", [(2, 1, 4, 32, 16), (3, 1, 4, 8, 16), (3, 1, 4, 32, 24), (3, 0, 4, 32, 16),
+                                  (3, 1, 0, 32, 16)])
+def test_gpnn_conv_rejects_bad_shapes_without_device(lib, args):
+    from paper_1601_04641_amd import nn
+    nn.load()
+    ks, n, d, cin, cout = args
+    assert lib.gpnn_conv(ks, n, d, cin, cout, 0x1000, 0x1000, None, 0, None, 0x1000, None, None) == \
+        nn.GPNN_ERR_INVALID
+    assert lib.gpnn_conv_wgrad(ks, n, d, cin, cout, 0x1000, 0x1000, 0x1000, None, None) == nn.GPNN_ERR_INVALID

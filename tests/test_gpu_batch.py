@@ -195,3 +195,35 @@ def test_batch_rejects_bad_arguments():
             b.set_mapping(mx=5)
         with pytest.raises(gp.GPError):
             b.set_mapping(mz=7)
+
+
+@pytest.mark.parametrize("prec", [gp.GP_C128, gp.GP_C64])
+def test_batch_residual_matches_oracle(prec):
+    from oracle.residual import residual
+    ws = instances()[:4]
+    states, offs, total = pack(ws, prec, seed=40)
+    psi = to_dev(states, total, prec)
+    with gp.Batch(psi, ws, offs) as b:
+        r, mu = b.residual()
+        _, mu_obs = b.energy_mu()
+    tol = 1e-10 if prec == gp.GP_C128 else 1e-5
+    for i, (w, s0) in enumerate(zip(ws, states)):
+        rr, mm = residual(s0, w)
+        say(f"  instance {i}: res {r[i]:.6e} vs {rr:.6e}, mu {mu[i]:.8f} vs {mm:.8f}")
+        assert abs(r[i] - rr) <= tol * rr and abs(mu[i] - mm) <= tol * abs(mm)
+        assert abs(mu[i] - mu_obs[i]) <= 1e-12 * abs(mu_obs[i]) + (0 if prec == gp.GP_C128 else 1e-7 * abs(mm))
+
+
+def test_batch_residual_small_at_converged_ground_state():
+    ws = [dict(w, g=min(w["g"], 50.0)) for w in instances()[:3]]
+    states = [inputs.gaussian_psi(w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"], w["nuz"])
+              for w in ws]
+    offs = np.cumsum([0] + [s.size for s in states[:-1]]).astype(np.int64)
+    psi = to_dev(states, sum(s.size for s in states), gp.GP_C128)
+    with gp.Batch(psi, ws, offs) as b:
+        r0, mu0 = b.residual()
+        b.converge_imag(tol=1e-10, check_every=50, max_steps=40000)
+        r1, mu1 = b.residual()
+    say(f"residual / mu: start {r0 / mu0}, converged {r1 / mu1}")
+    # the imaginary-time fixed point differs from the discrete ground state by O(dt)
+    assert np.all(r1 < 0.05 * r0) and np.all(r1 / mu1 < 5e-3)

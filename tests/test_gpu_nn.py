@@ -1,0 +1,338 @@
+"""GPU tests of the warm-start network kernels against the FP64 reference.
+
+Kernel level: inputs are BF16 values, which both sides use exactly; BF16 x BF16
+products are exact in FP32, so the GPU result differs from the FP64 reference only by
+FP32 accumulation (~1e-6 relative) and the final rounding of BF16 outputs (2^-9
+relative).  Network level: the GPU stores every activation and gradient in BF16, so
+the whole forward pass and the gradients are compared at the few-percent level.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gpnn_ref as R
+from paper_1601_04641_amd import inputs, nn
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+BF_REL = 2.0 ** -8
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    nn.load()
+    yield
+
+
+def bf(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16)
+
+
+def f64(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def close_bf16(gpu, ref, what):
+    err = np.abs(gpu - ref)
+    bound = BF_REL * np.abs(ref) + 1e-5 * np.max(np.abs(ref))
+    worst = float(np.max(err / bound))
+    say(f"  {what}: worst err / bound = {worst:.3f}")
+    assert worst <= 1.0
+
+
+def mirror_transpose(W):
+    """W'[26 - t][i][o] = W[t][o][i]: the weights of the input-gradient convolution."""
+    return np.ascontiguousarray(W[::-1].transpose(0, 2, 1))
+
+
+@pytest.mark.parametrize("cin,cout,D,n", [(32, 16, 5, 2), (64, 64, 8, 1), (16, 32, 6, 2), (32, 80, 4, 3),
+                                          (48, 16, 5, 1), (64, 32, 16, 1)])
+def test_conv3d_forward_bias_silu(cin, cout, D, n):
+    rng = np.random.default_rng(cin * 1000 + cout + D)
+    x = bf(rng.standard_normal((n, D, D, D, cin)))
+    W = bf(rng.standard_normal((27, cout, cin)) / np.sqrt(27 * cin))
+    b = torch.from_numpy(rng.standard_normal(cout).astype(np.float32))
+    y = torch.empty((n, D, D, D, cout), dtype=torch.bfloat16, device="cuda")
+    pre = torch.empty_like(y)
+    say(f"case: conv3d fwd cin {cin} cout {cout} D {D} n {n}")
+    nn.gpnn_conv(3, n, D, cin, cout, x.cuda(), W.cuda(), b.cuda(), 1, None, y, pre)
+    torch.cuda.synchronize()
+    ref = R.conv3d(f64(x), f64(W), b.double().numpy())
+    close_bf16(f64(pre), ref, "pre-activation")
+    close_bf16(f64(y), R.silu(ref), "silu output")
+
+
+@pytest.mark.parametrize("cin,cout,D,n", [(16, 32, 6, 2), (64, 32, 8, 1), (32, 64, 5, 2)])
+def test_conv3d_input_gradient_by_mirrored_weights_with_gate(cin, cout, D, n):
+    """dx = sum_t W[t]^T dy[q - off_t], times silu'(gate): the backward pass through a
+    convolution and the preceding activation."""
+    rng = np.random.default_rng(7 + cin + cout)
+    dy = bf(rng.standard_normal((n, D, D, D, cout)))
+    W = bf(rng.standard_normal((27, cout, cin)) / np.sqrt(27 * cout))
+    gate = bf(rng.standard_normal((n, D, D, D, cin)))
+    dx = torch.empty((n, D, D, D, cin), dtype=torch.bfloat16, device="cuda")
+    say(f"case: conv3d bwd-data cin {cin} cout {cout} D {D}")
+    nn.gpnn_conv(3, n, D, cout, cin, dy.cuda(), bf(mirror_transpose(f64(W))).cuda(), None, 0, gate.cuda(), dx)
+    torch.cuda.synchronize()
+    ref = R.conv3d_bwd_data(f64(dy), f64(W)) * R.silu_grad(f64(gate))
+    close_bf16(f64(dx), ref, "input gradient")
+
+
+@pytest.mark.parametrize("cin,cout,n", [(32, 384, 16), (384, 4096, 16), (4096, 384, 5), (32, 64, 3)])
+def test_dense_forward(cin, cout, n):
+    rng = np.random.default_rng(cin + cout + n)
+    x = bf(rng.standard_normal((n, cin)))
+    W = bf(rng.standard_normal((1, cout, cin)) / np.sqrt(cin))
+    b = torch.from_numpy(rng.standard_normal(cout).astype(np.float32))
+    y = torch.empty((n, cout), dtype=torch.bfloat16, device="cuda")
+    pre = torch.empty_like(y)
+    say(f"case: dense {cin}->{cout} n {n}")
+    nn.gpnn_conv(1, n, 1, cin, cout, x.cuda(), W.cuda(), b.cuda(), 1, None, y, pre)
+    torch.cuda.synchronize()
+    ref = f64(x) @ f64(W)[0].T + b.double().numpy()
+    close_bf16(f64(pre), ref, "pre-activation")
+    close_bf16(f64(y), R.silu(ref), "silu output")
+
+
+@pytest.mark.parametrize("ks,cin,cout,D,n", [(3, 32, 16, 8, 2), (3, 64, 64, 6, 1), (3, 32, 64, 24, 1),
+                                             (3, 16, 32, 13, 2), (1, 384, 4096, 1, 16), (1, 32, 384, 1, 7)])
+def test_weight_and_bias_gradients(ks, cin, cout, D, n):
+    rng = np.random.default_rng(ks + cin + cout + D)
+    shp = (n, D, D, D) if ks == 3 else (n,)
+    dy = bf(rng.standard_normal(shp + (cout,)))
+    x = bf(rng.standard_normal(shp + (cin,)))
+    T = ks ** 3
+    dw = torch.empty((T, cout, cin), dtype=torch.float32, device="cuda")
+    db = torch.empty(cout, dtype=torch.float32, device="cuda")
+    say(f"case: wgrad ks {ks} cin {cin} cout {cout} D {D} n {n} (positions {int(np.prod(shp))})")
+    nn.gpnn_conv_wgrad(ks, n, D, cin, cout, dy.cuda(), x.cuda(), dw, db)
+    torch.cuda.synchronize()
+    if ks == 3:
+        ref = R.conv3d_bwd_weight(f64(dy), f64(x))
+    else:
+        ref = (f64(dy).T @ f64(x))[None]
+    scale = np.sqrt(np.prod(shp))  # size of a sum of that many unit-variance products
+    err = float(np.max(np.abs(dw.cpu().numpy() - ref)))
+    say(f"  dw max err {err:.2e} (sum scale {scale:.0f})")
+    assert err <= 1e-5 * scale
+    dref = f64(dy).reshape(-1, cout).sum(axis=0)
+    assert float(np.max(np.abs(db.cpu().numpy() - dref))) <= 1e-5 * scale
+
+
+def tiny_cfg():
+    return dict(base=2, hidden=32, ch=(32, 32, 16), dx=0.5, max_batch=4)
+
+
+def ref_arch(cfg):
+    return R.Arch(base=cfg["base"], hidden=cfg["hidden"], ch=cfg["ch"], dx=cfg["dx"])
+
+
+def bf16_round_weights(w):
+    """The GPU multiplies with BF16 copies of the weight matrices (not biases or head)."""
+    out = dict(w)
+    for k in w:
+        if k in ("W1", "W2") or k[0] == "C":
+            out[k] = f64(bf(w[k]))
+    return out
+
+
+def trained_like_weights(cfg, seed):
+    """Initial weights plus small perturbations of every tensor and a head of unit
+    scale, so every path carries signal and activations stay O(1-10), as in training."""
+    rng = np.random.default_rng(seed)
+    w = inputs.nn_init_weights(nn.param_shapes(cfg["base"], cfg["hidden"], cfg["ch"]), seed)
+    for k in w:
+        w[k] = np.asarray(w[k]) + 0.01 * rng.standard_normal(np.shape(w[k]))
+    w["wh"] = rng.standard_normal(np.shape(w["wh"])) / np.sqrt(np.size(w["wh"]))
+    return {k: np.asarray(v, dtype=np.float32).astype(np.float64) for k, v in w.items()}
+
+
+def round_bf16(x):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16_storage(w, p, a):
+    """The reference forward pass with every stored activation rounded to BF16 where the
+    GPU stores it (features, each layer's output) and BF16 weight matrices."""
+    n = p.shape[0]
+    z0 = round_bf16(R.features(p, a))
+    a1 = round_bf16(R.silu(z0 @ round_bf16(w["W1"]).T + w["b1"]))
+    act = round_bf16(R.silu(a1 @ round_bf16(w["W2"]).T + w["b2"])).reshape(n, a.base, a.base, a.base, a.ch[0])
+    for s in range(1, a.stages + 1):
+        act = round_bf16(R.silu(R.conv3d(R.up2(act), round_bf16(w[f"C{s}"]), w[f"c{s}"])))
+    f = act @ w["wh"] + w["bh"] + R.log_prior(p, a.n_out, a.dx)
+    return np.exp(np.minimum(f, R.FMAX))
+
+
+@pytest.mark.parametrize("cfg_name", ["tiny", "full"])
+def test_network_forward_matches_reference(cfg_name):
+    cfg = tiny_cfg() if cfg_name == "tiny" else dict(base=4, hidden=384, ch=(64, 64, 64, 32, 16), dx=0.25,
+                                                     max_batch=2)
+    w = trained_like_weights(cfg, 3)
+    p = inputs.draw_nn_params(4, cfg["max_batch"])
+    say(f"case: network forward {cfg_name}")
+    with nn.Net(**cfg) as net:
+        net.set_params(w)
+        N = net.N
+        prm = torch.from_numpy(p.astype(np.float32)).cuda()
+        out = torch.empty((len(p), N, N, N), dtype=torch.float32, device="cuda")
+        net.forward(prm, out)
+        torch.cuda.synchronize()
+        psi = out.cpu().numpy().astype(np.float64)
+        outc = torch.empty((len(p), N, N, N), dtype=torch.complex64, device="cuda")
+        net.forward(prm, outc, complex_out=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(outc.real.cpu().numpy(), out.cpu().numpy())
+        assert float(outc.imag.abs().max()) == 0.0
+    p32 = p.astype(np.float32).astype(np.float64)
+    ref, _ = R.forward(bf16_round_weights(w), p32, ref_arch(cfg))
+    err = float(np.max(np.abs(psi - ref)) / np.max(np.abs(ref)))
+    emu = forward_bf16_storage(w, p32, ref_arch(cfg))
+    err_emu = float(np.max(np.abs(psi - emu)) / np.max(np.abs(emu)))
+    say(f"  psi rel err vs FP64 {err:.2e}, vs BF16-storage emulation {err_emu:.2e}")
+    assert err <= 2e-2
+    assert err_emu <= 5e-3
+
+
+def backward_bf16_storage(w, p, target, a):
+    """Reference gradients with BF16 storage at the GPU's points: weight matrices, stored
+    activations and pre-activations, and every propagated gradient (head output, input
+    gradients of the convolutions, pooled and gated gradients)."""
+    rb = round_bf16
+    n = p.shape[0]
+    W1, W2 = rb(w["W1"]), rb(w["W2"])
+    C = {s: rb(w[f"C{s}"]) for s in range(1, a.stages + 1)}
+    z0 = rb(R.features(p, a))
+    h1 = z0 @ W1.T + w["b1"]
+    pre1, a1 = rb(h1), rb(R.silu(h1))
+    h2 = a1 @ W2.T + w["b2"]
+    pre2 = rb(h2).reshape(n, a.base, a.base, a.base, a.ch[0])
+    act = rb(R.silu(h2)).reshape(pre2.shape)
+    us, pres = {}, {0: pre2}
+    for s in range(1, a.stages + 1):
+        us[s] = R.up2(act)
+        h = R.conv3d(us[s], C[s], w[f"c{s}"])
+        pres[s], act = rb(h), rb(R.silu(h))
+    f = act @ w["wh"] + w["bh"] + R.log_prior(p, a.n_out, a.dx)
+    psi = np.exp(np.minimum(f, R.FMAX))
+    g = {}
+    df = 2 * (psi - target) * a.dx ** 3 / n * psi * (f < R.FMAX)
+    g["wh"], g["bh"] = np.einsum("ndhw,ndhwc->c", df, act), np.array(df.sum())
+    dh = rb(df[..., None] * w["wh"] * R.silu_grad(pres[a.stages]))
+    for s in range(a.stages, 0, -1):
+        g[f"C{s}"], g[f"c{s}"] = R.conv3d_bwd_weight(dh, us[s]), dh.sum(axis=(0, 1, 2, 3))
+        dh = rb(R.pool2_sum(rb(R.conv3d_bwd_data(dh, C[s]))) * R.silu_grad(pres[s - 1]))
+    dh2 = dh.reshape(n, -1)
+    g["W2"], g["b2"] = dh2.T @ a1, dh2.sum(axis=0)
+    dh1 = rb((dh2 @ W2) * R.silu_grad(pre1))
+    g["W1"], g["b1"] = dh1.T @ z0, dh1.sum(axis=0)
+    return g
+
+
+def test_network_gradients_match_reference():
+    """Against the BF16-storage emulation (same rounding points; differences only from
+    FP32 summation order): 1.5e-2 per tensor.  Against plain FP64 the BF16 storage itself
+    costs 2-5% on this case, bound 0.1."""
+    cfg = tiny_cfg()
+    w = trained_like_weights(cfg, 5)
+    p = inputs.draw_nn_params(6, 4)
+    a = ref_arch(cfg)
+    wr = bf16_round_weights(w)
+    p32 = p.astype(np.float32).astype(np.float64)
+    psi_ref, _ = R.forward(wr, p32, a)
+    x = R.grid_axis(a.n_out, a.dx)
+    bump = 1 + 0.3 * np.cos(x)[None, :, None, None] * np.sin(0.7 * x)[None, None, :, None]
+    target = (psi_ref * bump).astype(np.float32)
+    with nn.Net(**cfg) as net:
+        net.set_params(w)
+        prm = torch.from_numpy(p.astype(np.float32)).cuda()
+        out = torch.empty((4, net.N, net.N, net.N), dtype=torch.float32, device="cuda")
+        net.forward(prm, out)
+        loss = net.loss_backward(torch.from_numpy(target).cuda())
+        g = nn.unflatten(net.get_grads(), net.shapes)
+    t64 = target.astype(np.float64)
+    _, cache = R.forward(wr, p32, a)
+    gref = R.backward(wr, cache, t64, a)
+    gemu = backward_bf16_storage(w, p32, t64, a)
+    lref = R.loss(cache["psi"], t64, a)
+    say(f"case: network gradients; loss gpu {loss:.6e} ref {lref:.6e}")
+    assert abs(loss - lref) <= 3e-2 * lref
+    for k, _ in net.shapes:
+        gk = np.asarray(g[k], dtype=np.float64)
+        e64 = float(np.linalg.norm(gk - gref[k]) / np.linalg.norm(gref[k]))
+        eem = float(np.linalg.norm(gk - gemu[k]) / np.linalg.norm(gemu[k]))
+        say(f"  {k}: rel err vs FP64 {e64:.2e}, vs BF16-storage emulation {eem:.2e}")
+        assert eem <= 1.5e-2 and e64 <= 0.1, k
+
+
+def test_adam_step_matches_reference():
+    cfg = tiny_cfg()
+    w = trained_like_weights(cfg, 9)
+    p = inputs.draw_nn_params(10, 3)
+    with nn.Net(**cfg) as net:
+        net.set_params(w)
+        prm = torch.from_numpy(p.astype(np.float32)).cuda()
+        out = torch.empty((3, net.N, net.N, net.N), dtype=torch.float32, device="cuda")
+        w0 = net.get_params().astype(np.float64)
+        m = np.zeros_like(w0)
+        v = np.zeros_like(w0)
+        for t in (1, 2, 3):
+            net.forward(prm, out)
+            net.loss_backward(torch.zeros_like(out), want_loss=False)
+            gv = net.get_grads().astype(np.float64)
+            net.adam_step(1e-3, t)
+            w1 = net.get_params().astype(np.float64)
+            want, m, v = R.adam(w0, gv, m, v, t, 1e-3)
+            err = float(np.max(np.abs(w1 - want)))
+            say(f"case: adam step {t}: max err {err:.2e}")
+            assert err <= 1e-6
+            w0 = w1
+
+
+def test_training_reduces_the_loss():
+    cfg = tiny_cfg()
+    a = ref_arch(cfg)
+    p = inputs.draw_nn_params(20, 4)
+    # targets: the prior reshaped by a smooth, parameter-dependent factor
+    x = R.grid_axis(8, cfg["dx"])
+    lp = R.log_prior(p, 8, cfg["dx"])
+    bump = np.exp(0.3 * np.tanh(np.log(p[:, 3]))[:, None, None, None] * np.cos(x)[None, :, None, None])
+    target = (np.exp(lp) * bump).astype(np.float32)
+    w = inputs.nn_init_weights(nn.param_shapes(cfg["base"], cfg["hidden"], cfg["ch"]), 21)
+    with nn.Net(**cfg) as net:
+        net.set_params(w)
+        prm = torch.from_numpy(p.astype(np.float32)).cuda()
+        tgt = torch.from_numpy(target).cuda()
+        out = torch.empty_like(tgt)
+        losses = []
+        for t in range(1, 301):
+            net.forward(prm, out)
+            losses.append(net.loss_backward(tgt))
+            net.adam_step(3e-3, t)
+    say(f"case: training loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert losses[-1] <= 0.1 * losses[0]
+    assert R.loss(np.exp(lp), target.astype(np.float64), a) == pytest.approx(losses[0], rel=1e-5)
+
+
+def test_state_and_argument_errors():
+    cfg = tiny_cfg()
+    with nn.Net(**cfg) as net:
+        with pytest.raises(nn.NNError):
+            net.loss_backward(torch.zeros((1, 8, 8, 8), device="cuda"))
+        prm = torch.ones((5, 4), device="cuda")
+        out = torch.empty((5, 8, 8, 8), device="cuda")
+        with pytest.raises(nn.NNError):
+            net.forward(prm, out)  # n > max_batch
+        with pytest.raises(nn.NNError):
+            net.set_params(np.zeros(3, dtype=np.float32))

@@ -364,3 +364,85 @@ def test_real_time_dt_order(split, order):
         res.append(o.psi.copy())
     r = np.max(np.abs(res[0] - res[1])) / np.max(np.abs(res[1] - res[2]))
     assert abs(math.log2(r) - order) < 0.2
+
+
+# ---------------------------------------------------------------- stationary-equation residual
+def _sine_mode(shape, modes):
+    out = np.ones(shape)
+    for a, (n, k) in enumerate(zip(shape, modes)):
+        s = [1, 1, 1]
+        s[a] = n
+        out = out * np.sin(np.arange(1, n + 1) * k * np.pi / (n + 1)).reshape(s)
+    return out
+
+
+def _sine_eig(shape, modes, d):
+    return sum(2.0 * np.sin(k * np.pi / (2 * (n + 1))) ** 2 / h ** 2 for n, k, h in zip(shape, modes, d))
+
+
+def test_residual_zero_on_discrete_eigenmodes():
+    """nu = 0, g = 0: products of Dirichlet sine modes are exact eigenvectors of -1/2 lap_h
+    with eigenvalue sum 2 sin^2(k pi / (2(n+1))) / d^2."""
+    from oracle.residual import residual
+    shape, d = (9, 7, 6), (0.3, 0.25, 0.4)
+    prm = dict(dx=d[0], dy=d[1], dz=d[2], nux=0.0, nuy=0.0, nuz=0.0, g=0.0)
+    for modes in [(1, 1, 1), (2, 3, 1), (4, 1, 5)]:
+        r, mu = residual(3.7 * _sine_mode(shape, modes), prm)
+        assert r <= 1e-12 * mu
+        assert abs(mu - _sine_eig(shape, modes, d)) <= 1e-12 * mu
+
+
+def test_residual_of_a_two_mode_mixture_closed_form():
+    """phi = a e1 + b e2 (orthonormal eigenvectors): mu = a^2 l1 + b^2 l2 and
+    res = |a b| |l1 - l2|."""
+    from oracle.residual import residual
+    shape, d = (8, 6, 7), (0.2, 0.3, 0.25)
+    prm = dict(dx=d[0], dy=d[1], dz=d[2], nux=0.0, nuy=0.0, nuz=0.0, g=0.0)
+    dV = np.prod(d)
+    e1, e2 = _sine_mode(shape, (1, 1, 1)), _sine_mode(shape, (3, 2, 1))
+    e1 /= np.sqrt(dV * (e1 ** 2).sum())
+    e2 /= np.sqrt(dV * (e2 ** 2).sum())
+    a, b = 0.8, 0.6
+    l1, l2 = _sine_eig(shape, (1, 1, 1), d), _sine_eig(shape, (3, 2, 1), d)
+    r, mu = residual(a * e1 + b * e2, prm)
+    assert abs(mu - (a * a * l1 + b * b * l2)) <= 1e-12 * mu
+    assert abs(r - a * b * abs(l1 - l2)) <= 1e-11 * mu
+
+
+def test_residual_matches_brute_force_on_a_tiny_grid():
+    """Every term of H written out point by point with explicit loops (trap, nonlinearity,
+    complex state)."""
+    from oracle.residual import residual
+    rng = np.random.default_rng(4)
+    nx, ny, nz = 4, 3, 5
+    prm = dict(dx=0.4, dy=0.5, dz=0.3, nux=1.3, nuy=0.7, nuz=2.1, g=17.0)
+    psi = rng.standard_normal((nx, ny, nz)) + 1j * rng.standard_normal((nx, ny, nz))
+    dV = prm["dx"] * prm["dy"] * prm["dz"]
+    phi = psi / np.sqrt(dV * np.sum(np.abs(psi) ** 2))
+    d = (prm["dx"], prm["dy"], prm["dz"])
+    nu = (prm["nux"], prm["nuy"], prm["nuz"])
+    dims = (nx, ny, nz)
+
+    def at(i, j, k):
+        return phi[i, j, k] if 0 <= i < nx and 0 <= j < ny and 0 <= k < nz else 0.0
+
+    h = np.zeros_like(phi)
+    for i in range(nx):
+        for j in range(ny):
+            for k in range(nz):
+                idx = (i, j, k)
+                v = 0.0
+                lap = 0.0
+                for a in range(3):
+                    x = (idx[a] - (dims[a] - 1) / 2.0) * d[a]
+                    v += 0.5 * nu[a] ** 2 * x * x
+                    up = list(idx)
+                    dn = list(idx)
+                    up[a] += 1
+                    dn[a] -= 1
+                    lap += (at(*up) + at(*dn) - 2 * phi[idx]) / d[a] ** 2
+                h[idx] = -0.5 * lap + v * phi[idx] + prm["g"] * abs(phi[idx]) ** 2 * phi[idx]
+    mu = (dV * np.sum(np.conj(phi) * h)).real
+    want = np.sqrt(dV * np.sum(np.abs(h - mu * phi) ** 2))
+    r, m = residual(psi, prm)
+    assert abs(m - mu) <= 1e-12 * abs(mu) and abs(r - want) <= 1e-12 * want
