@@ -99,8 +99,10 @@ int gp_set_psi(gp_ctx* c, void* psi_dev);
  * the imaginary-time renormalisation, and GP_FLAG_* bits.  Synchronises. */
 int gp_status(gp_ctx* c, int64_t* steps_done, double* mu_est, int32_t* flags);
 
-/* Imaginary-time propagation until |mu_n - mu_{n-K}| <= tol |mu_n|, mu evaluated every
- * check_every = K steps (K <= 0 selects ceil(0.25/dt)), at most max_steps steps.
+/* Imaginary-time propagation until |mu_n - mu_{n-K}| <= tol |mu_n| holds at two successive
+ * checks (one check can straddle a turning point of mu(t) when the start is already close),
+ * mu evaluated every check_every = K steps (K <= 0 selects ceil(0.25/dt)), at most
+ * max_steps steps.
  * Returns the steps taken and the final mu.  GP_OK also when max_steps is reached;
  * *converged tells which.  Synchronises at every check. */
 int gp_converge_imag(gp_ctx* c, double tol, int32_t check_every, int64_t max_steps,
@@ -160,8 +162,9 @@ int gp_batch_status(gp_batch* b, int64_t* steps_done, double* mu_est, int32_t* f
  * Zero exactly at a discrete ground state; used to judge a starting state before
  * imaginary-time propagation.  Synchronises. */
 int gp_batch_residual(gp_batch* b, double* res, double* mu);
-/* Imaginary time until every instance meets |mu_n - mu_{n-K}| <= tol |mu_n| (checked
- * every K steps, K <= 0 selects ceil(0.25/min dt)); converged instances are masked off
+/* Imaginary time until every instance meets |mu_n - mu_{n-K}| <= tol |mu_n| at two
+ * successive checks (every K steps, K <= 0 selects ceil(0.25/min dt)), as
+ * gp_converge_imag; converged instances are masked off
  * while the rest continue.  Per-instance steps taken, final mu and converged flag. */
 int gp_batch_converge_imag(gp_batch* b, double tol, int32_t check_every, int64_t max_steps,
                            int64_t* steps_taken, double* mu, int32_t* converged);

@@ -698,7 +698,7 @@ int gp_converge_imag(gp_ctx* c, double tol, int32_t check_every, int64_t max_ste
   if (K < 1) K = 1;
   int64_t done = 0;
   double prev = NAN, cur = NAN, e = 0;
-  int32_t conv = 0;
+  int32_t conv = 0, hits = 0;
   while (done < max_steps) {
     const int32_t n = (int32_t)std::min<int64_t>(K, max_steps - done);
     int rc = gp_step_imag(c, n);
@@ -706,7 +706,9 @@ int gp_converge_imag(gp_ctx* c, double tol, int32_t check_every, int64_t max_ste
     done += n;
     rc = gp_energy_mu(c, &e, &cur);
     if (rc) return rc;
-    if (std::isfinite(prev) && std::fabs(cur - prev) <= tol * std::fabs(cur)) {
+    // two successive checks within tol: one check can straddle a turning point of mu(t)
+    hits = (std::isfinite(prev) && std::fabs(cur - prev) <= tol * std::fabs(cur)) ? hits + 1 : 0;
+    if (hits >= 2) {
       conv = 1;
       break;
     }

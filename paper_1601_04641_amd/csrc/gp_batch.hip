@@ -1021,7 +1021,7 @@ int gp_batch_converge_imag(gp_batch* b, double tol, int32_t check_every, int64_t
   std::vector<double> prev(n, NAN), cur(n, NAN), e(n);
   std::vector<uint8_t> act(n, 1);
   std::vector<int64_t> taken(n, 0);
-  std::vector<int32_t> conv(n, 0);
+  std::vector<int32_t> conv(n, 0), hits(n, 0);
   int rc = bset_active(b, act.data());
   if (rc) return rc;
   int64_t done = 0;
@@ -1037,7 +1037,9 @@ int gp_batch_converge_imag(gp_batch* b, double tol, int32_t check_every, int64_t
     rc = GP_OK;
     for (int i = 0; i < n; ++i) {
       if (!act[i]) continue;
-      if (std::isfinite(prev[i]) && std::fabs(cur[i] - prev[i]) <= tol * std::fabs(cur[i])) {
+      // two successive checks within tol (as gp_converge_imag)
+      hits[i] = (std::isfinite(prev[i]) && std::fabs(cur[i] - prev[i]) <= tol * std::fabs(cur[i])) ? hits[i] + 1 : 0;
+      if (hits[i] >= 2) {
         conv[i] = 1;
         act[i] = 0;
         --remaining;

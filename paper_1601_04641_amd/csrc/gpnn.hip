@@ -31,7 +31,8 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr float kFMax = 10.0f;   // psi = exp(min(f, kFMax))
-constexpr int kChunk = 2048;     // positions per split-K block of the weight gradient
+constexpr int kChunkMin = 2048;  // fewest positions per split-K block of the weight gradient
+constexpr int kMaxChunks = 128;  // most split-K blocks (partial sums to reduce) per tap
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -136,11 +137,13 @@ k_conv(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const flo
 // Split-K weight gradient: block (chunk, tap, 64x64 tile of (cout, cin)); partial sums
 // over the chunk's positions written to part[chunk][tap][cout][cin].  Each 64-position
 // sub-tile of dy and of x (shifted by the tap, zero outside the grid) is staged in LDS
-// transposed ([channel][position]), so both MFMA operands are 16-byte LDS reads.
+// transposed ([channel][position]), so both MFMA operands are 16-byte LDS reads.  The
+// blocks of the centre tap and the first input-channel tile also sum the staged dy rows:
+// the bias gradient's partial sums, dbpart[chunk][cout] (nullable).
 template <int KS>
 __global__ void __launch_bounds__(256)
 k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, int64_t P, int D, int cin, int cout,
-        float* __restrict__ part) {
+        int64_t chunk, float* __restrict__ part, float* __restrict__ dbpart) {
   constexpr int LD = 72;  // 64 positions + 8 pad (row = 144 B, 16-byte aligned)
   __shared__ __align__(16) uint16_t sdy[64 * LD];
   __shared__ __align__(16) uint16_t sx[64 * LD];
@@ -150,10 +153,12 @@ k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, int64_t
   const int co0 = (blockIdx.z % cot) * 64, ci0 = (blockIdx.z / cot) * 64;
   const int nco = min(64, cout - co0), nci = min(64, cin - ci0);
   const int a = KS == 3 ? t / 9 - 1 : 0, b = KS == 3 ? (t / 3) % 3 - 1 : 0, c = KS == 3 ? t % 3 - 1 : 0;
-  const int64_t q0 = (int64_t)blockIdx.x * kChunk;
-  const int64_t q1 = min(P, q0 + kChunk);
+  const int64_t q0 = (int64_t)blockIdx.x * chunk;
+  const int64_t q1 = min(P, q0 + chunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, kq = lane >> 4;
+  const bool do_db = dbpart != nullptr && t == T / 2 && ci0 == 0;
+  float dbacc = 0.0f;  // channel threadIdx.x / 4, positions (threadIdx.x % 4) * 16 ... + 15
   f32x4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -192,6 +197,11 @@ k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, int64_t
       }
     }
     __syncthreads();
+    if (do_db) {
+      const uint16_t* row = sdy + (threadIdx.x >> 2) * LD + (threadIdx.x & 3) * 16;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) dbacc += bf2f(row[e]);
+    }
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
@@ -204,6 +214,12 @@ k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, int64_t
         acc[bi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[bi], 0, 0, 0);
       }
     }
+  }
+  if (do_db) {
+    dbacc += __shfl_xor(dbacc, 1);
+    dbacc += __shfl_xor(dbacc, 2);
+    const int co = threadIdx.x >> 2;
+    if ((threadIdx.x & 3) == 0 && co < nco) dbpart[(int64_t)blockIdx.x * cout + co0 + co] = dbacc;
   }
   float* out = part + ((int64_t)blockIdx.x * T + t) * (int64_t)cout * cin;
 #pragma unroll
@@ -226,35 +242,9 @@ k_reduce_chunks(const float* __restrict__ part, int nchunk, int64_t per_chunk, i
   const int i = (int)(e % cols);
   if (i >= keep) return;
   float s = 0.0f;
+#pragma unroll 8
   for (int k = 0; k < nchunk; ++k) s += part[(int64_t)k * per_chunk + e];
   out[(e / cols) * keep + i] = s;
-}
-
-// per-chunk column sums of dy [P][C] -> part[chunk][C]
-__global__ void __launch_bounds__(256)
-k_colsum(const uint16_t* __restrict__ dy, int64_t P, int C, float* __restrict__ part) {
-  __shared__ float red[256];
-  const int64_t q0 = (int64_t)blockIdx.x * kChunk, q1 = min(P, q0 + kChunk);
-  if (C >= 256) {
-    for (int ch = threadIdx.x; ch < C; ch += 256) {
-      float s = 0.0f;
-      for (int64_t q = q0; q < q1; ++q) s += bf2f(dy[q * C + ch]);
-      part[(int64_t)blockIdx.x * C + ch] = s;
-    }
-    return;
-  }
-  const int ns = 256 / C;  // position stripes
-  const int ch = threadIdx.x % C, st = threadIdx.x / C;
-  float s = 0.0f;
-  if (st < ns)
-    for (int64_t q = q0 + st; q < q1; q += ns) s += bf2f(dy[q * C + ch]);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x < C) {
-    float tot = 0.0f;
-    for (int k = 0; k < ns; ++k) tot += red[k * C + threadIdx.x];
-    part[(int64_t)blockIdx.x * C + threadIdx.x] = tot;
-  }
 }
 
 // nearest x2 upsampling, channels last, 8 channels (16 B) per thread
@@ -485,25 +475,32 @@ hipError_t launch_conv(int ks, int64_t P, int D, int cin, int cout, const uint16
   return hipGetLastError();
 }
 
+// positions per split-K block: at least kChunkMin, and at most kMaxChunks blocks per tap
+int64_t wgrad_chunk(int64_t P) {
+  const int64_t c = ((P + kMaxChunks - 1) / kMaxChunks + 63) / 64 * 64;
+  return c > kChunkMin ? c : kChunkMin;
+}
+int64_t wgrad_nch(int64_t P) { return (P + wgrad_chunk(P) - 1) / wgrad_chunk(P); }
+
 int64_t wgrad_part_floats(int ks, int64_t P, int cin, int cout) {
-  const int64_t nch = (P + kChunk - 1) / kChunk;
-  return nch * (int64_t)ks * ks * ks * cout * cin;
+  return wgrad_nch(P) * (int64_t)ks * ks * ks * cout * cin;
 }
 
-// dw[t][o][i < keep] (row stride keep) and db[o] (nullable) from dy [P][cout], x [P][cin]
+// dw[t][o][i < keep] (row stride keep) and db[o] (nullable) from dy [P][cout], x [P][cin];
+// part holds wgrad_part_floats, cpart wgrad_nch(P) * cout floats
 hipError_t launch_wgrad(int ks, int64_t P, int D, int cin, int cout, int keep, const uint16_t* dy, const uint16_t* x,
                         float* part, float* dw, float* cpart, float* db, hipStream_t st) {
-  const int nch = (int)((P + kChunk - 1) / kChunk);
+  const int64_t chunk = wgrad_chunk(P);
+  const int nch = (int)wgrad_nch(P);
   const int T = ks * ks * ks;
+  float* dbp = db ? cpart : nullptr;
   dim3 grid((unsigned)nch, (unsigned)T, (unsigned)(((cout + 63) / 64) * ((cin + 63) / 64)));
-  if (ks == 3) hipLaunchKernelGGL((k_wgrad<3>), grid, dim3(256), 0, st, dy, x, P, D, cin, cout, part);
-  else hipLaunchKernelGGL((k_wgrad<1>), grid, dim3(256), 0, st, dy, x, P, 1, cin, cout, part);
+  if (ks == 3) hipLaunchKernelGGL((k_wgrad<3>), grid, dim3(256), 0, st, dy, x, P, D, cin, cout, chunk, part, dbp);
+  else hipLaunchKernelGGL((k_wgrad<1>), grid, dim3(256), 0, st, dy, x, P, 1, cin, cout, chunk, part, dbp);
   const int64_t per = (int64_t)T * cout * cin;
   hipLaunchKernelGGL(k_reduce_chunks, dim3(nblk(per)), dim3(256), 0, st, part, nch, per, cin, keep, dw);
-  if (db) {
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nch), dim3(256), 0, st, dy, P, cout, cpart);
+  if (db)
     hipLaunchKernelGGL(k_reduce_chunks, dim3(nblk(cout)), dim3(256), 0, st, cpart, nch, (int64_t)cout, cout, cout, db);
-  }
   return hipGetLastError();
 }
 
@@ -631,7 +628,7 @@ int gpnn_create(const gpnn_arch* a, void* hip_stream, gpnn** out) {
     maxd = std::max(maxd, (int64_t)B * vol(D / 2) * a->ch[s - 1]);
     maxu = std::max(maxu, P * a->ch[s - 1]);
     maxpart = std::max(maxpart, wgrad_part_floats(3, P, a->ch[s - 1], a->ch[s]));
-    maxc = std::max(maxc, ((P + kChunk - 1) / kChunk) * a->ch[s]);
+    maxc = std::max(maxc, wgrad_nch(P) * a->ch[s]);
   }
   const int64_t PS = (int64_t)B * vol(m->N);
   const int64_t hblocks = (PS + 255) / 256;
@@ -813,7 +810,7 @@ int gpnn_conv_wgrad(int32_t ks, int32_t n, int32_t d, int32_t cin, int32_t cout,
   const int64_t P = ks == 3 ? (int64_t)n * vol(d) : n;
   hipStream_t st = (hipStream_t)hip_stream;
   float *part = nullptr, *cpart = nullptr;
-  const int64_t nch = (P + kChunk - 1) / kChunk;
+  const int64_t nch = wgrad_nch(P);
   if (hipMalloc((void**)&part, (size_t)wgrad_part_floats(ks, P, cin, cout) * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&cpart, (size_t)nch * cout * sizeof(float)) != hipSuccess) {
     (void)hipGetLastError();

@@ -178,12 +178,12 @@ def time_to_ground_state(torch, net, prm, tol, gate, batch, mu_ref, serial=True)
                                    mu_rel_err_max=float(np.max(np.abs(mu - mu_ref) / mu_ref)))
     log(f"[ttgs] gaussian batched: {res['gaussian_batched']}")
     # (c) network starts (inference + gate included), batched
-    gauss = gaussian_starts(torch, prm)  # fallback states, prepared before the clock
+    gauss = gaussian_starts(torch, prm)  # fallback states, built on the host like (a) and (b)
     prm_d = torch.from_numpy(np.asarray(prm, dtype=np.float32)).cuda()
-    with gp.Batch(gauss, probs, offs) as bg:
-        r_gauss, mu_gauss = bg.residual()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    with gp.Batch(gauss, probs, offs) as bg:
+        r_gauss, mu_gauss = bg.residual()
     infer(torch, net, prm_d, psi, batch)
     with gp.Batch(psi, probs, offs) as b:
         r_net, mu_net = b.residual()
@@ -192,9 +192,16 @@ def time_to_ground_state(torch, net, prm, tol, gate, batch, mu_ref, serial=True)
         pv, gv = psi.view(M, -1), gauss.view(M, -1)
         for i in bad:
             pv[i].copy_(gv[i])
+        t_gate = time.perf_counter() - t0
         st, mu, conv = b.converge_imag(tol=tol, check_every=0)
     torch.cuda.synchronize()
-    res["net_batched"] = dict(seconds=time.perf_counter() - t0, steps_mean=float(st.mean()),
+    elapsed = time.perf_counter() - t0
+    err_net = np.abs(mu - mu_ref) / mu_ref
+    worst = np.argsort(err_net)[::-1][:5]
+    res["net_worst"] = [dict(index=int(i), mu_rel_err=float(err_net[i]), steps=int(st[i]),
+                             prm=[float(v) for v in prm[i]], used_net=bool(use_net[i])) for i in worst]
+    res["net_mu_rel_err_quantiles"] = [float(np.quantile(err_net, q)) for q in (0.5, 0.9, 0.99, 1.0)]
+    res["net_batched"] = dict(seconds=elapsed, inference_and_gate_seconds=t_gate, steps_mean=float(st.mean()),
                               steps_max=int(st.max()), converged=int(np.sum(conv)),
                               fallbacks=int(len(bad)), gate=gate,
                               residual_net_median=float(np.median(r_net / np.abs(mu_net))),
@@ -210,7 +217,7 @@ def time_to_ground_state(torch, net, prm, tol, gate, batch, mu_ref, serial=True)
 
 
 def run(n_train=4096, n_test=512, epochs=40, batch=16, lr0=1e-3, data_tol=1e-8, tol=1e-7, gate=0.5,
-        serial=True, arch=None):
+        serial=True, arch=None, save_weights=None, load_weights=None):
     import torch
     gp.load()
     arch = arch or dict(base=4, hidden=384, ch=(64, 64, 64, 32, 16))
@@ -219,25 +226,31 @@ def run(n_train=4096, n_test=512, epochs=40, batch=16, lr0=1e-3, data_tol=1e-8, 
     out = dict(grid=N_GRID, dx=DX, dt=DT, n_train=n_train, n_test=n_test, epochs=epochs, batch=batch, lr0=lr0,
                data_tol=data_tol, tol=tol, arch=dict(arch, ch=list(arch["ch"])))
     t0 = time.perf_counter()
-    tgt, mu_train, st_train, cap_tr = ground_states(torch, prm_train, data_tol, tag="train data")
+    if load_weights is None:
+        tgt, mu_train, st_train, cap_tr = ground_states(torch, prm_train, data_tol, tag="train data")
     tgt_test, mu_test, st_test, cap_te = ground_states(torch, prm_test, data_tol, tag="test data")
-    out["data_capped"] = [cap_tr, cap_te]
     out["data_seconds"] = time.perf_counter() - t0
-    out["data_steps_mean"] = float(st_train.mean())
+    if load_weights is None:
+        out["data_capped"] = [cap_tr, cap_te]
+        out["data_steps_mean"] = float(st_train.mean())
     with nn.Net(dx=DX, max_batch=batch, **arch) as net:
         out["n_params"] = net.n_params
-        net.set_params(inputs.nn_init_weights(net.shapes, seed=0))
-        hist, tsec = train(torch, net, prm_train, tgt, epochs, batch, lr0)
-        out["train_seconds"] = tsec
-        out["loss_history"] = hist
-        e_tr = eval_l2(torch, net, prm_train[:512], tgt[:512], batch)
+        if load_weights is None:
+            net.set_params(inputs.nn_init_weights(net.shapes, seed=0))
+            hist, tsec = train(torch, net, prm_train, tgt, epochs, batch, lr0)
+            out["train_seconds"] = tsec
+            out["loss_history"] = hist
+            e_tr = eval_l2(torch, net, prm_train[:512], tgt[:512], batch)
+            out["rel_l2_train_median"] = float(np.median(e_tr))
+            del tgt
+            if save_weights:
+                np.save(save_weights, net.get_params())
+        else:
+            net.set_params(np.load(load_weights))
         e_te = eval_l2(torch, net, prm_test, tgt_test, batch)
-        out["rel_l2_train_median"] = float(np.median(e_tr))
         out["rel_l2_test_median"] = float(np.median(e_te))
         out["rel_l2_test_p90"] = float(np.percentile(e_te, 90))
-        log(f"[eval] relative L2: train median {np.median(e_tr):.2e}, test median {np.median(e_te):.2e}, "
-            f"p90 {np.percentile(e_te, 90):.2e}")
-        del tgt
+        log(f"[eval] relative L2: test median {np.median(e_te):.2e}, p90 {np.percentile(e_te, 90):.2e}")
         torch.cuda.empty_cache()
         out["time_to_ground_state"] = time_to_ground_state(torch, net, prm_test, tol, gate, batch, mu_test,
                                                             serial=serial)
@@ -254,8 +267,11 @@ def main(argv=None):
     ap.add_argument("--gate", type=float, default=0.5)
     ap.add_argument("--no-serial", action="store_true")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--save-weights", default=None, help="write the trained FP32 parameters (.npy)")
+    ap.add_argument("--load-weights", default=None, help="skip training; use these parameters (.npy)")
     a = ap.parse_args(argv)
-    r = run(a.train, a.test, a.epochs, a.batch, a.lr, gate=a.gate, serial=not a.no_serial)
+    r = run(a.train, a.test, a.epochs, a.batch, a.lr, gate=a.gate, serial=not a.no_serial,
+            save_weights=a.save_weights, load_weights=a.load_weights)
     txt = json.dumps(r, indent=1)
     if a.out:
         with open(a.out, "w") as f:
