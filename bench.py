@@ -9,7 +9,12 @@ z sweep.  psi is resident in HBM when the timed region starts.
 Prints ONE JSON line on stdout.  The roofline object prices the dominant kernel: its
 algorithmic bytes per launch (2 x 8 B per point for complex64: one read and one write of
 psi) over its mean duration from HIP events recorded on the library's stream during the
-timed region.  cpu_baseline times the CPU FP64 oracle on host cores on a bounded sample.
+timed region; `traffic` is the HBM bytes per launch from the committed counter runs
+(profiles/traffic.json) when present.  cpu_baseline times the CPU FP64 oracle on host
+cores on a bounded sample.  Sub-objects: `complex128` (the same steps in FP64),
+`batched` (256 uneven grids advanced by shared launches vs one solver after another) and
+`time_to_ground_state` (512 held-out problems: Gaussian starts serial and batched,
+learned warm starts batched).
 """
 from __future__ import annotations
 
@@ -44,6 +49,8 @@ def parse():
     ap.add_argument("--no-also-c128", dest="also_c128", action="store_false")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default line mapping")
+    ap.add_argument("--mapping", default=None,
+                    help="mx,swx,my,swy,segz,mz: use this line mapping instead of autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain device copy of known size (HBM counter calibration)")
@@ -52,6 +59,9 @@ def parse():
     ap.add_argument("--batch-n", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--batch-serial-steps", type=int, default=400)
+    ap.add_argument("--no-ttgs", action="store_true", help="skip the time-to-ground-state measurement")
+    ap.add_argument("--ttgs-n", type=int, default=512)
+    ap.add_argument("--weights", default=os.path.join(ROOT, "results", "warmstart_weights.npy"))
     return ap.parse_args()
 
 
@@ -74,7 +84,10 @@ def run_precision(torch, gp, inputs, w, prec, args):
     log(f"[bench] prepared state: mu={mu:.6f} E={e:.6f}")
     s = gp.Solver.from_workload(psi, w)
     s.set_g(w["g_quench"])
-    if not args.no_autotune:
+    if args.mapping:
+        s.set_mapping(*(int(v) for v in args.mapping.split(",")))
+        log(f"[bench] mapping set: {s.get_mapping()}")
+    elif not args.no_autotune:
         log(f"[bench] autotune: {s.autotune('real', steps=4)}")
     n0 = s.norm()
     s.step_real(args.warmup)
@@ -174,6 +187,24 @@ def run_batch(torch, gp, inputs, args):
             "kernels": kern, "mu_range": [float(np.min(mu)), float(np.max(mu))]}
 
 
+def run_ttgs(torch, args):
+    """Time to ground state at mu tolerance 1e-7 on 512 held-out problems of the learned
+    warm-start workload (64^3, dx = 0.25, dt = 0.00625, nu ~ U[0.5, 4]^3, g log-uniform
+    on [1, 1000], seed 2): Gaussian starts one solver after another, Gaussian starts
+    batched, and network starts (trained weights from results/, inference and residual
+    gate inside the clock) batched.  Reference mu: the same problems converged to 1e-8."""
+    from paper_1601_04641_amd import inputs, nn, warmstart as ws
+    prm = inputs.draw_nn_params(2, args.ttgs_n)
+    _, mu_ref, _, _ = ws.ground_states(torch, prm, 1e-8, tag="ttgs reference")
+    with nn.Net(dx=ws.DX, max_batch=16) as net:
+        net.set_params(np.load(args.weights))
+        r = ws.time_to_ground_state(torch, net, prm, 1e-7, 0.5, 16, mu_ref, serial=True)
+    torch.cuda.empty_cache()
+    r["workload"] = f"warmstart_64cube_dx0.25_{len(prm)}_heldout_seed2"
+    r["tol"] = 1e-7
+    return r
+
+
 def cpu_baseline(inputs, w, seconds):
     import oracle
     nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
@@ -234,7 +265,9 @@ def main():
     if os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
-            traffic = tj.get(f"{'c64' if precs[0] == gp.GP_C64 else 'c128'}:{dom}")
+            # counters are valid for the kernels they were taken on: same workload and mapping
+            if list(tj.get("mapping", [])) == list(main_r["mapping"]):
+                traffic = tj.get(f"{'c64' if precs[0] == gp.GP_C64 else 'c128'}:{dom}")
         except Exception:
             traffic = None
     out = {
@@ -267,6 +300,9 @@ def main():
                              "kernels": r["per_kernel"], "norm_drift": r["norm_drift"]}
     if not args.no_batch:
         out["batched"] = run_batch(torch, gp, inputs, args)
+    if not args.no_ttgs and os.path.exists(args.weights):
+        log("[bench] time to ground state (512 held-out problems, three starts)")
+        out["time_to_ground_state"] = run_ttgs(torch, args)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(inputs, w, args.cpu_seconds)
