@@ -39,13 +39,13 @@ __device__ __forceinline__ double dexp(double v) { return exp(v); }
 // x = k pi/2 + r with pi/2 split into three parts (each k * part exact inside an FMA),
 // |r| <= pi/4, then the Taylor series of sin and cos in r (through r^9 / r^10 in FP32,
 // r^17 / r^18 in FP64; truncation below 1e-10 resp. 1e-20 on [-pi/4, pi/4]), and the
-// quadrant k mod 4.  Worst error found on a dense sample of |x| <= 1e4 against the C
-// library: 1.4 ulp (FP32), 1.0 ulp (FP64).  Larger |x| take the library routine, kept
-// out of line so that it does not occupy registers in the unrolled sweep.  The phase of
-// one real-time step is usually far below 1/8; there the series is used directly.
-__device__ __noinline__ void sincos_far(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __noinline__ void sincos_far(double x, double* s, double* c) { sincos(x, s, c); }
-
+// quadrant k mod 4.  FP32 arguments beyond 1e4 are reduced in FP64 with the FP64 parts
+// (the residual of pi/2 after three FP64 parts is ~1e-49, so k stays exact to |x| ~ 1e15);
+// FP64 arguments use the same reduction up to |x| ~ 2^52.  Worst error found on a dense
+// sample of |x| <= 1e4 against the C library: 1.4 ulp (FP32), 1.0 ulp (FP64).  There is no
+// out-of-line fallback: a call inside the unrolled sweeps would force the calling
+// convention on every live register (94 instead of 77 VGPRs in the x sweep).  The phase
+// of one real-time step is usually far below 1/8; there the series is used directly.
 __device__ __forceinline__ void quadrant(int q, float sp, float cp, float* s, float* c) {
   float ss = (q & 1) ? cp : sp, cc = (q & 1) ? sp : cp;
   *s = (q & 2) ? -ss : ss;
@@ -57,6 +57,17 @@ __device__ __forceinline__ void quadrant(int q, double sp, double cp, double* s,
   *c = ((q + 1) & 2) ? -cc : cc;
 }
 
+// k mod 4 of an integer-valued double, without converting k itself to int
+__device__ __forceinline__ int quad_of(double k) { return (int)(k - 4.0 * floor(0.25 * k)); }
+
+// x = k pi/2 + r in FP64, |r| <= pi/4 (pi/2 = Q1 + Q2 + Q3, each part 53 bits)
+__device__ __forceinline__ double reduce_pio2(double x, double* k) {
+  *k = rint(x * 0.6366197723675814);  // 2/pi
+  double r = fma(-*k, 1.5707963267948966, x);
+  r = fma(-*k, 6.123233995736766e-17, r);
+  return fma(-*k, -1.4973849048591698e-33, r);
+}
+
 __device__ __forceinline__ void dsincos(float x, float* s, float* c) {
   if (fabsf(x) < 0.125f) {  // typical step: no reduction, series through x^5 / x^6
     const float x2 = x * x;  // truncation < (1/8)^7/7! / (1/8) = 7.6e-10 (sin), 1.5e-12 (cos)
@@ -64,21 +75,26 @@ __device__ __forceinline__ void dsincos(float x, float* s, float* c) {
     *c = fmaf(x2, fmaf(x2, fmaf(x2, -1.0f / 720.0f, 1.0f / 24.0f), -0.5f), 1.0f);
     return;
   }
-  if (fabsf(x) > 1.0e4f) {
-    sincos_far(x, s, c);
-    return;
+  float r;
+  int q;
+  if (fabsf(x) <= 1.0e4f) {
+    const float k = rintf(x * 0.636619772f);  // 2/pi
+    r = fmaf(-k, 1.57079637f, x);             // pi/2 = 1.57079637 - 4.37113883e-8 - 1.71512451e-15
+    r = fmaf(-k, -4.37113883e-08f, r);
+    r = fmaf(-k, -1.71512451e-15f, r);
+    q = (int)k & 3;
+  } else {
+    double k;
+    r = (float)reduce_pio2((double)x, &k);
+    q = quad_of(k);
   }
-  const float k = rintf(x * 0.636619772f);  // 2/pi
-  float r = fmaf(-k, 1.57079637f, x);       // pi/2 = 1.57079637 - 4.37113883e-8 - 1.71512451e-15
-  r = fmaf(-k, -4.37113883e-08f, r);
-  r = fmaf(-k, -1.71512451e-15f, r);
   const float r2 = r * r;
   const float ps = fmaf(r2, fmaf(r2, fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f), -1.0f / 6.0f);
   const float sp = fmaf(r * r2, ps, r);
   const float pc = fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -1.0f / 3628800.0f, 1.0f / 40320.0f), -1.0f / 720.0f),
                              1.0f / 24.0f), -0.5f);
   const float cp = fmaf(r2, pc, 1.0f);
-  quadrant((int)k & 3, sp, cp, s, c);
+  quadrant(q, sp, cp, s, c);
 }
 
 __device__ __forceinline__ void dsincos(double x, double* s, double* c) {
@@ -97,14 +113,8 @@ __device__ __forceinline__ void dsincos(double x, double* s, double* c) {
     *c = fma(x2, pc, 1.0);
     return;
   }
-  if (fabs(x) > 1.0e9) {
-    sincos_far(x, s, c);
-    return;
-  }
-  const double k = rint(x * 0.6366197723675814);  // 2/pi
-  double r = fma(-k, 1.5707963267948966, x);       // pi/2 in three parts
-  r = fma(-k, 6.123233995736766e-17, r);
-  r = fma(-k, -1.4973849048591698e-33, r);
+  double k;
+  const double r = reduce_pio2(x, &k);
   const double r2 = r * r;
   // ps = 1/3! - r^2/5! + ... - r^14/17!, sin r = r - r^3 ps; pc likewise, cos r = 1 - r^2 pc
   double ps = -1.0 / 355687428096000.0;               // -1/17!
@@ -126,7 +136,7 @@ __device__ __forceinline__ void dsincos(double x, double* s, double* c) {
   pc = fma(r2, pc, -1.0 / 24.0);                      // -1/4!
   pc = fma(r2, pc, 0.5);
   const double cp = fma(r2, -pc, 1.0);
-  quadrant((int)k & 3, sp, cp, s, c);
+  quadrant(quad_of(k), sp, cp, s, c);
 }
 
 // Potential + nonlinear step on one value (calcnu): p <- scale p, then

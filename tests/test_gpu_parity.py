@@ -185,6 +185,27 @@ def test_invalid_mapping_rejected():
         assert s.get_mapping() == before
 
 
+@pytest.mark.parametrize("prec,g", [(gp.GP_C128, 1e10), (gp.GP_C128, 1e14), (gp.GP_C64, 1e7), (gp.GP_C64, 1e9)])
+def test_large_real_time_phases(prec, g):
+    """One real-time step whose nonlinear phase tau g |psi|^2 reaches ~6e5..6e9 (complex128)
+    or ~6e2..6e4 rad (complex64): every argument reduction of the phase factor's sin/cos
+    is exercised.  The phase is computed from the stored precision's |psi|^2, so the bound
+    scales with the largest phase: 10 x theta x unit roundoff."""
+    nx, ny, nz = 16, 12, 10
+    prm = dict(nx=nx, ny=ny, nz=nz, dx=0.2, dy=0.2, dz=0.2, nux=0.0, nuy=0.0, nuz=0.0, g=g, dt=0.001)
+    psi0 = inputs.perturbed_psi(nx, ny, nz, 0.2, 0.2, 0.2, 1.0, 1.0, 1.0, seed=31, amp=0.3)
+    if prec == gp.GP_C64:
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    theta = prm["dt"] * g * float(np.max(np.abs(psi0) ** 2))
+    say(f"case: large phase prec {prec} g {g:.0e}: theta max {theta:.2e}")
+    out, _ = run_gpu(prm, psi0, prec, False, 1)
+    ref = run_ref(prm, psi0, False, 1).psi
+    err = rel_err(out, ref)
+    eps = 2.0 ** -53 if prec == gp.GP_C128 else 2.0 ** -24
+    say(f"  rel err {err:.2e} (bound {10 * theta * eps + 1e-12:.2e})")
+    assert err <= 10 * theta * eps + 1e-12
+
+
 # ----------------------------------------------------------------------------------------
 # full 512x480x448 shape: closed forms (any size) and one step against the oracle
 # ----------------------------------------------------------------------------------------
