@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default line mapping")
     ap.add_argument("--mapping", default=None,
                     help="mx,swx,my,swy,segz,mz: use this line mapping instead of autotuning")
+    ap.add_argument("--autotune-cache", default=os.path.join(ROOT, "results", "autotune_gfx950.txt"),
+                    help="autotuner cache (a hit applies the stored mapping, a miss tunes and appends)")
+    ap.add_argument("--autotune-steps", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain device copy of known size (HBM counter calibration)")
@@ -88,7 +91,7 @@ def run_precision(torch, gp, inputs, w, prec, args):
         s.set_mapping(*(int(v) for v in args.mapping.split(",")))
         log(f"[bench] mapping set: {s.get_mapping()}")
     elif not args.no_autotune:
-        log(f"[bench] autotune: {s.autotune('real', steps=4)}")
+        log(f"[bench] autotune: {s.autotune('real', steps=args.autotune_steps, cache_path=args.autotune_cache)}")
     n0 = s.norm()
     s.step_real(args.warmup)
     torch.cuda.synchronize()
