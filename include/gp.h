@@ -171,6 +171,15 @@ int gp_batch_converge_imag(gp_batch* b, double tol, int32_t check_every, int64_t
 /* Mapping shared by all instances: {m_x, sw_x, m_y, sw_y, m_z}; the z threads per line
  * follow per instance.  gp_batch_autotune times the candidates on the batch (psi and
  * state restored) and keeps the fastest. */
+/* Fused y and z sweeps (default off): for instances whose x-plane (ny x (nz+1) values)
+ * fits in one block's LDS and whose splitting is Lie, one kernel loads each x-plane once,
+ * solves its y and z lines in LDS and stores it: psi crosses HBM twice for y and z
+ * together instead of four times.  Same arithmetic per point, different rounding order
+ * from the separate sweeps (results agree to rounding, not bitwise).  gp_batch_autotune
+ * times both and keeps the faster.  get: whether fusion is enabled and how many instances
+ * use it; the z entry of gp_batch_get_timing covers the fused kernel. */
+int gp_batch_set_yz_fusion(gp_batch* b, int32_t enable);
+int gp_batch_get_yz_fusion(gp_batch* b, int32_t* enabled, int32_t* fused_instances);
 int gp_batch_get_mapping(gp_batch* b, int32_t map[5]);
 int gp_batch_set_mapping(gp_batch* b, const int32_t map[5]);
 int gp_batch_autotune(gp_batch* b, int32_t mode, int32_t steps, int32_t map_out[5]);

@@ -106,6 +106,189 @@ kb_sweep_z(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__
   }
 }
 
+// Crank-Nicolson solves of nl lines held in LDS (line l, element i at L0 + l * lstride +
+// i * stride, n points), S segments per line, thread t -> line t % nl, segment t / nl
+// (threads past nl * S only join the barriers).  The same elimination as the register
+// sweeps: each segment runs the constant-pivot recurrences from a zero start, the
+// segments' affine maps are composed through small shared arrays, and running powers of
+// a fix up the segment values; the Sherman-Morrison head correction u_i += omega_i u_0
+// (i < nw) comes last.  Boundary neighbours are read before any value is overwritten.
+// Every thread of the block must call this (it contains barriers).
+template <typename R, bool CC>
+__device__ __forceinline__ void lds_lines_solve(typename VecOf<R>::T* L0, int lstride, int stride, int n, int nl,
+                                                int S, const Coef<typename VecOf<R>::T>& cf,
+                                                const typename VecOf<R>::T* __restrict__ omega, int nw,
+                                                typename VecOf<R>::T* sB, typename VecOf<R>::T* sU,
+                                                typename VecOf<R>::T* sPw) {
+  typedef typename VecOf<R>::T V;
+  const int t = threadIdx.x;
+  const bool act = t < nl * S;
+  const int line = act ? t % nl : 0, q = act ? t / nl : 0;
+  const int m = (n + S - 1) / S;
+  const int start = min(n, q * m), end = min(n, start + m);
+  V* L = L0 + (int64_t)line * lstride;
+  V pl = vzero<V>(), pr = vzero<V>();
+  if (act) {
+    if (start > 0 && start < n) pl = L[(start - 1) * stride];
+    if (end < n) pr = L[end * stride];
+  }
+  __syncthreads();
+  // forward recurrence from d_{start-1} = 0; B = d at the segment end, Pw = a^len
+  if (act) {
+    V prev = pl, d = vzero<V>(), pw = vone<V>();
+    V cur = start < end ? L[start * stride] : vzero<V>();
+    for (int i = start; i < end; ++i) {
+      const V nxt = (i + 1 < end) ? L[(i + 1) * stride] : pr;
+      d = fwd_point<CC, R, V>(cf, prev, nxt, d, cur);
+      L[i * stride] = d;
+      pw = cmul<CC>(cf.a, pw);
+      prev = cur;
+      cur = nxt;
+    }
+    sB[t] = d;
+    sPw[t] = pw;
+  }
+  __syncthreads();
+  // true d_{start-1}: compose the earlier segments' maps D -> a^m D + B_r; add a^(k+1) D
+  if (act && q > 0) {
+    V D = vzero<V>();
+    for (int r = 0; r < q; ++r) D = cfma<CC>(sPw[r * nl + line], D, sB[r * nl + line]);
+    V rr = D;
+    for (int i = start; i < end; ++i) {
+      rr = cmul<CC>(cf.a, rr);
+      L[i * stride] = vadd(L[i * stride], rr);
+    }
+  }
+  __syncthreads();
+  // backward recurrence from u_end = 0; U = u at the segment start
+  if (act) {
+    V u = vzero<V>();
+    for (int i = end - 1; i >= start; --i) {
+      u = cfma<CC>(cf.a, u, L[i * stride]);
+      L[i * stride] = u;
+    }
+    sU[t] = u;
+  }
+  __syncthreads();
+  // true u_end: compose the later segments' maps U -> u0_start + a^len U; add a^(end-i) U
+  if (act && q < S - 1) {
+    V U = vzero<V>();
+    for (int r = S - 1; r > q; --r) U = cfma<CC>(sPw[r * nl + line], U, sU[r * nl + line]);
+    V rr = U;
+    for (int i = end - 1; i >= start; --i) {
+      rr = cmul<CC>(cf.a, rr);
+      L[i * stride] = vadd(L[i * stride], rr);
+    }
+  }
+  __syncthreads();
+  if (act && q == 0 && nw > 0) {
+    const V u0 = L[0];
+    for (int i = 0; i < nw; ++i) L[i * stride] = cfma<CC>(omega[i], u0, L[i * stride]);
+  }
+  __syncthreads();
+}
+
+// segments per line for nl lines of n points on 256 threads: a power of two with
+// nl * S <= 256 and at least 4 points per segment
+__device__ __forceinline__ int lds_segments(int nl, int n) {
+  int S = 1;
+  while (nl * S * 2 <= 256 && (n + 2 * S - 1) / (2 * S) >= 4) S *= 2;
+  return S;
+}
+
+// Fused y and z sweeps of one x-plane of one instance (the plane [y][z] is contiguous in
+// psi): load the plane into LDS (row pitch nz + 1, so the z lines of consecutive threads
+// fall in different banks), solve the nz y-lines, then the ny z-lines, store, and
+// (imaginary time) the FP64 sum |psi|^2 of the plane.  psi crosses HBM twice per step for
+// y and z together instead of four times.
+template <typename R, bool CC, bool NORM>
+__global__ void __launch_bounds__(256)
+kb_sweep_yz(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst, const BWork* __restrict__ work,
+            const typename VecOf<R>::T* __restrict__ omega_all, double* __restrict__ partials) {
+  typedef typename VecOf<R>::T V;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[4];
+  __shared__ V sB[256], sU[256], sPw[256];
+  V* plane = reinterpret_cast<V*>(smem_raw);
+  const BWork wk = work[blockIdx.x];
+  const BInst& I = inst[wk.inst];
+  if (!I.active) {
+    if (NORM && threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+    return;
+  }
+  constexpr int mode = CC ? 1 : 0;
+  const int ny = I.ny, nz = I.nz, pitch = nz + 1;
+  const int np = ny * nz;
+  V* g = psi_all + I.off + (int64_t)wk.blk * np;
+  // plane in: 16-byte units (E values each), 8 loads in flight per thread; a unit never
+  // straddles a row when nz is a multiple of E (else the scalar loop)
+  constexpr int E = 16 / (int)sizeof(V);
+  const bool vec = (nz % E) == 0 && ((I.off + (int64_t)wk.blk * np) % E) == 0;
+  if (vec) {
+    const int nu = np / E;
+    const uint4* g4 = reinterpret_cast<const uint4*>(g);
+    for (int base = threadIdx.x; base < nu; base += 256 * 8) {
+      uint4 r[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (base + k * 256 < nu) r[k] = g4[base + k * 256];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int u = base + k * 256;
+        if (u < nu) {
+          const int q = u * E;
+          const V* e = reinterpret_cast<const V*>(&r[k]);
+          V* dst = plane + (q / nz) * pitch + q % nz;
+#pragma unroll
+          for (int h = 0; h < E; ++h) dst[h] = e[h];
+        }
+      }
+    }
+  } else {
+    for (int q = threadIdx.x; q < np; q += 256) plane[(q / nz) * pitch + q % nz] = g[q];
+  }
+  __syncthreads();
+  {
+    const double* c = I.coef[mode][1];
+    const Coef<V> cf{dval<R>(c), dval<R>(c + 2), dval<R>(c + 4)};
+    lds_lines_solve<R, CC>(plane, 1, pitch, ny, nz, lds_segments(nz, ny), cf, omega_all + I.omega_off[mode][1],
+                           I.nw[mode][1], sB, sU, sPw);
+  }
+  {
+    const double* c = I.coef[mode][2];
+    const Coef<V> cf{dval<R>(c), dval<R>(c + 2), dval<R>(c + 4)};
+    lds_lines_solve<R, CC>(plane, pitch, 1, nz, ny, lds_segments(ny, nz), cf, omega_all + I.omega_off[mode][2],
+                           I.nw[mode][2], sB, sU, sPw);
+  }
+  double acc = 0.0;
+  if (vec) {
+    const int nu = np / E;
+    uint4* g4 = reinterpret_cast<uint4*>(g);
+    for (int u = threadIdx.x; u < nu; u += 256) {
+      const int q = u * E;
+      uint4 w;
+      V* e = reinterpret_cast<V*>(&w);
+      const V* src = plane + (q / nz) * pitch + q % nz;
+#pragma unroll
+      for (int h = 0; h < E; ++h) {
+        e[h] = src[h];
+        if (NORM) acc += (double)e[h].x * (double)e[h].x + (double)e[h].y * (double)e[h].y;
+      }
+      g4[u] = w;
+    }
+  } else {
+    for (int q = threadIdx.x; q < np; q += 256) {
+      const V u = plane[(q / nz) * pitch + q % nz];
+      g[q] = u;
+      if (NORM) acc += (double)u.x * (double)u.x + (double)u.y * (double)u.y;
+    }
+  }
+  if (NORM) {
+    const double t = block_sum_256(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  }
+}
+
 // Sherman-Morrison head correction of x or y lines for instances whose correction is
 // longer than a segment (m points): one thread per line, lw lines per block (the line
 // blocks of the sweep's work table).
@@ -422,8 +605,12 @@ struct gp_batch {
   double* vd = nullptr;    // FP64 potentials, same layout
   double* a2 = nullptr;    // FP64 coordinate squares, same layout
   void* omega = nullptr;   // storage precision, per instance [mode][axis]
-  BWork *wx = nullptr, *wy = nullptr, *wz = nullptr, *wo = nullptr;
-  int nbx = 0, nby = 0, nbz = 0, nbo = 0;
+  BWork *wx = nullptr, *wy = nullptr, *wz = nullptr, *wo = nullptr, *wyz = nullptr;
+  int nbx = 0, nby = 0, nbz = 0, nbo = 0, nbyz = 0;
+  int yz_fuse = 0;          // fuse the y and z sweeps of instances whose x-plane fits in LDS
+  int nfused = 0;           // instances on the fused path
+  size_t max_lds = 65536;   // dynamic LDS per block available to the fused kernel
+  size_t ldsyz = 0;
   int thrx = 64, thry = 64;
   bool need_hc[2][2] = {{false, false}, {false, false}};  // [mode][axis]: nw > m somewhere
   size_t ldsx = 0, ldsy = 0, ldsz = 0;
@@ -489,6 +676,7 @@ void bfree(gp_batch* b) {
   (void)hipFree(b->wy);
   (void)hipFree(b->wz);
   (void)hipFree(b->wo);
+  (void)hipFree(b->wyz);
   (void)hipFree(b->zpart);
   (void)hipFree(b->opart);
   (void)hipFree(b->oout);
@@ -525,8 +713,11 @@ int configure(gp_batch* b) {
     return GP_ERR_INVALID;
   const bool f32 = b->prec == GP_C64;
   std::vector<BInst> hi(b->n);
-  std::vector<BWork> wx, wy, wz, wo;
+  std::vector<BWork> wx, wy, wz, wo, wyz;
+  std::vector<int> yzb0(b->n, 0), yzb1(b->n, 0);
   std::vector<unsigned char> omega;
+  size_t ldsyz = 0;
+  int nfused = 0;
   bool need_hc[2][2] = {{false, false}, {false, false}};
   int wavesx = 1, wavesy = 1;
   size_t ldsz = 0;
@@ -554,12 +745,16 @@ int configure(gp_batch* b) {
     while (seg < 64 && (int64_t)seg * mz < p.nz) seg <<= 1;
     if ((int64_t)seg * mz < p.nz) return GP_ERR_UNSUPPORTED;
     I.nseg[2] = seg;
-    if (cdiv(I.nseg[0], swx) > 16 || cdiv(I.nseg[1], swy) > 16) return GP_ERR_UNSUPPORTED;
+    const size_t lyz = (size_t)p.ny * (p.nz + 1) * b->esize;
+    const bool fuse = b->yz_fuse && p.split == GP_SPLIT_LIE && p.ny <= 256 && p.nz <= 256 && lyz <= b->max_lds;
+    if (cdiv(I.nseg[0], swx) > 16 || (!fuse && cdiv(I.nseg[1], swy) > 16)) return GP_ERR_UNSUPPORTED;
     const size_t lz = (size_t)4 * (64 / seg) * p.nz * b->esize;
-    if (lz + 512 > 65536) return GP_ERR_UNSUPPORTED;
-    ldsz = std::max(ldsz, lz);
+    if (!fuse && lz + 512 > 65536) return GP_ERR_UNSUPPORTED;
+    if (!fuse) ldsz = std::max(ldsz, lz);
+    if (fuse) ldsyz = std::max(ldsyz, lyz);
+    nfused += fuse ? 1 : 0;
     wavesx = std::max(wavesx, cdiv(I.nseg[0], swx));
-    wavesy = std::max(wavesy, cdiv(I.nseg[1], swy));
+    if (!fuse) wavesy = std::max(wavesy, cdiv(I.nseg[1], swy));
     const int m[3] = {mx, my, mz};
     for (int mode = 0; mode < 2; ++mode)
       for (int a = 0; a < 3; ++a) {
@@ -581,14 +776,26 @@ int configure(gp_batch* b) {
     const int bz = cdiv((int64_t)p.nx * p.ny, 4 * (64 / seg));
     const int bo = cdiv((int64_t)p.nx * p.ny * p.nz, gpk::kChunk);
     for (int k = 0; k < bx; ++k) wx.push_back({i, k});
-    for (int k = 0; k < by; ++k) wy.push_back({i, k});
-    I.zb0 = (int)wz.size();
-    for (int k = 0; k < bz; ++k) wz.push_back({i, k});
-    I.zb1 = (int)wz.size();
+    if (fuse) {
+      yzb0[i] = (int)wyz.size();
+      for (int k = 0; k < p.nx; ++k) wyz.push_back({i, k});  // one block per x-plane
+      yzb1[i] = (int)wyz.size();
+      I.zb0 = I.zb1 = -1;  // set below: fused partials follow the z-sweep partials
+    } else {
+      for (int k = 0; k < by; ++k) wy.push_back({i, k});
+      I.zb0 = (int)wz.size();
+      for (int k = 0; k < bz; ++k) wz.push_back({i, k});
+      I.zb1 = (int)wz.size();
+    }
     I.ob0 = (int)wo.size();
     for (int k = 0; k < bo; ++k) wo.push_back({i, k});
     I.ob1 = (int)wo.size();
   }
+  for (int i = 0; i < b->n; ++i)
+    if (hi[i].zb0 < 0) {
+      hi[i].zb0 = (int)wz.size() + yzb0[i];
+      hi[i].zb1 = (int)wz.size() + yzb1[i];
+    }
   // potential and coordinate tables
   std::vector<double> vd(voff), a2(voff);
   std::vector<float> vf(voff);
@@ -622,8 +829,25 @@ int configure(gp_batch* b) {
   (void)hipFree(b->omega);
   b->omega = om;
   if ((rc = upload(b, &b->wx, wx)) || (rc = upload(b, &b->wy, wy)) || (rc = upload(b, &b->wz, wz)) ||
-      (rc = upload(b, &b->wo, wo)) || (rc = upload(b, &b->dinst, hi)))
+      (rc = upload(b, &b->wo, wo)) || (rc = upload(b, &b->wyz, wyz)) || (rc = upload(b, &b->dinst, hi)))
     return rc;
+  if (ldsyz > 65536) {  // opt in to the large LDS allocation for the kernels this batch uses
+    hipError_t e;
+    if (f32) {
+      e = hipFuncSetAttribute((const void*)gpk::kb_sweep_yz<float, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsyz);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)gpk::kb_sweep_yz<float, true, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsyz);
+    } else {
+      e = hipFuncSetAttribute((const void*)gpk::kb_sweep_yz<double, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsyz);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)gpk::kb_sweep_yz<double, true, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsyz);
+    }
+    if (e != hipSuccess) return bfail(b, e, "hipFuncSetAttribute");
+  }
   b->hinst = hi;
   for (int mode = 0; mode < 2; ++mode)
     for (int a = 0; a < 2; ++a) b->need_hc[mode][a] = need_hc[mode][a];
@@ -631,6 +855,9 @@ int configure(gp_batch* b) {
   b->nby = (int)wy.size();
   b->nbz = (int)wz.size();
   b->nbo = (int)wo.size();
+  b->nbyz = (int)wyz.size();
+  b->ldsyz = ldsyz;
+  b->nfused = nfused;
   b->thrx = wavesx * 64;
   b->thry = wavesy * 64;
   b->ldsx = (size_t)3 * wavesx * swx * (64 / swx) * b->esize;
@@ -639,7 +866,7 @@ int configure(gp_batch* b) {
   (void)hipFree(b->zpart);
   (void)hipFree(b->opart);
   b->zpart = b->opart = nullptr;
-  if ((rc = bdalloc(b, &b->zpart, (size_t)b->nbz * sizeof(double)))) return rc;
+  if ((rc = bdalloc(b, &b->zpart, (size_t)(b->nbz + b->nbyz + 1) * sizeof(double)))) return rc;
   if ((rc = bdalloc(b, &b->opart, (size_t)b->nbo * 9 * sizeof(double)))) return rc;
   return GP_OK;
 }
@@ -711,14 +938,41 @@ int benqueue_step(gp_batch* b, int mode, hipStream_t s) {
     return e;
   });
   if (rc) return rc;
-  rc = btimed(b, s, 1, [&](hipStream_t t) {
-    hipError_t e = gpk::launch_b_lines(b->prec, cc, ay, t);
-    if (e == hipSuccess && b->need_hc[mode][1]) e = head(ay, t);
-    return e;
-  });
-  if (rc) return rc;
-  rc = btimed(b, s, 2, [&](hipStream_t t) { return gpk::launch_b_z(b->prec, cc, az, t); });
-  if (rc) return rc;
+  if (b->nby > 0) {
+    rc = btimed(b, s, 1, [&](hipStream_t t) {
+      hipError_t e = gpk::launch_b_lines(b->prec, cc, ay, t);
+      if (e == hipSuccess && b->need_hc[mode][1]) e = head(ay, t);
+      return e;
+    });
+    if (rc) return rc;
+  }
+  if (b->nbz > 0) {
+    rc = btimed(b, s, 2, [&](hipStream_t t) { return gpk::launch_b_z(b->prec, cc, az, t); });
+    if (rc) return rc;
+  }
+  if (b->nbyz > 0) {  // fused y+z sweeps (timed with the z sweeps)
+    rc = btimed(b, s, 2, [&](hipStream_t t) {
+      double* part = b->zpart + b->nbz;
+      const dim3 grid(b->nbyz), blk(256);
+      if (b->prec == GP_C64) {
+        if (cc)
+          hipLaunchKernelGGL((gpk::kb_sweep_yz<float, true, false>), grid, blk, b->ldsyz, t, (float2*)b->psi, b->dinst,
+                             b->wyz, (const float2*)b->omega, part);
+        else
+          hipLaunchKernelGGL((gpk::kb_sweep_yz<float, false, true>), grid, blk, b->ldsyz, t, (float2*)b->psi, b->dinst,
+                             b->wyz, (const float2*)b->omega, part);
+      } else {
+        if (cc)
+          hipLaunchKernelGGL((gpk::kb_sweep_yz<double, true, false>), grid, blk, b->ldsyz, t, (double2*)b->psi,
+                             b->dinst, b->wyz, (const double2*)b->omega, part);
+        else
+          hipLaunchKernelGGL((gpk::kb_sweep_yz<double, false, true>), grid, blk, b->ldsyz, t, (double2*)b->psi,
+                             b->dinst, b->wyz, (const double2*)b->omega, part);
+      }
+      return hipGetLastError();
+    });
+    if (rc) return rc;
+  }
   if (mode == 0) {
     rc = btimed(b, s, 3, [&](hipStream_t t) {
       hipLaunchKernelGGL(gpk::kb_finalize_norm, dim3(b->n), dim3(256), 0, t, b->zpart, b->dinst, b->st);
@@ -858,6 +1112,13 @@ int gp_batch_init(const gp_params* p, int32_t n, void* psi_dev, const int64_t* o
       (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
     (void)hipGetLastError();
     rc = GP_ERR_INVALID;
+  }
+  if (rc == GP_OK) {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) == hipSuccess && lds > 0)
+      b->max_lds = (size_t)lds - 3 * 256 * 16 - 512;  // the fused kernel's static shared arrays
+    else
+      (void)hipGetLastError();
   }
   if (rc == GP_OK) rc = configure(b);
   if (rc == GP_OK) rc = bdalloc(b, &b->st, (size_t)n * sizeof(DevState));
@@ -1061,6 +1322,26 @@ int gp_batch_converge_imag(gp_batch* b, double tol, int32_t check_every, int64_t
   return rc;
 }
 
+int gp_batch_set_yz_fusion(gp_batch* b, int32_t enable) {
+  if (!b) return GP_ERR_INVALID;
+  BCHK(b, hipStreamSynchronize(b->stream));
+  const int old = b->yz_fuse;
+  b->yz_fuse = enable ? 1 : 0;
+  int rc = configure(b);
+  if (rc) {
+    b->yz_fuse = old;
+    (void)configure(b);
+  }
+  return rc;
+}
+
+int gp_batch_get_yz_fusion(gp_batch* b, int32_t* enabled, int32_t* fused_instances) {
+  if (!b) return GP_ERR_INVALID;
+  if (enabled) *enabled = b->yz_fuse;
+  if (fused_instances) *fused_instances = b->nfused;
+  return GP_OK;
+}
+
 int gp_batch_get_mapping(gp_batch* b, int32_t map[5]) {
   if (!b || !map) return GP_ERR_INVALID;
   for (int q = 0; q < 5; ++q) map[q] = b->map[q];
@@ -1126,6 +1407,8 @@ int gp_batch_autotune(gp_batch* b, int32_t mode, int32_t steps, int32_t map_out[
   int best[5];
   for (int q = 0; q < 5; ++q) best[q] = b->map[q];
   double best_ms[3] = {1e300, 1e300, 1e300};
+  const int fuse_in = b->yz_fuse;
+  b->yz_fuse = 0;  // tune the separate sweeps' mappings first (set_mapping reconfigures)
   auto trial = [&](int kind, const int* cand, double* ms) -> int {
     int rc2 = gp_batch_set_mapping(b, cand);
     if (rc2) return rc2;
@@ -1178,6 +1461,26 @@ int gp_batch_autotune(gp_batch* b, int32_t mode, int32_t steps, int32_t map_out[
     }
   }
   if (rc == GP_OK) rc = gp_batch_set_mapping(b, best);
+  // fused y+z sweeps against separate ones: whole-step time, keep the faster
+  if (rc == GP_OK) {
+    double step_ms[2] = {1e300, 1e300};
+    const int fuse0 = fuse_in;
+    for (int f = 0; f < 2 && rc == GP_OK; ++f) {
+      if ((rc = gp_batch_set_yz_fusion(b, f))) break;
+      if ((rc = brun(b, mode, 1)) || (rc = gp_batch_set_timing(b, 1)) || (rc = brun(b, mode, steps))) break;
+      double mean[5];
+      int64_t cnt[5];
+      if ((rc = gp_batch_get_timing(b, mean, cnt)) || (rc = gp_batch_set_timing(b, 0))) break;
+      double tot = 0.0;
+      for (int k = 0; k < 4; ++k) tot += mean[k] * (double)cnt[k];
+      step_ms[f] = tot / steps;
+    }
+    if (rc == GP_OK) rc = gp_batch_set_yz_fusion(b, step_ms[1] <= step_ms[0] ? 1 : 0);
+    else (void)gp_batch_set_yz_fusion(b, fuse0);
+  } else {
+    b->yz_fuse = fuse_in;
+    (void)configure(b);
+  }
   (void)hipMemcpy(b->psi, saved, bytes, hipMemcpyDeviceToDevice);
   (void)hipMemcpy(b->st, st0.data(), b->n * sizeof(DevState), hipMemcpyHostToDevice);
   (void)hipFree(saved);

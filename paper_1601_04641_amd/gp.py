@@ -29,7 +29,7 @@ EXPORTS = ("gp_init", "gp_destroy", "gp_step_imag", "gp_step_real", "gp_norm", "
            "gp_batch_init", "gp_batch_destroy", "gp_batch_step_imag", "gp_batch_step_real",
            "gp_batch_norm", "gp_batch_energy_mu", "gp_batch_rms", "gp_batch_raw_sums",
            "gp_batch_status", "gp_batch_residual", "gp_batch_converge_imag", "gp_batch_get_mapping",
-           "gp_batch_set_mapping", "gp_batch_autotune", "gp_batch_set_timing",
+           "gp_batch_set_mapping", "gp_batch_autotune", "gp_batch_set_yz_fusion", "gp_batch_get_yz_fusion", "gp_batch_set_timing",
            "gp_batch_get_timing", "gp_batch_last_error")
 
 
@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
         "gp_batch_get_mapping": [vp, P(i32)],
         "gp_batch_set_mapping": [vp, P(i32)],
         "gp_batch_autotune": [vp, i32, i32, P(i32)],
+        "gp_batch_set_yz_fusion": [vp, i32],
+        "gp_batch_get_yz_fusion": [vp, P(i32), P(i32)],
         "gp_batch_set_timing": [vp, i32],
         "gp_batch_get_timing": [vp, P(d), P(i64)],
     }
@@ -362,6 +364,15 @@ class Batch:
         self._chk(self._L.gp_batch_autotune(self._h, 0 if mode == "imag" else 1, int(steps), out),
                   "gp_batch_autotune")
         return list(out)
+
+    def set_yz_fusion(self, on: bool):
+        self._chk(self._L.gp_batch_set_yz_fusion(self._h, int(bool(on))), "gp_batch_set_yz_fusion")
+
+    def get_yz_fusion(self):
+        """(enabled, number of instances on the fused y+z path)"""
+        e, f = ctypes.c_int32(), ctypes.c_int32()
+        self._chk(self._L.gp_batch_get_yz_fusion(self._h, ctypes.byref(e), ctypes.byref(f)), "gp_batch_get_yz_fusion")
+        return bool(e.value), f.value
 
     def set_timing(self, on):
         self._chk(self._L.gp_batch_set_timing(self._h, int(bool(on))), "gp_batch_set_timing")

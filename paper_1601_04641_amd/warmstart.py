@@ -50,8 +50,8 @@ def _offsets(m):
     return np.arange(m, dtype=np.int64) * N_GRID ** 3
 
 
-def gaussian_starts(torch, prm, out=None):
-    host = inputs.gaussian_cube_batch(prm, N_GRID, DX)
+def gaussian_starts(torch, prm, out=None, complex128=False):
+    host = inputs.gaussian_cube_batch(prm, N_GRID, DX, dtype=np.complex128 if complex128 else np.complex64)
     t = torch.from_numpy(host.reshape(-1))
     if out is None:
         return t.to("cuda")
@@ -59,10 +59,11 @@ def gaussian_starts(torch, prm, out=None):
     return out
 
 
-def ground_states(torch, prm, tol, chunk=512, max_steps=40000, tag="data"):
+def ground_states(torch, prm, tol, chunk=512, max_steps=40000, tag="data", complex128=False):
     """Ground states (FP32 real part, [M, n, n, n] on the device), their mu, the steps
     each took and how many stopped at max_steps instead of meeting tol (complex64 storage
-    puts a noise floor near 1e-9 on the relative mu change of some problems)."""
+    puts a noise floor near 1e-9 on the relative mu change of some problems; complex128
+    runs the same scheme in FP64, for reference values)."""
     M = len(prm)
     tgt = torch.empty((M, N_GRID, N_GRID, N_GRID), dtype=torch.float32, device="cuda")
     mus, steps = np.zeros(M), np.zeros(M, dtype=np.int64)
@@ -70,11 +71,11 @@ def ground_states(torch, prm, tol, chunk=512, max_steps=40000, tag="data"):
     t0 = time.perf_counter()
     for c0 in range(0, M, chunk):
         sl = slice(c0, min(M, c0 + chunk))
-        psi = gaussian_starts(torch, prm[sl])
+        psi = gaussian_starts(torch, prm[sl], complex128=complex128)
         with gp.Batch(psi, [problem(r) for r in prm[sl]], _offsets(sl.stop - sl.start)) as b:
             st, mu, conv = b.converge_imag(tol=tol, check_every=0, max_steps=max_steps)
         capped += int(np.sum(~conv.astype(bool)))
-        tgt[sl] = psi.view(-1, N_GRID, N_GRID, N_GRID).real
+        tgt[sl] = psi.view(-1, N_GRID, N_GRID, N_GRID).real.float()
         mus[sl], steps[sl] = mu, st
         log(f"[{tag}] {sl.stop}/{M} ground states, steps {int(st.min())}..{int(st.max())}, "
             f"{time.perf_counter() - t0:.1f} s, {capped} stopped at {max_steps} steps")
@@ -230,6 +231,10 @@ def run(n_train=4096, n_test=512, epochs=40, batch=16, lr0=1e-3, data_tol=1e-8, 
         tgt, mu_train, st_train, cap_tr = ground_states(torch, prm_train, data_tol, tag="train data")
     tgt_test, mu_test, st_test, cap_te = ground_states(torch, prm_test, data_tol, tag="test data")
     out["data_seconds"] = time.perf_counter() - t0
+    # reference mu: the same scheme in FP64 until the change is below 1e-12
+    _, mu_ref, _, cap_ref = ground_states(torch, prm_test, 1e-12, tag="reference mu", complex128=True)
+    out["mu_reference"] = dict(precision="complex128", tol=1e-12, capped=cap_ref,
+                               c64_data_vs_ref_max=float(np.max(np.abs(mu_test - mu_ref) / mu_ref)))
     if load_weights is None:
         out["data_capped"] = [cap_tr, cap_te]
         out["data_steps_mean"] = float(st_train.mean())
@@ -252,7 +257,7 @@ def run(n_train=4096, n_test=512, epochs=40, batch=16, lr0=1e-3, data_tol=1e-8, 
         out["rel_l2_test_p90"] = float(np.percentile(e_te, 90))
         log(f"[eval] relative L2: test median {np.median(e_te):.2e}, p90 {np.percentile(e_te, 90):.2e}")
         torch.cuda.empty_cache()
-        out["time_to_ground_state"] = time_to_ground_state(torch, net, prm_test, tol, gate, batch, mu_test,
+        out["time_to_ground_state"] = time_to_ground_state(torch, net, prm_test, tol, gate, batch, mu_ref,
                                                             serial=serial)
     return out
 

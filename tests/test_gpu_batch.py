@@ -108,6 +108,7 @@ def test_batch_real_time_bitwise_equals_single_grid_with_same_mapping():
     states, offs, total = pack(ws, prec, seed=10)
     psi = to_dev(states, total, prec)
     with gp.Batch(psi, ws, offs) as b:
+        assert b.get_yz_fusion() == (False, 0)  # default: the separate (single-grid) sweeps
         mx, swx, my, swy, mz = b.get_mapping()
         b.step_real(7)
         torch.cuda.synchronize()
@@ -227,3 +228,75 @@ def test_batch_residual_small_at_converged_ground_state():
     say(f"residual / mu: start {r0 / mu0}, converged {r1 / mu1}")
     # the imaginary-time fixed point differs from the discrete ground state by O(dt)
     assert np.all(r1 < 0.05 * r0) and np.all(r1 / mu1 < 5e-3)
+
+
+@pytest.mark.parametrize("prec", [gp.GP_C64, gp.GP_C128])
+@pytest.mark.parametrize("imag", [True, False])
+def test_fused_yz_sweeps_agree_with_separate_sweeps(prec, imag):
+    """The fused y+z plane kernel computes the same solves in a different rounding order."""
+    ws = instances()
+    states, offs, total = pack(ws, prec, seed=50)
+    outs = []
+    for fuse in (True, False):
+        psi = to_dev(states, total, prec)
+        with gp.Batch(psi, ws, offs) as b:
+            b.set_yz_fusion(fuse)
+            on, nf = b.get_yz_fusion()
+            assert on == fuse and nf == (len(ws) if fuse else 0)
+            (b.step_imag if imag else b.step_real)(12)
+            torch.cuda.synchronize()
+            outs.append(unpack(psi, ws, offs))
+    for i, (w, s0, a, c) in enumerate(zip(ws, states, *outs)):
+        err = float(np.max(np.abs(a - c)) / np.max(np.abs(c)))
+        if prec == gp.GP_C128:
+            tol = 1e-13
+        else:  # two FP32 rounding orders: bounded by the problem's conditioning, as against the oracle
+            o = oracle.Oracle.from_params(w, s0)
+            (o.step_imag if imag else o.step_real)(12)
+            tol = c64_tolerance(w, s0, o.psi, imag, steps=12)
+        say(f"  instance {i}: fused vs separate {err:.2e} (tol {tol:.1e})")
+        assert err <= tol
+
+
+def test_mixed_fused_and_separate_instances_match_oracle():
+    """An instance whose x-plane does not fit in LDS (120 x 101 complex128 = 194 KB) takes the separate y and z
+    sweeps while the others are fused, in the same launches; both kinds match the oracle,
+    and the per-instance norms (renormalisation) come from the right partial sums."""
+    ws = instances()[:3] + [dict(instances()[1], nx=12, ny=120, nz=100, g=30.0)]
+    prec = gp.GP_C128
+    states, offs, total = pack(ws, prec, seed=60)
+    psi = to_dev(states, total, prec)
+    with gp.Batch(psi, ws, offs) as b:
+        b.set_yz_fusion(True)
+        assert b.get_yz_fusion() == (True, 3)
+        b.step_imag(6)
+        b.step_real(4)
+        torch.cuda.synchronize()
+        outs = unpack(psi, ws, offs)
+        norms = b.norm()
+    for i, (w, s0, out) in enumerate(zip(ws, states, outs)):
+        o = oracle.Oracle.from_params(w, s0)
+        o.step_imag(6)
+        o.step_real(4)
+        err = float(np.max(np.abs(out - o.psi)) / np.max(np.abs(o.psi)))
+        say(f"  instance {i} {w['ny']}x{w['nz']}: rel err {err:.2e}, norm {norms[i]:.15f}")
+        assert err <= 1e-12
+        assert abs(norms[i] - o.norm()) <= 1e-12
+
+
+@pytest.mark.parametrize("imag", [True, False])
+def test_strang_batch_matches_oracle(imag):
+    ws = instances()[:3]
+    prec = gp.GP_C128
+    states, offs, total = pack(ws, prec, seed=70)
+    psi = to_dev(states, total, prec)
+    with gp.Batch(psi, ws, offs, split=gp.GP_SPLIT_STRANG) as b:
+        b.set_yz_fusion(True)
+        assert b.get_yz_fusion()[1] == 0  # the fused kernel has no trailing half step
+        (b.step_imag if imag else b.step_real)(9)
+        torch.cuda.synchronize()
+        outs = unpack(psi, ws, offs)
+    for w, s0, out in zip(ws, states, outs):
+        o = oracle.Oracle.from_params(w, s0, split=1)
+        (o.step_imag if imag else o.step_real)(9)
+        assert float(np.max(np.abs(out - o.psi)) / np.max(np.abs(o.psi))) <= 1e-12
