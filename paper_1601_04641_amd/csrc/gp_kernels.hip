@@ -197,11 +197,13 @@ static hipError_t go_lines_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
   return a.nstep ? go_lines<R, M, SW, true, 2>(a, s) : go_lines<R, M, SW, true, 0>(a, s);
 }
 
-// Instances: complex64 M in {8, 16, 32}, complex128 M in {8, 16} (32 complex doubles per
-// thread would not fit the 128-VGPR budget of 1024-thread blocks); SW in {1, 2, 4}.
+// Instances: complex64 M in {8, 10, 12, 16, 32}, complex128 M in {8, 16} (32 complex
+// doubles per thread would not fit the 128-VGPR budget of 1024-thread blocks); SW in
+// {1, 2, 4}.  M = 10 and 12 keep the real-time x sweep (with the phase factor) at <= 64
+// VGPRs, i.e. 8 waves per SIMD, where M = 16 needs 80 (6 waves).
 bool sweep_lines_supported(int precision, int m, int sw) {
   if (sw != 1 && sw != 2 && sw != 4) return false;
-  if (precision == 0) return m == 8 || m == 16 || m == 32;
+  if (precision == 0) return m == 8 || m == 10 || m == 12 || m == 16 || m == 32;
   return m == 8 || m == 16;
 }
 
@@ -216,6 +218,8 @@ hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipS
   if (precision == 0) {
     if (a.m == 8) GP_LINES_SW(float, 8);
     if (a.m == 16) GP_LINES_SW(float, 16);
+    if (a.m == 12) GP_LINES_SW(float, 12);
+    if (a.m == 10) GP_LINES_SW(float, 10);
     if (a.m == 32) GP_LINES_SW(float, 32);
   } else {
     if (a.m == 8) GP_LINES_SW(double, 8);

@@ -153,7 +153,7 @@ def test_large_dt_long_head_correction(prec, imag):
 
 
 MAPPINGS = [(8, 1, 8, 1, 4, 0), (16, 1, 16, 2, 8, 0), (32, 2, 8, 4, 16, 0), (0, 4, 0, 1, 32, 0),
-            (16, 4, 32, 1, 64, 0), (8, 2, 16, 4, 0, 0)]
+            (16, 4, 32, 1, 64, 0), (8, 2, 16, 4, 0, 0), (12, 4, 10, 2, 0, 0), (10, 1, 12, 1, 0, 0)]
 
 
 @pytest.mark.parametrize("prec", [gp.GP_C128, gp.GP_C64])
@@ -162,8 +162,9 @@ def test_every_line_mapping_agrees(prec, mapping):
     nx, ny, nz = 96, 70, 45
     prm = dict(nx=nx, ny=ny, nz=nz, dx=0.2, dy=0.2, dz=0.2, nux=1.0, nuy=1.4142, nuz=1.7321, g=50.0, dt=0.004)
     psi0 = inputs.perturbed_psi(nx, ny, nz, 0.2, 0.2, 0.2, 1.0, 1.4, 1.7, seed=4, amp=0.1)
-    if prec == gp.GP_C128:   # complex128 runs at most 16 points per thread
-        mapping = tuple(16 if (i in (0, 2) and v == 32) else v for i, v in enumerate(mapping))
+    if prec == gp.GP_C128:   # complex128 runs 8 or 16 points per thread
+        mapping = tuple((16 if v == 32 else 8 if v in (10, 12) else v) if i in (0, 2) else v
+                        for i, v in enumerate(mapping))
     say(f"case: mapping {mapping} prec {prec}")
     for imag in (True, False):
         out, s = run_gpu(prm, psi0, prec, imag, 2, mapping=mapping)
