@@ -279,6 +279,9 @@ gpk::SweepLaunch lines_args(gp_ctx* c, int axis, int mode) {
     a.vx = c->vtab[0];
     a.vy = c->vtab[1];
     a.vz = c->vtab[2];
+    a.ph = 0.5 * p.nux * p.nux;
+    a.pc = 0.5 * (p.nx - 1);
+    a.pd = p.dx;
   }
   a.ny = p.ny;
   a.nz = p.nz;
@@ -303,6 +306,9 @@ gpk::SweepLaunch z_args(gp_ctx* c, int mode) {
   a.vx = c->vtab[0];
   a.vy = c->vtab[1];
   a.vz = c->vtab[2];
+  a.ph = 0.5 * p.nuz * p.nuz;
+  a.pc = 0.5 * (p.nz - 1);
+  a.pd = p.dz;
   a.ny = p.ny;
   a.nz = p.nz;
   a.st = c->st;

@@ -35,6 +35,8 @@ struct BInst {
   int ob0, ob1;          // observables / scale blocks of this instance
   double dt, dV;
   double id2[3];         // 1 / dx^2, 1 / dy^2, 1 / dz^2
+  double ph[3], pc[3];   // potential per axis: V(i) = ph ((i - pc) d)^2
+  double pd[3];          // grid spacing per axis
   double coef[2][3][8];  // a, b, b_lo, P as (re, im) [imag, real][axis]
 };
 
@@ -75,8 +77,8 @@ kb_sweep_lines(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restri
   const int nw = I.nw[mode][axis];
   lines_body<R, M, SW, CC, NSTEP>(psi_all + I.off, I.bytes, dval<R>(cf), dval<R>(cf + 2), dval<R>(cf + 4),
                                   dval<R>(cf + 6), omega_all + I.omega_off[mode][axis], nw <= M ? nw : 0, n,
-                                  I.nseg[axis], nlines, inner, vtab + I.v_off[0], vtab + I.v_off[1],
-                                  vtab + I.v_off[2], I.nz, tau, scale, g, wk.blk, smem_raw);
+                                  I.nseg[axis], nlines, inner, Pot1D<R>{(R)I.ph[0], (R)I.pc[0], (R)I.pd[0]},
+                                  vtab + I.v_off[1], vtab + I.v_off[2], I.nz, tau, scale, g, wk.blk, smem_raw);
 }
 
 template <typename R, int MZ, bool CC, bool NORM, int EPI>
@@ -99,7 +101,8 @@ kb_sweep_z(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__
   const double acc = z_body<R, MZ, CC, NORM, EPI>(
       psi_all + I.off, dval<R>(cf), dval<R>(cf + 2), dval<R>(cf + 4), dval<R>(cf + 6),
       omega_all + I.omega_off[mode][2], I.nw[mode][2], I.nz, I.nseg[2], (int64_t)I.nx * I.ny, vtab + I.v_off[0],
-      vtab + I.v_off[1], vtab + I.v_off[2], I.ny, (R)(0.5 * I.dt), g, wk.blk, (int64_t)1 << 62, smem_raw);
+      vtab + I.v_off[1], Pot1D<R>{(R)I.ph[2], (R)I.pc[2], (R)I.pd[2]}, I.ny, (R)(0.5 * I.dt), g, wk.blk,
+      (int64_t)1 << 62, smem_raw);
   if (NORM) {
     const double t = block_sum_256(acc, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -737,6 +740,15 @@ int configure(gp_batch* b) {
     I.id2[0] = 1.0 / (p.dx * p.dx);
     I.id2[1] = 1.0 / (p.dy * p.dy);
     I.id2[2] = 1.0 / (p.dz * p.dz);
+    {
+      const double nu3[3] = {p.nux, p.nuy, p.nuz}, d3[3] = {p.dx, p.dy, p.dz};
+      const int n3[3] = {p.nx, p.ny, p.nz};
+      for (int a = 0; a < 3; ++a) {
+        I.ph[a] = 0.5 * nu3[a] * nu3[a];
+        I.pc[a] = 0.5 * (n3[a] - 1);
+        I.pd[a] = d3[a];
+      }
+    }
     const int n[3] = {p.nx, p.ny, p.nz};
     const double d[3] = {p.dx, p.dy, p.dz};
     I.nseg[0] = cdiv(p.nx, mx);

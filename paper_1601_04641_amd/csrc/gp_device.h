@@ -209,6 +209,17 @@ __device__ __forceinline__ V fwd_point(const Coef<V>& c, V prev, V nxt, V d, V p
   return cfma<CC>(c.b, p, dn);
 }
 
+// Harmonic potential along one axis, V(i) = h x^2 with x = (i - c) d, h = nu^2 / 2,
+// c = (n - 1) / 2: evaluated in place of a table load (the same operations, in the same
+// order, as the host tables, so FP64 values are identical to them).
+template <typename R> struct Pot1D {
+  R h, c, d;
+  __device__ __forceinline__ R at(int i) const {
+    const R x = ((R)i - c) * d;
+    return h * x * x;
+  }
+};
+
 // ---------------------------------------------------------------------------------------
 // x / y sweep.  Block = ceil(nseg/SW) wavefronts; a wavefront holds SW segments of
 // LW = 64/SW consecutive lines (lane = segment-in-wave * LW + line).  Lines l of a block
@@ -222,7 +233,7 @@ __device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ ps
                                            typename VecOf<R>::T ca, typename VecOf<R>::T cb,
                                            typename VecOf<R>::T cbl, typename VecOf<R>::T cP,
                                            const typename VecOf<R>::T* __restrict__ omega, int nwi, int n,
-                                           int nseg, int64_t nlines, int64_t inner, const R* __restrict__ vline,
+                                           int nseg, int64_t nlines, int64_t inner, Pot1D<R> px,
                                            const R* __restrict__ vy, const R* __restrict__ vz, int nz, R tau,
                                            R scale, R g, int64_t bidx, unsigned char* smem_raw) {
   typedef typename VecOf<R>::T V;
@@ -260,7 +271,7 @@ __device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ ps
 #pragma unroll
     for (int t = 0; t < M; ++t) {
       const int pos = min(s + t, n - 1);
-      v[t] = nstep<NSTEP, R, V>(v[t], scale, vline[pos] + vyz, g, tau);  // padding stays 0
+      v[t] = nstep<NSTEP, R, V>(v[t], scale, px.at(pos) + vyz, g, tau);  // padding stays 0
     }
   }
 
@@ -367,7 +378,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
                                          typename VecOf<R>::T cb, typename VecOf<R>::T cbl,
                                          typename VecOf<R>::T cP, const typename VecOf<R>::T* __restrict__ omega,
                                          int nwi, int nz, int nseg, int64_t nlines, const R* __restrict__ vx,
-                                         const R* __restrict__ vy, const R* __restrict__ vz, int ny, R tau, R g,
+                                         const R* __restrict__ vy, Pot1D<R> pz, int ny, R tau, R g,
                                          int64_t grp_begin, int64_t grp_step, unsigned char* smem_raw) {
   typedef typename VecOf<R>::T V;
   V* sdata = reinterpret_cast<V*>(smem_raw);
@@ -498,7 +509,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
 #pragma unroll
       for (int t = 0; t < MZ; ++t) {
         if (t < len) {
-          if (EPI != 0) v[t] = nstep<EPI, R, V>(v[t], (R)1, vxy + vz[s + t], g, tau);
+          if (EPI != 0) v[t] = nstep<EPI, R, V>(v[t], (R)1, vxy + pz.at(s + t), g, tau);
           if (NORM) acc = fma((double)v[t].x, (double)v[t].x, fma((double)v[t].y, (double)v[t].y, acc));
           row[s + t] = v[t];
         }

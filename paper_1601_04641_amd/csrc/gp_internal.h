@@ -36,6 +36,7 @@ struct SweepLaunch {
   int64_t inner;    // x sweep: ny*nz; y sweep: nz (line l -> base (l/inner)*n*inner + l%inner)
   int sw;           // segments per wavefront (x/y kernels)
   // potential step fused into the load (x sweep) or store (z sweep, Strang)
+  double ph, pc, pd;  // potential of the swept axis: V(i) = ph ((i - pc) pd)^2
   int nstep;        // 0 none, 1 imaginary, 2 real
   double tau;
   const void* vx;   // storage-precision potential tables 1/2 nu^2 a^2

@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(1024)
 k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, uint32_t psi_bytes, typename VecOf<R>::T ca,
               typename VecOf<R>::T cb, typename VecOf<R>::T cbl, typename VecOf<R>::T cP,
               const typename VecOf<R>::T* __restrict__ omega, int nwi, int n, int nseg, int64_t nlines,
-              int64_t inner, const R* __restrict__ vline, const R* __restrict__ vy, const R* __restrict__ vz, int nz,
+              int64_t inner, Pot1D<R> px, const R* __restrict__ vy, const R* __restrict__ vz, int nz,
               R tau, const DevState* __restrict__ st) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R scale = 1, g = 0;
@@ -49,7 +49,7 @@ k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, uint32_t psi_bytes, typena
     scale = (R)st->s;
     g = (R)st->g;
   }
-  lines_body<R, M, SW, CC, NSTEP>(psi, psi_bytes, ca, cb, cbl, cP, omega, nwi, n, nseg, nlines, inner, vline, vy, vz,
+  lines_body<R, M, SW, CC, NSTEP>(psi, psi_bytes, ca, cb, cbl, cP, omega, nwi, n, nseg, nlines, inner, px, vy, vz,
                                   nz, tau, scale, g, blockIdx.x, smem_raw);
 }
 
@@ -58,12 +58,12 @@ __global__ void __launch_bounds__(256)
 k_sweep_z(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typename VecOf<R>::T cb,
           typename VecOf<R>::T cbl, typename VecOf<R>::T cP, const typename VecOf<R>::T* __restrict__ omega, int nwi,
           int nz, int nseg, int64_t nlines, double* __restrict__ partials, const R* __restrict__ vx,
-          const R* __restrict__ vy, const R* __restrict__ vz, int ny, R tau, const DevState* __restrict__ st) {
+          const R* __restrict__ vy, Pot1D<R> pz, int ny, R tau, const DevState* __restrict__ st) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[4];
   R g = 0;
   if (EPI != 0) g = (R)st->g;
-  const double acc = z_body<R, MZ, CC, NORM, EPI>(psi, ca, cb, cbl, cP, omega, nwi, nz, nseg, nlines, vx, vy, vz, ny,
+  const double acc = z_body<R, MZ, CC, NORM, EPI>(psi, ca, cb, cbl, cP, omega, nwi, nz, nseg, nlines, vx, vy, pz, ny,
                                                   tau, g, blockIdx.x, gridDim.x, smem_raw);
   if (NORM) {
     const double t = block_sum_256(acc, red);
@@ -181,8 +181,8 @@ static hipError_t go_lines(const SweepLaunch& a, hipStream_t s) {
   const int nwi = (a.nw <= M) ? a.nw : 0;
   hipLaunchKernelGGL((k_sweep_lines<R, M, SW, CC, NSTEP>), dim3((unsigned)blocks), dim3(waves * 64), lds, s,
                      (V*)a.psi, a.psi_bytes, cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4),
-                     cval<R>(a.coef + 6), (const V*)a.omega, nwi, a.n, a.nseg, a.nlines, a.inner, (const R*)a.vx,
-                     (const R*)a.vy, (const R*)a.vz, a.nz, (R)a.tau, a.st);
+                     cval<R>(a.coef + 6), (const V*)a.omega, nwi, a.n, a.nseg, a.nlines, a.inner,
+                     Pot1D<R>{(R)a.ph, (R)a.pc, (R)a.pd}, (const R*)a.vy, (const R*)a.vz, a.nz, (R)a.tau, a.st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || nwi > 0 || a.nw == 0) return e;
   const int64_t want = (a.nlines + 255) / 256;
@@ -237,7 +237,7 @@ static hipError_t go_z(const SweepLaunch& a, hipStream_t s) {
   hipLaunchKernelGGL((k_sweep_z<R, MZ, CC, NORM, EPI>), dim3(a.grid), dim3(256), lds, s, (V*)a.psi,
                      cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4), cval<R>(a.coef + 6),
                      (const V*)a.omega, a.nw, a.nz, a.nseg, a.nlines, a.partials, (const R*)a.vx, (const R*)a.vy,
-                     (const R*)a.vz, a.ny, (R)a.tau, a.st);
+                     Pot1D<R>{(R)a.ph, (R)a.pc, (R)a.pd}, a.ny, (R)a.tau, a.st);
   return hipGetLastError();
 }
 
