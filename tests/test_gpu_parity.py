@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C-ABI) against the CPU FP64 oracle.
 
-Tolerances follow from the arithmetic ("Tolerances"): complex128 agrees
+Tolerances follow from the arithmetic: complex128 agrees
 with the oracle to a few units of FP64 rounding per step; complex64 carries FP32 storage
 and sweeps (unit roundoff 6e-8) and FP64 reductions, so one step differs by ~1e-7 of
 max|psi| and the long imaginary-time run is held to the stated precision-form bound
