@@ -134,6 +134,100 @@ k_conv(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const flo
   }
 }
 
+// 3x3x3 convolution with the input tile staged in LDS, for D^3 grids with D a power of
+// two >= 8.  A block computes a TI x TJ x TK = 256-position brick of one sample (TK =
+// min(D, 16) along z, TJ = 4, TI = 256 / (TJ TK)) for 64 output channels: for each chunk
+// of KC input channels it stages the brick's halo ((TI+2)(TJ+2)(TK+2) positions, KC
+// channels, row pitch KC + 8 so the 16 lanes of a fragment hit distinct banks), then runs
+// the 27 taps from LDS.  Each wave owns 4 tiles of 16 positions x up to 4 tiles of 16
+// output channels, so every A fragment (LDS) feeds up to 4 MFMAs and every B fragment
+// (weights, global/L1) feeds 4.  Epilogue as k_conv.
+template <int KC>
+__global__ void __launch_bounds__(256)
+k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const float* __restrict__ bias, int D,
+              int cin, int cout, int act, const uint16_t* __restrict__ gate, uint16_t* __restrict__ y,
+              uint16_t* __restrict__ pre) {
+  typedef Frag<KC> F;
+  constexpr int KQ = KC / 4;
+  constexpr int PITCH = KC + 8;  // bf16 per halo position
+  constexpr int U = KC / 8;      // 16-byte units per position
+  extern __shared__ __align__(16) uint16_t halo[];
+  const int TK = D < 16 ? D : 16, TJ = 4, TI = 256 / (TJ * TK);
+  const int HK = TK + 2, HJ = TJ + 2, HI = TI + 2;
+  const int nhalo = HI * HJ * HK;
+  int64_t bq = blockIdx.x;
+  const int tkn = D / TK, tjn = D / TJ, tin = D / TI;
+  const int k0 = (int)(bq % tkn) * TK;
+  bq /= tkn;
+  const int j0 = (int)(bq % tjn) * TJ;
+  bq /= tjn;
+  const int i0 = (int)(bq % tin) * TI;
+  const int64_t smp = bq / tin;
+  const int64_t sbase = smp * D * D * D;
+  const int co0 = blockIdx.y * 64;
+  const int nb = min(4, (cout - co0) >> 4);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, kq = lane >> 4;
+  int hbase[4];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const int tp = wave * 64 + mb * 16 + r;
+    const int tk = tp % TK, tj = (tp / TK) % TJ, ti = tp / (TK * TJ);
+    hbase[mb] = ((ti + 1) * HJ + (tj + 1)) * HK + (tk + 1);
+  }
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[mb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ci0 = 0; ci0 < cin; ci0 += KC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < nhalo * U; e += 256) {
+      const int hp = e / U, u = e % U;
+      const int hk = hp % HK, hj = (hp / HK) % HJ, hi = hp / (HK * HJ);
+      const int gi = i0 - 1 + hi, gj = j0 - 1 + hj, gk = k0 - 1 + hk;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if ((unsigned)gi < (unsigned)D && (unsigned)gj < (unsigned)D && (unsigned)gk < (unsigned)D)
+        v = *reinterpret_cast<const uint4*>(x + (sbase + ((int64_t)gi * D + gj) * D + gk) * cin + ci0 + u * 8);
+      *reinterpret_cast<uint4*>(halo + hp * PITCH + u * 8) = v;
+    }
+    __syncthreads();
+    for (int t = 0; t < 27; ++t) {
+      const int toff = ((t / 9 - 1) * HJ + ((t / 3) % 3 - 1)) * HK + (t % 3 - 1);
+      const uint16_t* wt = w + ((int64_t)t * cout + co0 + r) * cin + ci0 + kq * KQ;
+      typename F::T bv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = j < nb ? F::load(wt + (int64_t)j * 16 * cin) : F::zero();
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        const typename F::T av = F::load(halo + (hbase[mb] + toff) * PITCH + kq * KQ);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < nb) acc[mb][j] = F::mma(av, bv[j], acc[mb][j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j >= nb) continue;
+      const int co = co0 + j * 16 + r;
+      const float bvv = bias ? bias[co] : 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int tp = wave * 64 + mb * 16 + kq * 4 + i;
+        const int tk = tp % TK, tj = (tp / TK) % TJ, ti = tp / (TK * TJ);
+        const int64_t o = (sbase + ((int64_t)(i0 + ti) * D + (j0 + tj)) * D + (k0 + tk)) * cout + co;
+        float v = acc[mb][j][i] + bvv;
+        if (pre) pre[o] = f2bf(v);
+        if (gate) v *= silu_d(bf2f(gate[o]));
+        else if (act) v = silu(v);
+        y[o] = f2bf(v);
+      }
+    }
+}
+
 // Split-K weight gradient: block (chunk, tap, 64x64 tile of (cout, cin)); partial sums
 // over the chunk's positions written to part[chunk][tap][cout][cin].  Each 64-position
 // sub-tile of dy and of x (shifted by the tap, zero outside the grid) is staged in LDS
@@ -465,6 +559,16 @@ hipError_t launch_conv(int ks, int64_t P, int D, int cin, int cout, const uint16
                        hipStream_t st) {
   dim3 grid((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64));
   const bool k32 = cin % 32 == 0;
+  // tiled path: D a power of two >= 8 and P a whole number of D^3 samples
+  const bool pow2 = D >= 8 && (D & (D - 1)) == 0 && P % ((int64_t)D * D * D) == 0;
+  if (ks == 3 && pow2) {
+    const int TK = D < 16 ? D : 16, TJ = 4, TI = 256 / (TJ * TK);
+    const size_t lds = (size_t)(TI + 2) * (TJ + 2) * (TK + 2) * ((k32 ? 32 : 16) + 8) * sizeof(uint16_t);
+    dim3 tg((unsigned)(P / 256), (unsigned)((cout + 63) / 64));
+    if (k32) hipLaunchKernelGGL((k_conv3_tiled<32>), tg, dim3(256), lds, st, x, w, bias, D, cin, cout, act, gate, y, pre);
+    else hipLaunchKernelGGL((k_conv3_tiled<16>), tg, dim3(256), lds, st, x, w, bias, D, cin, cout, act, gate, y, pre);
+    return hipGetLastError();
+  }
   if (ks == 3) {
     if (k32) hipLaunchKernelGGL((k_conv<3, 32>), grid, dim3(256), 0, st, x, w, bias, P, D, cin, cout, act, gate, y, pre);
     else hipLaunchKernelGGL((k_conv<3, 16>), grid, dim3(256), 0, st, x, w, bias, P, D, cin, cout, act, gate, y, pre);

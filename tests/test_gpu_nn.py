@@ -1,5 +1,8 @@
 """GPU tests of the warm-start network kernels against the FP64 reference.
 
+Grids whose edge is a power of two >= 8 run the LDS-tiled convolution, other sizes the
+direct one; both are covered.
+
 Kernel level: inputs are BF16 values, which both sides use exactly; BF16 x BF16
 products are exact in FP32, so the GPU result differs from the FP64 reference only by
 FP32 accumulation (~1e-6 relative) and the final rounding of BF16 outputs (2^-9
@@ -54,7 +57,8 @@ def mirror_transpose(W):
 
 
 @pytest.mark.parametrize("cin,cout,D,n", [(32, 16, 5, 2), (64, 64, 8, 1), (16, 32, 6, 2), (32, 80, 4, 3),
-                                          (48, 16, 5, 1), (64, 32, 16, 1)])
+                                          (48, 16, 5, 1), (64, 32, 16, 1), (64, 32, 32, 1), (32, 16, 64, 1),
+                                          (16, 80, 8, 3)])
 def test_conv3d_forward_bias_silu(cin, cout, D, n):
     rng = np.random.default_rng(cin * 1000 + cout + D)
     x = bf(rng.standard_normal((n, D, D, D, cin)))
@@ -70,7 +74,8 @@ def test_conv3d_forward_bias_silu(cin, cout, D, n):
     close_bf16(f64(y), R.silu(ref), "silu output")
 
 
-@pytest.mark.parametrize("cin,cout,D,n", [(16, 32, 6, 2), (64, 32, 8, 1), (32, 64, 5, 2)])
+@pytest.mark.parametrize("cin,cout,D,n", [(16, 32, 6, 2), (64, 32, 8, 1), (32, 64, 5, 2), (32, 16, 32, 1),
+                                          (64, 64, 16, 2)])
 def test_conv3d_input_gradient_by_mirrored_weights_with_gate(cin, cout, D, n):
     """dx = sum_t W[t]^T dy[q - off_t], times silu'(gate): the backward pass through a
     convolution and the preceding activation."""
