@@ -228,84 +228,123 @@ k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, co
     }
 }
 
-// Split-K weight gradient: block (chunk, tap, 64x64 tile of (cout, cin)); partial sums
-// over the chunk's positions written to part[chunk][tap][cout][cin].  Each 64-position
-// sub-tile of dy and of x (shifted by the tap, zero outside the grid) is staged in LDS
-// transposed ([channel][position]), so both MFMA operands are 16-byte LDS reads.  The
-// blocks of the centre tap and the first input-channel tile also sum the staged dy rows:
-// the bias gradient's partial sums, dbpart[chunk][cout] (nullable).
-template <int KS>
+// Split-K weight gradient: block (chunk of positions, group of 4 taps, 64x64 tile of
+// (cout, cin)); partial sums over the chunk's positions written to
+// part[chunk][tap][cout][cin].  Each 64-position sub-tile of dy is staged in LDS once and
+// the x sub-tiles of the group's 4 taps (shifted, zero outside the grid) next to it, all
+// transposed ([channel][position]) so both MFMA operands are 16-byte LDS reads; wave w
+// accumulates tap 4 g + w for the whole 64x64 tile.  The block holding the centre tap and
+// the first input-channel tile also sums the staged dy rows: the bias gradient's partial
+// sums, dbpart[chunk][cout] (nullable).
+template <int KS, int MCO, int MCI>
 __global__ void __launch_bounds__(256)
 k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, int64_t P, int D, int cin, int cout,
         int64_t chunk, float* __restrict__ part, float* __restrict__ dbpart) {
+  // a tile covers up to MCO x MCI blocks of 16 output x 16 input channels (MCO, MCI <= 4)
+  constexpr int NB = MCO * MCI;
   constexpr int LD = 72;  // 64 positions + 8 pad (row = 144 B, 16-byte aligned)
-  __shared__ __align__(16) uint16_t sdy[64 * LD];
-  __shared__ __align__(16) uint16_t sx[64 * LD];
   constexpr int T = KS * KS * KS;
-  const int t = blockIdx.y;
+  constexpr int G = T < 4 ? T : 4;  // taps per block
+  extern __shared__ __align__(16) uint16_t smem[];
   const int cot = (cout + 63) / 64;
   const int co0 = (blockIdx.z % cot) * 64, ci0 = (blockIdx.z / cot) * 64;
   const int nco = min(64, cout - co0), nci = min(64, cin - ci0);
-  const int a = KS == 3 ? t / 9 - 1 : 0, b = KS == 3 ? (t / 3) % 3 - 1 : 0, c = KS == 3 ? t % 3 - 1 : 0;
+  uint16_t* sdy = smem;              // [nco][LD]
+  uint16_t* sxb = smem + nco * LD;   // [G][nci][LD]
+  const int t0 = blockIdx.y * G;
   const int64_t q0 = (int64_t)blockIdx.x * chunk;
   const int64_t q1 = min(P, q0 + chunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, kq = lane >> 4;
-  const bool do_db = dbpart != nullptr && t == T / 2 && ci0 == 0;
+  const int tw = t0 + wave;  // this wave's tap
+  const bool wact = wave < G && tw < T;
+  const bool do_db = dbpart != nullptr && ci0 == 0 && T / 2 >= t0 && T / 2 < t0 + G;
   float dbacc = 0.0f;  // channel threadIdx.x / 4, positions (threadIdx.x % 4) * 16 ... + 15
-  f32x4 acc[4];
+  f32x4 acc[NB];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int pp = threadIdx.x >> 2;          // staged position of this thread
-  const int cg = (threadIdx.x & 3) * 8;     // first channel group of this thread
+  for (int j = 0; j < NB; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // staging: thread -> positions 2 pq, 2 pq + 1 of the sub-tile and 8 channels c8 .. c8 + 7;
+  // each channel's pair of positions is one 32-bit LDS word (consecutive lanes, consecutive
+  // words: conflict-free)
+  const int pq = threadIdx.x & 31;
+  const int c8 = (threadIdx.x >> 5) * 8;
   for (int64_t s0 = q0; s0 < q1; s0 += 64) {
     __syncthreads();
     {
-      const int64_t pos = s0 + pp;
-      const bool pv = pos < q1;
-      for (int c8 = cg; c8 < 64; c8 += 32) {
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (pv && c8 < nco) v = *reinterpret_cast<const uint4*>(dy + pos * cout + co0 + c8);
-        const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+      int64_t pos[2];
+      bool pv[2];
+      int pi[2] = {0, 0}, pj[2] = {0, 0}, pk[2] = {0, 0};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sdy[(c8 + q) * LD + pp] = e[q];
+      for (int h = 0; h < 2; ++h) {
+        pos[h] = s0 + 2 * pq + h;
+        pv[h] = pos[h] < q1;
+        if (KS == 3 && pv[h]) {
+          int64_t q = pos[h];
+          pk[h] = (int)(q % D);
+          q /= D;
+          pj[h] = (int)(q % D);
+          q /= D;
+          pi[h] = (int)(q % D);
+        }
       }
-      bool ok = pv;
-      int64_t nbr = pos;
-      if (KS == 3 && pv) {
-        int64_t q = pos;
-        const int pk = (int)(q % D);
-        q /= D;
-        const int pj = (int)(q % D);
-        q /= D;
-        const int pi = (int)(q % D);
-        ok = (unsigned)(pi + a) < (unsigned)D && (unsigned)(pj + b) < (unsigned)D && (unsigned)(pk + c) < (unsigned)D;
-        nbr = pos + ((int64_t)a * D + b) * D + c;
-      }
-      for (int c8 = cg; c8 < 64; c8 += 32) {
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (ok && c8 < nci) v = *reinterpret_cast<const uint4*>(x + nbr * cin + ci0 + c8);
-        const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+      {
+        uint4 v[2];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sx[(c8 + q) * LD + pp] = e[q];
+        for (int h = 0; h < 2; ++h) {
+          v[h] = make_uint4(0, 0, 0, 0);
+          if (pv[h] && c8 < nco) v[h] = *reinterpret_cast<const uint4*>(dy + pos[h] * cout + co0 + c8);
+        }
+        const uint16_t* e0 = reinterpret_cast<const uint16_t*>(&v[0]);
+        const uint16_t* e1 = reinterpret_cast<const uint16_t*>(&v[1]);
+        if (c8 < nco)
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            *reinterpret_cast<uint32_t*>(sdy + (c8 + q) * LD + 2 * pq) = (uint32_t)e0[q] | ((uint32_t)e1[q] << 16);
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int t = t0 + g;
+        uint4 v[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          bool ok = pv[h] && t < T && c8 < nci;
+          int64_t nbr = pos[h];
+          if (KS == 3 && ok) {
+            const int a = t / 9 - 1, b = (t / 3) % 3 - 1, c = t % 3 - 1;
+            ok = (unsigned)(pi[h] + a) < (unsigned)D && (unsigned)(pj[h] + b) < (unsigned)D &&
+                 (unsigned)(pk[h] + c) < (unsigned)D;
+            nbr = pos[h] + ((int64_t)a * D + b) * D + c;
+          }
+          v[h] = make_uint4(0, 0, 0, 0);
+          if (ok) v[h] = *reinterpret_cast<const uint4*>(x + nbr * cin + ci0 + c8);
+        }
+        const uint16_t* e0 = reinterpret_cast<const uint16_t*>(&v[0]);
+        const uint16_t* e1 = reinterpret_cast<const uint16_t*>(&v[1]);
+        if (c8 < nci)
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            *reinterpret_cast<uint32_t*>(sxb + (g * nci + c8 + q) * LD + 2 * pq) =
+                (uint32_t)e0[q] | ((uint32_t)e1[q] << 16);
       }
     }
     __syncthreads();
-    if (do_db) {
+    if (do_db && (threadIdx.x >> 2) < nco) {
       const uint16_t* row = sdy + (threadIdx.x >> 2) * LD + (threadIdx.x & 3) * 16;
 #pragma unroll
       for (int e = 0; e < 16; ++e) dbacc += bf2f(row[e]);
     }
+    if (wact) {
+      const uint16_t* sxw = sxb + (wave < G ? wave : 0) * nci * LD;
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
+      for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
-      for (int bi = 0; bi < 4; ++bi) {
-        const int blk = wave + bi * 4;
-        const int bco = blk & 3, bci = blk >> 2;
-        if (bco * 16 >= nco || bci * 16 >= nci) continue;
-        const bf16x8 av = *reinterpret_cast<const bf16x8*>(sdy + (bco * 16 + r) * LD + ks * 32 + kq * 8);
-        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sx + (bci * 16 + r) * LD + ks * 32 + kq * 8);
-        acc[bi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[bi], 0, 0, 0);
+        for (int blk = 0; blk < NB; ++blk) {
+          const int bco = blk % MCO, bci = blk / MCO;
+          if (bco * 16 >= nco || bci * 16 >= nci) continue;
+          const bf16x8 av = *reinterpret_cast<const bf16x8*>(sdy + (bco * 16 + r) * LD + ks * 32 + kq * 8);
+          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sxw + (bci * 16 + r) * LD + ks * 32 + kq * 8);
+          acc[blk] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[blk], 0, 0, 0);
+        }
       }
     }
   }
@@ -315,16 +354,27 @@ k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, int64_t
     const int co = threadIdx.x >> 2;
     if ((threadIdx.x & 3) == 0 && co < nco) dbpart[(int64_t)blockIdx.x * cout + co0 + co] = dbacc;
   }
-  float* out = part + ((int64_t)blockIdx.x * T + t) * (int64_t)cout * cin;
+  if (!wact) return;
+  float* out = part + ((int64_t)blockIdx.x * T + tw) * (int64_t)cout * cin;
 #pragma unroll
-  for (int bi = 0; bi < 4; ++bi) {
-    const int blk = wave + bi * 4;
-    const int bco = blk & 3, bci = blk >> 2;
+  for (int blk = 0; blk < NB; ++blk) {
+    const int bco = blk % MCO, bci = blk / MCO;
     if (bco * 16 >= nco || bci * 16 >= nci) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      out[(int64_t)(co0 + bco * 16 + kq * 4 + i) * cin + ci0 + bci * 16 + r] = acc[bi][i];
+      out[(int64_t)(co0 + bco * 16 + kq * 4 + i) * cin + ci0 + bci * 16 + r] = acc[blk][i];
   }
+}
+
+// partial sums of up to 128 consecutive chunks: out[c2][e] = sum_{k < 128} part[c2 * 128 + k][e]
+__global__ void __launch_bounds__(256)
+k_reduce_chunks_pre(const float* __restrict__ part, int nchunk, int64_t per_chunk, float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= per_chunk) return;
+  const int k0 = blockIdx.y * 128, k1 = min(nchunk, k0 + 128);
+  float s = 0.0f;
+  for (int k = k0; k < k1; ++k) s += part[(int64_t)k * per_chunk + e];
+  out[(int64_t)blockIdx.y * per_chunk + e] = s;
 }
 
 // out[(t * rows + o) * keep + i] = sum_chunks part[chunk][t][o][i], i < keep (fixed order)
@@ -598,9 +648,30 @@ hipError_t launch_wgrad(int ks, int64_t P, int D, int cin, int cout, int keep, c
   const int nch = (int)wgrad_nch(P);
   const int T = ks * ks * ks;
   float* dbp = db ? cpart : nullptr;
-  dim3 grid((unsigned)nch, (unsigned)T, (unsigned)(((cout + 63) / 64) * ((cin + 63) / 64)));
-  if (ks == 3) hipLaunchKernelGGL((k_wgrad<3>), grid, dim3(256), 0, st, dy, x, P, D, cin, cout, chunk, part, dbp);
-  else hipLaunchKernelGGL((k_wgrad<1>), grid, dim3(256), 0, st, dy, x, P, 1, cin, cout, chunk, part, dbp);
+  dim3 grid((unsigned)nch, (unsigned)((T + 3) / 4), (unsigned)(((cout + 63) / 64) * ((cin + 63) / 64)));
+  // accumulators for the largest tile of this launch; LDS for its rows
+  const int tco = cout < 64 ? cout : 64, tci = cin < 64 ? cin : 64;
+  const int G = T < 4 ? T : 4;
+  const size_t lds = (size_t)(tco + G * tci) * 72 * sizeof(uint16_t);
+  const int mco = tco <= 16 ? 1 : tco <= 32 ? 2 : 4, mci = tci <= 16 ? 1 : tci <= 32 ? 2 : 4;
+#define WG(A, B)                                                                                                   \
+  do {                                                                                                             \
+    if (ks == 3)                                                                                                   \
+      hipLaunchKernelGGL((k_wgrad<3, A, B>), grid, dim3(256), lds, st, dy, x, P, D, cin, cout, chunk, part, dbp); \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_wgrad<1, A, B>), grid, dim3(256), lds, st, dy, x, P, 1, cin, cout, chunk, part, dbp); \
+  } while (0)
+#define WGB(A)            \
+  do {                    \
+    if (mci == 1) WG(A, 1); \
+    else if (mci == 2) WG(A, 2); \
+    else WG(A, 4);        \
+  } while (0)
+  if (mco == 1) WGB(1);
+  else if (mco == 2) WGB(2);
+  else WGB(4);
+#undef WGB
+#undef WG
   const int64_t per = (int64_t)T * cout * cin;
   hipLaunchKernelGGL(k_reduce_chunks, dim3(nblk(per)), dim3(256), 0, st, part, nch, per, cin, keep, dw);
   if (db)
@@ -736,6 +807,7 @@ int gpnn_create(const gpnn_arch* a, void* hip_stream, gpnn** out) {
   }
   const int64_t PS = (int64_t)B * vol(m->N);
   const int64_t hblocks = (PS + 255) / 256;
+  maxc = std::max(maxc, ((hblocks + 127) / 128) * (a->ch[S] + 1));  // head partials, first stage
   A(&m->dA, maxd); A(&m->dB, maxd); A(&m->dU, maxu);
   A(&m->part, maxpart); A(&m->cpart, maxc);
   A(&m->gpart, hblocks * (a->ch[S] + 1));
@@ -843,8 +915,13 @@ int gpnn_loss_backward(gpnn* m, const float* tgt, double* loss) {
   else
     hipLaunchKernelGGL((k_head_bwd<64>), dim3(hb), dim3(256), 0, st, psi, tgt, m->act[S], m->h[S], P, m->w + m->owh,
                        scale, m->dA, m->gpart, m->lpart);
-  hipLaunchKernelGGL(k_reduce_chunks, dim3(nblk(a.ch[S] + 1)), dim3(256), 0, st, m->gpart, (int)hb,
-                     (int64_t)(a.ch[S] + 1), a.ch[S] + 1, a.ch[S] + 1, m->g + m->owh);
+  {  // head partials: groups of 128 blocks first (into the bias-partials buffer, free here)
+    const int per = a.ch[S] + 1, n2 = (int)((hb + 127) / 128);
+    hipLaunchKernelGGL(k_reduce_chunks_pre, dim3(nblk(per), (unsigned)n2), dim3(256), 0, st, m->gpart, (int)hb,
+                       (int64_t)per, m->cpart);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(nblk(per)), dim3(256), 0, st, m->cpart, n2, (int64_t)per, per, per,
+                       m->g + m->owh);
+  }
   hipLaunchKernelGGL(k_sum_double, dim3(1), dim3(256), 0, st, m->lpart, (int)hb, m->lsum);
   hipError_t e = hipGetLastError();
   uint16_t* dh = m->dA;  // gradient w.r.t. the pre-activation of the current layer
