@@ -366,6 +366,192 @@ k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, int64_t
   }
 }
 
+// Weight gradient of the 3x3x3 convolution on power-of-two grids (D >= 8, whole samples),
+// tiled like k_conv3_tiled.  A block walks a run of 256-position bricks (TI x TJ x TK,
+// z fastest).  Per brick it stages dy transposed ([channel][position], 264-element rows)
+// and the x halo of one input-channel tile transposed ([channel][hi][hj][hk]: rows of HK
+// z-values, HK >= TK + 2 and a multiple of 8; channel stride CS = 8 mod 128 elements so
+// the 16 rows of a fragment hit distinct banks).  Position pairs are packed into 32-bit
+// LDS words on the way in.  A wave owns units (one (x, y) tap offset pair x one 16-channel
+// input block) and, for each, the three z offsets: one 16-byte plus one 4-byte LDS read
+// gives the eight z-consecutive halo values of all three (shifted by 0, 1 or 2 elements
+// with funnel shifts), so every staged value feeds three MFMAs.  The A fragments (dy)
+// are shared by all of a wave's units.  Partial sums over the block's bricks go to
+// part[chunk][tap][cout][cin]; blocks of the first tap group and input tile also sum the
+// staged dy rows into dbpart[chunk][cout] (nullable).
+template <int MCO, int MCI, int NU>
+__global__ void __launch_bounds__(256)
+k_wgrad3_tiled(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, int D, int lg, int cin, int cout,
+               int nab, int ntiles, int tpb, float* __restrict__ part, float* __restrict__ dbpart) {
+  constexpr int MU = 6;    // x staging units per thread (<= 6 * 256 16-byte pairs per brick)
+  constexpr int DP = 264;  // dy row pitch (elements)
+  constexpr int CIT = 16 * MCI;
+  extern __shared__ __align__(16) uint16_t smem[];
+  const int TK = D < 16 ? D : 16, TJ = 4, TI = 256 / (TJ * TK);
+  const int lgk = TK == 16 ? 4 : 3;
+  const int HK = TK == 16 ? 24 : 16, HJ = TJ + 2, HI = TI + 2;
+  const int HR = HI * HJ * HK;
+  const int CS = HR + ((8 - HR) % 128 + 128) % 128;
+  const int NP = (TK + 2) / 2;
+  uint16_t* sdy = smem;                // [16 MCO][DP]
+  uint16_t* sx = smem + 16 * MCO * DP;  // [CIT][CS]
+  const int cit = (cin + CIT - 1) / CIT;
+  const int co0 = (blockIdx.z / cit) * 16 * MCO, ci0 = (blockIdx.z % cit) * CIT;
+  const int nco = min(16 * MCO, cout - co0), nci = min(CIT, cin - ci0);
+  const int ab0 = blockIdx.y * nab, nabb = min(nab, 9 - ab0), nunit = nabb * MCI;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, kq = lane >> 4;
+  const bool do_db = dbpart != nullptr && blockIdx.y == 0 && ci0 == 0;
+  // x staging units of this thread: unit n -> (channel group cg, halo row, z pair pr)
+  int xl[MU], xg[MU];
+  const int nxu = (CIT / 8) * HI * HJ * NP;
+#pragma unroll
+  for (int m = 0; m < MU; ++m) {
+    const int n = threadIdx.x + 256 * m;
+    xl[m] = -1;
+    xg[m] = 0;
+    if (n < nxu) {
+      const int pr = n % NP, rest = n / NP, row = rest % (HI * HJ), cg = rest / (HI * HJ);
+      if (cg * 8 < nci) {
+        xl[m] = (cg * 8 * CS + row * HK + 2 * pr) >> 1;
+        xg[m] = (row / HJ) | ((row % HJ) << 8) | ((2 * pr) << 16) | (cg << 24);
+      }
+    }
+  }
+  // this wave's units: u = wave + 4 j -> (tap pair ab, input block mci); uoff = LDS offset
+  int uoff[NU];
+  bool uact[NU];
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    const int u = wave + 4 * j;
+    const int abl = u / MCI, mci = u % MCI, ab = ab0 + abl;
+    uact[j] = u < nunit && mci * 16 < nci;
+    uoff[j] = uact[j] ? (mci * 16 + r) * CS + ((ab / 3) * HJ + ab % 3) * HK : 0;
+  }
+  f32x4 acc[NU][3][MCO];
+#pragma unroll
+  for (int j = 0; j < NU; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int b = 0; b < MCO; ++b) acc[j][c][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float dbacc = 0.0f;
+  const int tkn = D / TK, tjn = D / TJ, tin = D / TI;
+  const int tb0 = blockIdx.x * tpb, tb1 = min(ntiles, tb0 + tpb);
+  for (int tb = tb0; tb < tb1; ++tb) {
+    int q = tb;
+    const int k0 = (q % tkn) * TK;
+    q /= tkn;
+    const int j0 = (q % tjn) * TJ;
+    q /= tjn;
+    const int i0 = (q % tin) * TI;
+    const int64_t sbase = (int64_t)(q / tin) << (3 * lg);
+    __syncthreads();
+    // dy: 128 position pairs x (16 MCO / 8) channel groups
+#pragma unroll
+    for (int m = 0; m < MCO; ++m) {
+      const int n = threadIdx.x + 256 * m;
+      const int pp = n & 127, cg = n >> 7;
+      if (cg * 8 < nco) {
+        const int p = 2 * pp;
+        const int kk = p & (TK - 1), jj = (p >> lgk) & 3, ii = p >> (lgk + 2);
+        const int64_t g = sbase + ((int64_t)(i0 + ii) << (2 * lg)) + ((j0 + jj) << lg) + (k0 + kk);
+        const uint4 v0 = *reinterpret_cast<const uint4*>(dy + g * cout + co0 + cg * 8);
+        const uint4 v1 = *reinterpret_cast<const uint4*>(dy + (g + 1) * cout + co0 + cg * 8);
+        const uint16_t* e0 = reinterpret_cast<const uint16_t*>(&v0);
+        const uint16_t* e1 = reinterpret_cast<const uint16_t*>(&v1);
+        uint32_t* d32 = reinterpret_cast<uint32_t*>(sdy);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) d32[((cg * 8 + e) * DP + p) >> 1] = (uint32_t)e0[e] | ((uint32_t)e1[e] << 16);
+      }
+    }
+    // x halo of the input tile, zero outside the grid
+#pragma unroll
+    for (int m = 0; m < MU; ++m) {
+      if (xl[m] < 0) continue;
+      const int gi = i0 + (xg[m] & 255) - 1, gj = j0 + ((xg[m] >> 8) & 255) - 1;
+      const int gk = k0 + ((xg[m] >> 16) & 255) - 1, cg = xg[m] >> 24;
+      uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
+      if ((unsigned)gi < (unsigned)D && (unsigned)gj < (unsigned)D) {
+        const int64_t g = sbase + ((int64_t)gi << (2 * lg)) + (gj << lg) + gk;
+        const uint16_t* src = x + g * cin + ci0 + cg * 8;
+        if ((unsigned)gk < (unsigned)D) v0 = *reinterpret_cast<const uint4*>(src);
+        if ((unsigned)(gk + 1) < (unsigned)D) v1 = *reinterpret_cast<const uint4*>(src + cin);
+      }
+      const uint16_t* e0 = reinterpret_cast<const uint16_t*>(&v0);
+      const uint16_t* e1 = reinterpret_cast<const uint16_t*>(&v1);
+      uint32_t* d32 = reinterpret_cast<uint32_t*>(sx);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) d32[xl[m] + e * (CS >> 1)] = (uint32_t)e0[e] | ((uint32_t)e1[e] << 16);
+    }
+    __syncthreads();
+    if (do_db && (threadIdx.x >> 2) < nco) {
+      const uint16_t* row = sdy + (threadIdx.x >> 2) * DP + (threadIdx.x & 3) * 64;
+#pragma unroll
+      for (int e = 0; e < 64; e += 8) {
+        const uint4 v = *reinterpret_cast<const uint4*>(row + e);
+        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) dbacc += bf2f((uint16_t)(wv[h] & 0xffffu)) + bf2f((uint16_t)(wv[h] >> 16));
+      }
+    }
+#pragma unroll 2
+    for (int ks = 0; ks < 8; ++ks) {
+      const int p0 = ks * 32 + kq * 8;
+      const int posoff = ((p0 >> (lgk + 2)) * HJ + ((p0 >> lgk) & 3)) * HK + (p0 & (TK - 1));
+      bf16x8 av[MCO];
+#pragma unroll
+      for (int b = 0; b < MCO; ++b)
+        av[b] = b * 16 < nco ? *reinterpret_cast<const bf16x8*>(sdy + (b * 16 + r) * DP + p0) : bf16x8{};
+#pragma unroll
+      for (int j = 0; j < NU; ++j) {
+        if (!uact[j]) continue;
+        const uint16_t* src = sx + uoff[j] + posoff;
+        const uint4 w4 = *reinterpret_cast<const uint4*>(src);
+        const uint32_t w5 = *reinterpret_cast<const uint32_t*>(src + 8);
+        const uint32_t wv[5] = {w4.x, w4.y, w4.z, w4.w, w5};
+        uint32_t sh[3][4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          sh[0][d] = wv[d];
+          sh[1][d] = __builtin_amdgcn_alignbit(wv[d + 1], wv[d], 16);
+          sh[2][d] = wv[d + 1];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          bf16x8 bv;
+          __builtin_memcpy(&bv, sh[c], 16);
+#pragma unroll
+          for (int b = 0; b < MCO; ++b)
+            if (b * 16 < nco) acc[j][c][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[b], bv, acc[j][c][b], 0, 0, 0);
+        }
+      }
+    }
+  }
+  if (do_db) {
+    dbacc += __shfl_xor(dbacc, 1);
+    dbacc += __shfl_xor(dbacc, 2);
+    const int co = threadIdx.x >> 2;
+    if ((threadIdx.x & 3) == 0 && co < nco) dbpart[(int64_t)blockIdx.x * cout + co0 + co] = dbacc;
+  }
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    if (!uact[j]) continue;
+    const int u = wave + 4 * j;
+    const int ab = ab0 + u / MCI, ci = ci0 + (u % MCI) * 16 + r;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float* out = part + ((int64_t)blockIdx.x * 27 + ab * 3 + c) * (int64_t)cout * cin;
+#pragma unroll
+      for (int b = 0; b < MCO; ++b) {
+        if (b * 16 >= nco) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[(int64_t)(co0 + b * 16 + kq * 4 + i) * cin + ci] = acc[j][c][b][i];
+      }
+    }
+  }
+}
+
 // partial sums of up to 128 consecutive chunks: out[c2][e] = sum_{k < 128} part[c2 * 128 + k][e]
 __global__ void __launch_bounds__(256)
 k_reduce_chunks_pre(const float* __restrict__ part, int nchunk, int64_t per_chunk, float* __restrict__ out) {
@@ -636,18 +822,86 @@ int64_t wgrad_chunk(int64_t P) {
 }
 int64_t wgrad_nch(int64_t P) { return (P + wgrad_chunk(P) - 1) / wgrad_chunk(P); }
 
-int64_t wgrad_part_floats(int ks, int64_t P, int cin, int cout) {
-  return wgrad_nch(P) * (int64_t)ks * ks * ks * cout * cin;
+// Launch shape of one weight gradient.  Tiled (k_wgrad3_tiled) for 3x3x3 taps on a
+// power-of-two grid D >= 8 holding whole samples: units of (tap pair, 16 input channels)
+// spread over the 4 waves with at most ~64 accumulators per lane, the rest of the grid
+// split into runs of bricks so that about kTiledBlocks blocks are in flight.
+constexpr int kTiledBlocks = 512;
+struct WgPlan {
+  bool tiled = false;
+  int mco = 1, mci = 1, nu = 1, nab = 9, groups = 1, zt = 1, ntiles = 0, tpb = 0;
+  int64_t nch = 0;
+  size_t lds = 0;
+};
+
+WgPlan wgrad_plan(int ks, int64_t P, int D, int cin, int cout) {
+  WgPlan w;
+  w.tiled = ks == 3 && D >= 8 && (D & (D - 1)) == 0 && P % ((int64_t)D * D * D) == 0 && P / 256 < (1ll << 30);
+  if (!w.tiled) {
+    w.nch = wgrad_nch(P);
+    return w;
+  }
+  const int tco = cout < 64 ? cout : 64;
+  w.mco = tco <= 16 ? 1 : tco <= 32 ? 2 : 4;
+  w.mci = cin >= 32 ? 2 : 1;
+  w.nab = w.mco == 1 ? 9 : w.mco == 2 ? 3 : 2;
+  w.nu = (w.nab * w.mci + 3) / 4;
+  w.groups = (9 + w.nab - 1) / w.nab;
+  w.zt = ((cout + 16 * w.mco - 1) / (16 * w.mco)) * ((cin + 16 * w.mci - 1) / (16 * w.mci));
+  w.ntiles = (int)(P / 256);
+  int64_t want = (kTiledBlocks + w.groups * w.zt - 1) / (w.groups * w.zt);
+  if (want < 1) want = 1;
+  if (want > w.ntiles) want = w.ntiles;
+  w.tpb = (int)((w.ntiles + want - 1) / want);
+  w.nch = (w.ntiles + w.tpb - 1) / w.tpb;
+  const int TK = D < 16 ? D : 16, TJ = 4, TI = 256 / (TJ * TK);
+  const int HR = (TI + 2) * (TJ + 2) * (TK == 16 ? 24 : 16);
+  const int CS = HR + ((8 - HR) % 128 + 128) % 128;
+  w.lds = ((size_t)16 * w.mco * 264 + (size_t)16 * w.mci * CS) * sizeof(uint16_t);
+  return w;
+}
+
+int64_t wgrad_part_floats(int ks, int64_t P, int D, int cin, int cout) {
+  return wgrad_plan(ks, P, D, cin, cout).nch * (int64_t)ks * ks * ks * cout * cin;
 }
 
 // dw[t][o][i < keep] (row stride keep) and db[o] (nullable) from dy [P][cout], x [P][cin];
-// part holds wgrad_part_floats, cpart wgrad_nch(P) * cout floats
+// part holds wgrad_part_floats, cpart wgrad_plan(...).nch * cout floats
 hipError_t launch_wgrad(int ks, int64_t P, int D, int cin, int cout, int keep, const uint16_t* dy, const uint16_t* x,
                         float* part, float* dw, float* cpart, float* db, hipStream_t st) {
-  const int64_t chunk = wgrad_chunk(P);
-  const int nch = (int)wgrad_nch(P);
   const int T = ks * ks * ks;
   float* dbp = db ? cpart : nullptr;
+  const WgPlan pl = wgrad_plan(ks, P, D, cin, cout);
+  const int nch = (int)pl.nch;
+  if (pl.tiled) {
+    int lg = 0;
+    while ((1 << lg) < D) ++lg;
+    dim3 grid((unsigned)nch, (unsigned)pl.groups, (unsigned)pl.zt);
+#define WT(A, B, U)                                                                                             \
+  do {                                                                                                          \
+    static bool attr = false;                                                                                   \
+    if (!attr) {                                                                                                \
+      hipError_t ea = hipFuncSetAttribute((const void*)k_wgrad3_tiled<A, B, U>,                                 \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);       \
+      if (ea != hipSuccess) return ea;                                                                          \
+      attr = true;                                                                                              \
+    }                                                                                                           \
+    hipLaunchKernelGGL((k_wgrad3_tiled<A, B, U>), grid, dim3(256), pl.lds, st, dy, x, D, lg, cin, cout, pl.nab, \
+                       pl.ntiles, pl.tpb, part, dbp);                                                           \
+  } while (0)
+    if (pl.mco == 1) {
+      if (pl.mci == 2) WT(1, 2, 5);
+      else WT(1, 1, 3);
+    } else if (pl.mco == 2) {
+      if (pl.mci == 2) WT(2, 2, 2);
+      else WT(2, 1, 1);
+    } else {
+      if (pl.mci == 2) WT(4, 2, 1);
+      else WT(4, 1, 1);
+    }
+#undef WT
+  } else {
+  const int64_t chunk = wgrad_chunk(P);
   dim3 grid((unsigned)nch, (unsigned)((T + 3) / 4), (unsigned)(((cout + 63) / 64) * ((cin + 63) / 64)));
   // accumulators for the largest tile of this launch; LDS for its rows
   const int tco = cout < 64 ? cout : 64, tci = cin < 64 ? cin : 64;
@@ -672,6 +926,7 @@ hipError_t launch_wgrad(int ks, int64_t P, int D, int cin, int cout, int keep, c
   else WGB(4);
 #undef WGB
 #undef WG
+  }
   const int64_t per = (int64_t)T * cout * cin;
   hipLaunchKernelGGL(k_reduce_chunks, dim3(nblk(per)), dim3(256), 0, st, part, nch, per, cin, keep, dw);
   if (db)
@@ -789,7 +1044,7 @@ int gpnn_create(const gpnn_arch* a, void* hip_stream, gpnn** out) {
   A(&m->h1, (int64_t)B * a->hidden); A(&m->a1, (int64_t)B * a->hidden);
   A(&m->h2, (int64_t)B * m->F2); A(&m->a2, (int64_t)B * m->F2);
   int64_t maxd = (int64_t)B * std::max(m->F2, a->hidden), maxu = 0, maxpart = 0, maxc = 0;
-  maxpart = std::max(wgrad_part_floats(1, B, a->hidden, m->F2), wgrad_part_floats(1, B, 32, a->hidden));
+  maxpart = std::max(wgrad_part_floats(1, B, 1, a->hidden, m->F2), wgrad_part_floats(1, B, 1, 32, a->hidden));
   maxc = std::max<int64_t>(m->F2, a->hidden);
   for (int s = 1; s <= S; ++s) {
     const int D = a->base << s;
@@ -802,8 +1057,8 @@ int gpnn_create(const gpnn_arch* a, void* hip_stream, gpnn** out) {
     maxd = std::max(maxd, P * a->ch[s]);
     maxd = std::max(maxd, (int64_t)B * vol(D / 2) * a->ch[s - 1]);
     maxu = std::max(maxu, P * a->ch[s - 1]);
-    maxpart = std::max(maxpart, wgrad_part_floats(3, P, a->ch[s - 1], a->ch[s]));
-    maxc = std::max(maxc, wgrad_nch(P) * a->ch[s]);
+    maxpart = std::max(maxpart, wgrad_part_floats(3, P, D, a->ch[s - 1], a->ch[s]));
+    maxc = std::max(maxc, wgrad_plan(3, P, D, a->ch[s - 1], a->ch[s]).nch * a->ch[s]);
   }
   const int64_t PS = (int64_t)B * vol(m->N);
   const int64_t hblocks = (PS + 255) / 256;
@@ -991,8 +1246,9 @@ int gpnn_conv_wgrad(int32_t ks, int32_t n, int32_t d, int32_t cin, int32_t cout,
   const int64_t P = ks == 3 ? (int64_t)n * vol(d) : n;
   hipStream_t st = (hipStream_t)hip_stream;
   float *part = nullptr, *cpart = nullptr;
-  const int64_t nch = wgrad_nch(P);
-  if (hipMalloc((void**)&part, (size_t)wgrad_part_floats(ks, P, cin, cout) * sizeof(float)) != hipSuccess ||
+  const int64_t nch = wgrad_plan(ks, P, ks == 3 ? d : 1, cin, cout).nch;
+  if (hipMalloc((void**)&part, (size_t)wgrad_part_floats(ks, P, ks == 3 ? d : 1, cin, cout) * sizeof(float)) !=
+          hipSuccess ||
       hipMalloc((void**)&cpart, (size_t)nch * cout * sizeof(float)) != hipSuccess) {
     (void)hipGetLastError();
     if (part) (void)hipFree(part);

@@ -107,7 +107,11 @@ def test_dense_forward(cin, cout, n):
     close_bf16(f64(y), R.silu(ref), "silu output")
 
 
-@pytest.mark.parametrize("ks,cin,cout,D,n", [(3, 32, 16, 8, 2), (3, 64, 64, 6, 1), (3, 32, 64, 24, 1),
+# power-of-two grids D >= 8 take the brick-tiled kernel (every tile shape: 16/32/64 output and
+# 16/32 input channels per block, ragged last tiles); the others the position-chunked one
+@pytest.mark.parametrize("ks,cin,cout,D,n", [(3, 32, 16, 8, 2), (3, 64, 64, 8, 2), (3, 64, 32, 16, 2),
+                                             (3, 32, 16, 32, 1), (3, 16, 80, 16, 1), (3, 48, 16, 8, 3),
+                                             (3, 64, 64, 6, 1), (3, 32, 64, 24, 1),
                                              (3, 16, 32, 13, 2), (1, 384, 4096, 1, 16), (1, 32, 384, 1, 7)])
 def test_weight_and_bias_gradients(ks, cin, cout, D, n):
     rng = np.random.default_rng(ks + cin + cout + D)
