@@ -36,15 +36,11 @@ constexpr int kMaxChunks = 128;  // most split-K blocks (partial sums to reduce)
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// round to nearest even; NaN stays NaN
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// round to nearest even (the gfx950 conversion instruction); NaN stays NaN
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f)); }
 
-__device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + __expf(-x)); }
+// hardware reciprocal (1 ulp): the result is rounded to BF16 afterwards
+__device__ __forceinline__ float sigm(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 __device__ __forceinline__ float silu(float x) { return x * sigm(x); }
 __device__ __forceinline__ float silu_d(float x) {
   const float s = sigm(x);
@@ -134,28 +130,95 @@ k_conv(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const flo
   }
 }
 
+// Dense layer for few positions (a batch of problems), split over the input channels:
+// block (16 positions, 64 output channels, input-channel slice blockIdx.z); its 4 waves
+// take interleaved 32-channel steps of the slice, are summed in LDS, and the slice sum goes
+// to part[z][p][cout] for k_dense_finish.  A plain one-tap launch would leave 3 of 4 waves
+// idle at 16 positions and walk all input channels in one wave.
+__global__ void __launch_bounds__(256)
+k_dense_sk(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, int P, int cin, int cout, int kslice,
+           float* __restrict__ part) {
+  __shared__ float red[4][16][65];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, kq = lane >> 4;
+  const int p0 = blockIdx.x * 16, co0 = blockIdx.y * 64;
+  const int nb = min(4, (cout - co0) >> 4);
+  const int kb = blockIdx.z * kslice, ke = min(cin, kb + kslice);
+  const int p = p0 + r;
+  const bool pv = p < P;
+  f32x4 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* xr = x + (int64_t)(pv ? p : 0) * cin + kq * 8;
+  const uint16_t* wr = w + (int64_t)(co0 + r) * cin + kq * 8;
+#pragma unroll 4
+  for (int k0 = kb + wave * 32; k0 < ke; k0 += 128) {
+    const bf16x8 av = pv ? *reinterpret_cast<const bf16x8*>(xr + k0) : bf16x8{};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < nb)
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            av, *reinterpret_cast<const bf16x8*>(wr + (int64_t)j * 16 * cin + k0), acc[j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[wave][kq * 4 + i][j * 16 + r] = acc[j][i];
+  __syncthreads();
+#pragma unroll
+  for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+    const int pr = e >> 6, c = e & 63;
+    if (p0 + pr < P && c < nb * 16)
+      part[((int64_t)blockIdx.z * P + p0 + pr) * cout + co0 + c] = red[0][pr][c] + red[1][pr][c] + red[2][pr][c] +
+                                                                      red[3][pr][c];
+  }
+}
+
+// y[p][o] = epilogue(bias[o] + sum_z part[z][p][o]), epilogue as k_conv
+__global__ void __launch_bounds__(256)
+k_dense_finish(const float* __restrict__ part, int S, int P, int cout, const float* __restrict__ bias, int act,
+               const uint16_t* __restrict__ gate, uint16_t* __restrict__ y, uint16_t* __restrict__ pre) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)P * cout) return;
+  float v = bias ? bias[e % cout] : 0.0f;
+  for (int z = 0; z < S; ++z) v += part[(int64_t)z * P * cout + e];
+  if (pre) pre[e] = f2bf(v);
+  if (gate) v *= silu_d(bf2f(gate[e]));
+  else if (act) v = silu(v);
+  y[e] = f2bf(v);
+}
+
 // 3x3x3 convolution with the input tile staged in LDS, for D^3 grids with D a power of
 // two >= 8.  A block computes a TI x TJ x TK = 256-position brick of one sample (TK =
-// min(D, 16) along z, TJ = 4, TI = 256 / (TJ TK)) for 64 output channels: for each chunk
+// min(D, 16) along z, TJ = 4, TI = 256 / (TJ TK)) for 16 NB output channels: for each chunk
 // of KC input channels it stages the brick's halo ((TI+2)(TJ+2)(TK+2) positions, KC
 // channels, row pitch KC + 8 so the 16 lanes of a fragment hit distinct banks), then runs
-// the 27 taps from LDS.  Each wave owns 4 tiles of 16 positions x up to 4 tiles of 16
-// output channels, so every A fragment (LDS) feeds up to 4 MFMAs and every B fragment
-// (weights, global/L1) feeds 4.  Epilogue as k_conv.
-template <int KC>
+// the 27 taps from LDS.  Each wave owns 4 tiles of 16 positions x NB tiles of 16 output
+// channels, so every A fragment (LDS) feeds NB MFMAs and every B fragment (weights,
+// global/L1) feeds 4.  Latency: a thread's first six halo loads are issued before the
+// barrier that frees the LDS, and the next tap's weight and halo fragments load during
+// the current tap's MFMAs.  Epilogue as k_conv.
+template <int KC, int TK, int NB>
 __global__ void __launch_bounds__(256)
 k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const float* __restrict__ bias, int D,
               int cin, int cout, int act, const uint16_t* __restrict__ gate, uint16_t* __restrict__ y,
               uint16_t* __restrict__ pre) {
   typedef Frag<KC> F;
+  typedef typename F::T FT;
   constexpr int KQ = KC / 4;
   constexpr int PITCH = KC + 8;  // bf16 per halo position
   constexpr int U = KC / 8;      // 16-byte units per position
+  constexpr int TJ = 4, TI = 256 / (TJ * TK);
+  constexpr int HK = TK + 2, HJ = TJ + 2, HI = TI + 2;
+  constexpr int nhalo = HI * HJ * HK;
+  constexpr int NE = (nhalo * U + 255) / 256;  // staged 16-byte units per thread
+  constexpr int NE1 = NE < 6 ? NE : 6;         // of which loaded before the barrier
   extern __shared__ __align__(16) uint16_t halo[];
-  const int TK = D < 16 ? D : 16, TJ = 4, TI = 256 / (TJ * TK);
-  const int HK = TK + 2, HJ = TJ + 2, HI = TI + 2;
-  const int nhalo = HI * HJ * HK;
+  // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous run of
+  // bricks so that neighbouring halos are read through the same L2
   int64_t bq = blockIdx.x;
+  const int64_t nbr = gridDim.x, per = nbr / 8;
+  if (bq < per * 8) bq = (bq % 8) * per + bq / 8;
   const int tkn = D / TK, tjn = D / TJ, tin = D / TI;
   const int k0 = (int)(bq % tkn) * TK;
   bq /= tkn;
@@ -164,8 +227,8 @@ k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, co
   const int i0 = (int)(bq % tin) * TI;
   const int64_t smp = bq / tin;
   const int64_t sbase = smp * D * D * D;
-  const int co0 = blockIdx.y * 64;
-  const int nb = min(4, (cout - co0) >> 4);
+  const int co0 = blockIdx.y * 16 * NB;
+  const int nb = min(NB, (cout - co0) >> 4);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, kq = lane >> 4;
   int hbase[4];
@@ -173,52 +236,114 @@ k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, co
   for (int mb = 0; mb < 4; ++mb) {
     const int tp = wave * 64 + mb * 16 + r;
     const int tk = tp % TK, tj = (tp / TK) % TJ, ti = tp / (TK * TJ);
-    hbase[mb] = ((ti + 1) * HJ + (tj + 1)) * HK + (tk + 1);
+    hbase[mb] = (((ti + 1) * HJ + (tj + 1)) * HK + (tk + 1)) * PITCH + kq * KQ;
   }
-  f32x4 acc[4][4];
+  // this thread's halo units: grid position within the sample (-1 outside) and LDS offset
+  int gpos[NE], lofs[NE];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[mb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int ci0 = 0; ci0 < cin; ci0 += KC) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < nhalo * U; e += 256) {
+  for (int m = 0; m < NE; ++m) {
+    const int e = threadIdx.x + 256 * m;
+    gpos[m] = -1;
+    lofs[m] = -1;
+    if (e < nhalo * U) {
       const int hp = e / U, u = e % U;
       const int hk = hp % HK, hj = (hp / HK) % HJ, hi = hp / (HK * HJ);
       const int gi = i0 - 1 + hi, gj = j0 - 1 + hj, gk = k0 - 1 + hk;
-      uint4 v = make_uint4(0, 0, 0, 0);
+      lofs[m] = hp * PITCH + u * 8;
       if ((unsigned)gi < (unsigned)D && (unsigned)gj < (unsigned)D && (unsigned)gk < (unsigned)D)
-        v = *reinterpret_cast<const uint4*>(x + (sbase + ((int64_t)gi * D + gj) * D + gk) * cin + ci0 + u * 8);
-      *reinterpret_cast<uint4*>(halo + hp * PITCH + u * 8) = v;
+        gpos[m] = (gi * D + gj) * D + gk;
+    }
+  }
+  const uint16_t* xs = x + sbase * cin;
+  f32x4 acc[4][NB];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[mb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ci0 = 0; ci0 < cin; ci0 += KC) {
+    // the first NE1 halo loads and the first tap's weights in flight across the barrier
+    uint4 v[NE1];
+#pragma unroll
+    for (int m = 0; m < NE1; ++m) {
+      v[m] = make_uint4(0, 0, 0, 0);
+      if (gpos[m] >= 0) v[m] = *reinterpret_cast<const uint4*>(xs + (int64_t)gpos[m] * cin + ci0 + (lofs[m] % PITCH));
+    }
+    const uint16_t* wbase = w + ((int64_t)co0 + r) * cin + ci0 + kq * KQ;
+    FT bv[NB], bn[NB], av[4], an[4];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) bv[j] = j < nb ? F::load(wbase + (int64_t)j * 16 * cin) : F::zero();
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NE1; ++m)
+      if (lofs[m] >= 0) *reinterpret_cast<uint4*>(halo + lofs[m]) = v[m];
+    if (NE > NE1) {
+      uint4 v2[NE - NE1 > 0 ? NE - NE1 : 1];
+#pragma unroll
+      for (int m = NE1; m < NE; ++m) {
+        v2[m - NE1] = make_uint4(0, 0, 0, 0);
+        if (gpos[m] >= 0)
+          v2[m - NE1] = *reinterpret_cast<const uint4*>(xs + (int64_t)gpos[m] * cin + ci0 + (lofs[m] % PITCH));
+      }
+#pragma unroll
+      for (int m = NE1; m < NE; ++m)
+        if (lofs[m] >= 0) *reinterpret_cast<uint4*>(halo + lofs[m]) = v2[m - NE1];
     }
     __syncthreads();
-    for (int t = 0; t < 27; ++t) {
-      const int toff = ((t / 9 - 1) * HJ + ((t / 3) % 3 - 1)) * HK + (t % 3 - 1);
-      const uint16_t* wt = w + ((int64_t)t * cout + co0 + r) * cin + ci0 + kq * KQ;
-      typename F::T bv[4];
+    // the fragments of tap t + 1 load while tap t's MFMAs run (for one output tile, taps
+    // in pairs with two register sets and no copies between them)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = j < nb ? F::load(wt + (int64_t)j * 16 * cin) : F::zero();
+    for (int mb = 0; mb < 4; ++mb) av[mb] = F::load(halo + hbase[mb] + (((-1) * HJ + (-1)) * HK + (-1)) * PITCH);
+    auto fetch = [&](int tn, FT* ax, FT* bx) {
+      const int toffn = ((tn / 9 - 1) * HJ + ((tn / 3) % 3 - 1)) * HK + (tn % 3 - 1);
+      const uint16_t* wt = wbase + (int64_t)tn * cout * cin;
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        const typename F::T av = F::load(halo + (hbase[mb] + toff) * PITCH + kq * KQ);
+      for (int j = 0; j < NB; ++j) bx[j] = j < nb ? F::load(wt + (int64_t)j * 16 * cin) : F::zero();
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (j < nb) acc[mb][j] = F::mma(av, bv[j], acc[mb][j]);
+      for (int mb = 0; mb < 4; ++mb) ax[mb] = F::load(halo + hbase[mb] + toffn * PITCH);
+    };
+    auto mfmas = [&](const FT* ac, const FT* bc) {
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (j < nb) acc[mb][j] = F::mma(ac[mb], bc[j], acc[mb][j]);
+    };
+    if constexpr (NB == 1) {
+#pragma unroll 1
+      for (int t = 0; t < 26; t += 2) {
+        fetch(t + 1, an, bn);
+        mfmas(av, bv);
+        fetch(t + 2, av, bv);
+        mfmas(an, bn);
+      }
+      mfmas(av, bv);  // tap 26
+    } else {
+      // wider output tiles: one register set plus copies keeps the occupancy
+#pragma unroll 1
+      for (int t = 0; t < 27; ++t) {
+        if (t + 1 < 27) fetch(t + 1, an, bn);
+        mfmas(av, bv);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) bv[j] = bn[j];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) av[mb] = an[mb];
       }
     }
   }
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NB; ++j) {
       if (j >= nb) continue;
       const int co = co0 + j * 16 + r;
       const float bvv = bias ? bias[co] : 0.0f;
+      // the 4 rows of a lane are consecutive positions along z
+      const int tp = wave * 64 + mb * 16 + kq * 4;
+      const int tk = tp % TK, tj = (tp / TK) % TJ, ti = tp / (TK * TJ);
+      const int64_t o0 = (sbase + ((int64_t)(i0 + ti) * D + (j0 + tj)) * D + (k0 + tk)) * cout + co;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int tp = wave * 64 + mb * 16 + kq * 4 + i;
-        const int tk = tp % TK, tj = (tp / TK) % TJ, ti = tp / (TK * TJ);
-        const int64_t o = (sbase + ((int64_t)(i0 + ti) * D + (j0 + tj)) * D + (k0 + tk)) * cout + co;
+        const int64_t o = o0 + (int64_t)i * cout;
         float v = acc[mb][j][i] + bvv;
         if (pre) pre[o] = f2bf(v);
         if (gate) v *= silu_d(bf2f(gate[o]));
@@ -790,9 +915,31 @@ namespace {
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// input-channel slice of the split dense layer: a multiple of 128 (4 waves x 32), at most
+// 8 slices
+int dense_kslice(int cin) {
+  const int ks = (cin + 7) / 8;
+  return ((ks + 127) / 128) * 128;
+}
+int64_t dense_ws_floats(int64_t P, int cin, int cout) {
+  const int kslice = dense_kslice(cin);
+  return (int64_t)((cin + kslice - 1) / kslice) * P * cout;
+}
+
+// ws (nullable): FP32 workspace of ws_floats; with room for dense_ws_floats, one-tap
+// layers over at most 64 positions take the split path
 hipError_t launch_conv(int ks, int64_t P, int D, int cin, int cout, const uint16_t* x, const uint16_t* w,
                        const float* bias, int act, const uint16_t* gate, uint16_t* y, uint16_t* pre,
-                       hipStream_t st) {
+                       hipStream_t st, float* ws = nullptr, int64_t ws_floats = 0) {
+  if (ks == 1 && P <= 64 && cin % 32 == 0 && ws && dense_ws_floats(P, cin, cout) <= ws_floats) {
+    const int kslice = dense_kslice(cin);
+    const int S = (cin + kslice - 1) / kslice;
+    dim3 g((unsigned)((P + 15) / 16), (unsigned)((cout + 63) / 64), (unsigned)S);
+    hipLaunchKernelGGL(k_dense_sk, g, dim3(256), 0, st, x, w, (int)P, cin, cout, kslice, ws);
+    hipLaunchKernelGGL(k_dense_finish, dim3(nblk(P * cout)), dim3(256), 0, st, ws, S, (int)P, cout, bias, act, gate,
+                       y, pre);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64));
   const bool k32 = cin % 32 == 0;
   // tiled path: D a power of two >= 8 and P a whole number of D^3 samples
@@ -800,9 +947,24 @@ hipError_t launch_conv(int ks, int64_t P, int D, int cin, int cout, const uint16
   if (ks == 3 && pow2) {
     const int TK = D < 16 ? D : 16, TJ = 4, TI = 256 / (TJ * TK);
     const size_t lds = (size_t)(TI + 2) * (TJ + 2) * (TK + 2) * ((k32 ? 32 : 16) + 8) * sizeof(uint16_t);
-    dim3 tg((unsigned)(P / 256), (unsigned)((cout + 63) / 64));
-    if (k32) hipLaunchKernelGGL((k_conv3_tiled<32>), tg, dim3(256), lds, st, x, w, bias, D, cin, cout, act, gate, y, pre);
-    else hipLaunchKernelGGL((k_conv3_tiled<16>), tg, dim3(256), lds, st, x, w, bias, D, cin, cout, act, gate, y, pre);
+    const int nbt = cout <= 16 ? 1 : cout <= 32 ? 2 : 4;  // 16-channel output blocks per wave
+    dim3 tg((unsigned)(P / 256), (unsigned)((cout + 16 * nbt - 1) / (16 * nbt)));
+#define CT(A, B, C) hipLaunchKernelGGL((k_conv3_tiled<A, B, C>), tg, dim3(256), lds, st, x, w, bias, D, cin, cout, act, gate, y, pre)
+#define CTN(A, B)     \
+  do {                \
+    if (nbt == 1) CT(A, B, 1); \
+    else if (nbt == 2) CT(A, B, 2); \
+    else CT(A, B, 4); \
+  } while (0)
+    if (k32) {
+      if (TK == 16) CTN(32, 16);
+      else CTN(32, 8);
+    } else {
+      if (TK == 16) CTN(16, 16);
+      else CTN(16, 8);
+    }
+#undef CTN
+#undef CT
     return hipGetLastError();
   }
   if (ks == 3) {
@@ -824,7 +986,7 @@ int64_t wgrad_nch(int64_t P) { return (P + wgrad_chunk(P) - 1) / wgrad_chunk(P);
 
 // Launch shape of one weight gradient.  Tiled (k_wgrad3_tiled) for 3x3x3 taps on a
 // power-of-two grid D >= 8 holding whole samples: units of (tap pair, 16 input channels)
-// spread over the 4 waves with at most ~64 accumulators per lane, the rest of the grid
+// spread over the 4 waves with at most 120 accumulators per lane, the rest of the grid
 // split into runs of bricks so that about kTiledBlocks blocks are in flight.
 constexpr int kTiledBlocks = 512;
 struct WgPlan {
@@ -844,7 +1006,7 @@ WgPlan wgrad_plan(int ks, int64_t P, int D, int cin, int cout) {
   const int tco = cout < 64 ? cout : 64;
   w.mco = tco <= 16 ? 1 : tco <= 32 ? 2 : 4;
   w.mci = cin >= 32 ? 2 : 1;
-  w.nab = w.mco == 1 ? 9 : w.mco == 2 ? 3 : 2;
+  w.nab = w.mco <= 2 ? 9 : 3;
   w.nu = (w.nab * w.mci + 3) / 4;
   w.groups = (9 + w.nab - 1) / w.nab;
   w.zt = ((cout + 16 * w.mco - 1) / (16 * w.mco)) * ((cin + 16 * w.mci - 1) / (16 * w.mci));
@@ -893,10 +1055,10 @@ hipError_t launch_wgrad(int ks, int64_t P, int D, int cin, int cout, int keep, c
       if (pl.mci == 2) WT(1, 2, 5);
       else WT(1, 1, 3);
     } else if (pl.mco == 2) {
-      if (pl.mci == 2) WT(2, 2, 2);
-      else WT(2, 1, 1);
+      if (pl.mci == 2) WT(2, 2, 5);
+      else WT(2, 1, 3);
     } else {
-      if (pl.mci == 2) WT(4, 2, 1);
+      if (pl.mci == 2) WT(4, 2, 2);
       else WT(4, 1, 1);
     }
 #undef WT
@@ -951,6 +1113,7 @@ struct gpnn {
   uint16_t *u[7] = {}, *h[7] = {}, *act[7] = {};
   uint16_t *dA = nullptr, *dB = nullptr, *dU = nullptr;
   float *part = nullptr, *cpart = nullptr, *gpart = nullptr;
+  int64_t npart = 0;  // floats in part
   double *lpart = nullptr, *lsum = nullptr;
   std::vector<void*> allocs;
   // last forward
@@ -1064,6 +1227,9 @@ int gpnn_create(const gpnn_arch* a, void* hip_stream, gpnn** out) {
   const int64_t hblocks = (PS + 255) / 256;
   maxc = std::max(maxc, ((hblocks + 127) / 128) * (a->ch[S] + 1));  // head partials, first stage
   A(&m->dA, maxd); A(&m->dB, maxd); A(&m->dU, maxu);
+  maxpart = std::max(maxpart, std::max(dense_ws_floats(B, 32, a->hidden),
+                                       std::max(dense_ws_floats(B, a->hidden, m->F2), dense_ws_floats(B, m->F2, a->hidden))));
+  m->npart = maxpart;
   A(&m->part, maxpart); A(&m->cpart, maxc);
   A(&m->gpart, hblocks * (a->ch[S] + 1));
   A(&m->lpart, hblocks); A(&m->lsum, 1);
@@ -1125,9 +1291,11 @@ int gpnn_forward(gpnn* m, const float* prm, int32_t n, void* out, int32_t out_co
   const gpnn_arch& a = m->a;
   hipStream_t st = m->st;
   hipLaunchKernelGGL(k_features, dim3(nblk((int64_t)n * 32)), dim3(256), 0, st, prm, n, m->ms, m->z0);
-  hipError_t e = launch_conv(1, n, 1, 32, a.hidden, m->z0, m->W1p, m->w + m->ob1, 1, nullptr, m->a1, m->h1, st);
+  hipError_t e = launch_conv(1, n, 1, 32, a.hidden, m->z0, m->W1p, m->w + m->ob1, 1, nullptr, m->a1, m->h1, st,
+                             m->part, m->npart);
   if (e == hipSuccess)
-    e = launch_conv(1, n, 1, a.hidden, m->F2, m->a1, m->W2, m->w + m->ob2, 1, nullptr, m->a2, m->h2, st);
+    e = launch_conv(1, n, 1, a.hidden, m->F2, m->a1, m->W2, m->w + m->ob2, 1, nullptr, m->a2, m->h2, st, m->part,
+                    m->npart);
   const uint16_t* prev = m->a2;
   for (int s = 1; s <= m->S && e == hipSuccess; ++s) {
     const int Dc = a.base << (s - 1), D = a.base << s;
@@ -1200,7 +1368,7 @@ int gpnn_loss_backward(gpnn* m, const float* tgt, double* loss) {
     e = launch_wgrad(1, n, 1, a.hidden, m->F2, a.hidden, dh, m->a1, m->part, m->g + m->oW2, m->cpart, m->g + m->ob2,
                      st);
   if (e == hipSuccess)
-    e = launch_conv(1, n, 1, m->F2, a.hidden, dh, m->W2t, nullptr, 0, m->h1, other, nullptr, st);
+    e = launch_conv(1, n, 1, m->F2, a.hidden, dh, m->W2t, nullptr, 0, m->h1, other, nullptr, st, m->part, m->npart);
   if (e == hipSuccess)
     e = launch_wgrad(1, n, 1, 32, a.hidden, 4, other, m->z0, m->part, m->g + m->oW1, m->cpart, m->g + m->ob1, st);
   if (e != hipSuccess) return hip_chk(m, e, "backward");
@@ -1232,9 +1400,16 @@ int gpnn_conv(int32_t ks, int32_t n, int32_t d, int32_t cin, int32_t cout, const
     return GPNN_ERR_INVALID;
   const int64_t P = ks == 3 ? (int64_t)n * vol(d) : n;
   hipStream_t st = (hipStream_t)hip_stream;
+  float* ws = nullptr;
+  const int64_t nws = ks == 1 ? dense_ws_floats(P, cin, cout) : 0;
+  if (nws > 0 && hipMalloc((void**)&ws, (size_t)nws * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    return GPNN_ERR_OOM;
+  }
   hipError_t e = launch_conv(ks, P, ks == 3 ? d : 1, cin, cout, (const uint16_t*)x, (const uint16_t*)w, bias, act,
-                             (const uint16_t*)gate, (uint16_t*)y, (uint16_t*)pre, st);
+                             (const uint16_t*)gate, (uint16_t*)y, (uint16_t*)pre, st, ws, nws);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (ws) (void)hipFree(ws);
   return e == hipSuccess ? GPNN_OK : GPNN_ERR_HIP;
 }
 

@@ -91,7 +91,10 @@ def test_conv3d_input_gradient_by_mirrored_weights_with_gate(cin, cout, D, n):
     close_bf16(f64(dx), ref, "input gradient")
 
 
-@pytest.mark.parametrize("cin,cout,n", [(32, 384, 16), (384, 4096, 16), (4096, 384, 5), (32, 64, 3)])
+# up to 64 positions with cin a multiple of 32: split over input channels; otherwise one tap
+# of the convolution kernel
+@pytest.mark.parametrize("cin,cout,n", [(32, 384, 16), (384, 4096, 16), (4096, 384, 5), (32, 64, 3), (4096, 80, 64),
+                                        (64, 48, 100), (48, 64, 10)])
 def test_dense_forward(cin, cout, n):
     rng = np.random.default_rng(cin + cout + n)
     x = bf(rng.standard_normal((n, cin)))
