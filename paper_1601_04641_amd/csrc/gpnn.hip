@@ -563,51 +563,106 @@ k_wgrad3_tiled(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, 
   float dbacc = 0.0f;
   const int tkn = D / TK, tjn = D / TJ, tin = D / TI;
   const int tb0 = blockIdx.x * tpb, tb1 = min(ntiles, tb0 + tpb);
-  for (int tb = tb0; tb < tb1; ++tb) {
+  // staging of a brick: global loads into registers, then position pairs packed into
+  // 32-bit LDS words.  Where the accumulators leave room for it at two waves per SIMD, the
+  // next brick's loads are in flight while the current one is computed.
+  struct Org {
+    int i0, j0, k0;
+    int64_t sbase;
+  };
+  auto origin = [&](int tb) {
+    Org o;
     int q = tb;
-    const int k0 = (q % tkn) * TK;
+    o.k0 = (q % tkn) * TK;
     q /= tkn;
-    const int j0 = (q % tjn) * TJ;
+    o.j0 = (q % tjn) * TJ;
     q /= tjn;
-    const int i0 = (q % tin) * TI;
-    const int64_t sbase = (int64_t)(q / tin) << (3 * lg);
-    __syncthreads();
-    // dy: 128 position pairs x (16 MCO / 8) channel groups
+    o.i0 = (q % tin) * TI;
+    o.sbase = (int64_t)(q / tin) << (3 * lg);
+    return o;
+  };
+  // dy: 128 position pairs x (16 MCO / 8) channel groups
+  auto load_dy = [&](int m, const Org& o, uint4& v0, uint4& v1) {
+    const int n = threadIdx.x + 256 * m;
+    const int pp = n & 127, cg = n >> 7;
+    if (cg * 8 >= nco) return;
+    const int p = 2 * pp;
+    const int kk = p & (TK - 1), jj = (p >> lgk) & 3, ii = p >> (lgk + 2);
+    const int64_t g = o.sbase + ((int64_t)(o.i0 + ii) << (2 * lg)) + ((o.j0 + jj) << lg) + (o.k0 + kk);
+    v0 = *reinterpret_cast<const uint4*>(dy + g * cout + co0 + cg * 8);
+    v1 = *reinterpret_cast<const uint4*>(dy + (g + 1) * cout + co0 + cg * 8);
+  };
+  auto store_dy = [&](int m, const uint4& v0, const uint4& v1) {
+    const int n = threadIdx.x + 256 * m;
+    const int pp = n & 127, cg = n >> 7;
+    if (cg * 8 >= nco) return;
+    const uint16_t* e0 = reinterpret_cast<const uint16_t*>(&v0);
+    const uint16_t* e1 = reinterpret_cast<const uint16_t*>(&v1);
+    uint32_t* d32 = reinterpret_cast<uint32_t*>(sdy);
 #pragma unroll
-    for (int m = 0; m < MCO; ++m) {
-      const int n = threadIdx.x + 256 * m;
-      const int pp = n & 127, cg = n >> 7;
-      if (cg * 8 < nco) {
-        const int p = 2 * pp;
-        const int kk = p & (TK - 1), jj = (p >> lgk) & 3, ii = p >> (lgk + 2);
-        const int64_t g = sbase + ((int64_t)(i0 + ii) << (2 * lg)) + ((j0 + jj) << lg) + (k0 + kk);
-        const uint4 v0 = *reinterpret_cast<const uint4*>(dy + g * cout + co0 + cg * 8);
-        const uint4 v1 = *reinterpret_cast<const uint4*>(dy + (g + 1) * cout + co0 + cg * 8);
-        const uint16_t* e0 = reinterpret_cast<const uint16_t*>(&v0);
-        const uint16_t* e1 = reinterpret_cast<const uint16_t*>(&v1);
-        uint32_t* d32 = reinterpret_cast<uint32_t*>(sdy);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) d32[((cg * 8 + e) * DP + p) >> 1] = (uint32_t)e0[e] | ((uint32_t)e1[e] << 16);
-      }
+    for (int e = 0; e < 8; ++e) d32[((cg * 8 + e) * DP >> 1) + pp] = (uint32_t)e0[e] | ((uint32_t)e1[e] << 16);
+  };
+  // x halo of the input tile, zero outside the grid
+  auto load_x = [&](int m, const Org& o, uint4& v0, uint4& v1) {
+    v0 = make_uint4(0, 0, 0, 0);
+    v1 = v0;
+    if (xl[m] < 0) return;
+    const int gi = o.i0 + (xg[m] & 255) - 1, gj = o.j0 + ((xg[m] >> 8) & 255) - 1;
+    const int gk = o.k0 + ((xg[m] >> 16) & 255) - 1, cg = xg[m] >> 24;
+    if ((unsigned)gi < (unsigned)D && (unsigned)gj < (unsigned)D) {
+      const int64_t g = o.sbase + ((int64_t)gi << (2 * lg)) + (gj << lg) + gk;
+      const uint16_t* src = x + g * cin + ci0 + cg * 8;
+      if ((unsigned)gk < (unsigned)D) v0 = *reinterpret_cast<const uint4*>(src);
+      if ((unsigned)(gk + 1) < (unsigned)D) v1 = *reinterpret_cast<const uint4*>(src + cin);
     }
-    // x halo of the input tile, zero outside the grid
+  };
+  auto store_x = [&](int m, const uint4& v0, const uint4& v1) {
+    if (xl[m] < 0) return;
+    const uint16_t* e0 = reinterpret_cast<const uint16_t*>(&v0);
+    const uint16_t* e1 = reinterpret_cast<const uint16_t*>(&v1);
+    uint32_t* x32 = reinterpret_cast<uint32_t*>(sx);
 #pragma unroll
-    for (int m = 0; m < MU; ++m) {
-      if (xl[m] < 0) continue;
-      const int gi = i0 + (xg[m] & 255) - 1, gj = j0 + ((xg[m] >> 8) & 255) - 1;
-      const int gk = k0 + ((xg[m] >> 16) & 255) - 1, cg = xg[m] >> 24;
-      uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
-      if ((unsigned)gi < (unsigned)D && (unsigned)gj < (unsigned)D) {
-        const int64_t g = sbase + ((int64_t)gi << (2 * lg)) + (gj << lg) + gk;
-        const uint16_t* src = x + g * cin + ci0 + cg * 8;
-        if ((unsigned)gk < (unsigned)D) v0 = *reinterpret_cast<const uint4*>(src);
-        if ((unsigned)(gk + 1) < (unsigned)D) v1 = *reinterpret_cast<const uint4*>(src + cin);
+    for (int e = 0; e < 8; ++e) x32[xl[m] + e * (CS >> 1)] = (uint32_t)e0[e] | ((uint32_t)e1[e] << 16);
+  };
+  constexpr bool PIPE = MCO <= 2 && MCO * NU * 12 <= 72;
+  uint4 rdy[PIPE ? MCO : 1][2], rx[PIPE ? MU : 1][2];
+  if constexpr (PIPE) {
+    if (tb0 < tb1) {
+      const Org o = origin(tb0);
+#pragma unroll
+      for (int m = 0; m < MCO; ++m) load_dy(m, o, rdy[m][0], rdy[m][1]);
+#pragma unroll
+      for (int m = 0; m < MU; ++m) load_x(m, o, rx[m][0], rx[m][1]);
+    }
+  }
+  for (int tb = tb0; tb < tb1; ++tb) {
+    __syncthreads();
+    if constexpr (PIPE) {
+#pragma unroll
+      for (int m = 0; m < MCO; ++m) store_dy(m, rdy[m][0], rdy[m][1]);
+#pragma unroll
+      for (int m = 0; m < MU; ++m) store_x(m, rx[m][0], rx[m][1]);
+      if (tb + 1 < tb1) {
+        const Org o = origin(tb + 1);
+#pragma unroll
+        for (int m = 0; m < MCO; ++m) load_dy(m, o, rdy[m][0], rdy[m][1]);
+#pragma unroll
+        for (int m = 0; m < MU; ++m) load_x(m, o, rx[m][0], rx[m][1]);
       }
-      const uint16_t* e0 = reinterpret_cast<const uint16_t*>(&v0);
-      const uint16_t* e1 = reinterpret_cast<const uint16_t*>(&v1);
-      uint32_t* d32 = reinterpret_cast<uint32_t*>(sx);
+    } else {
+      const Org o = origin(tb);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) d32[xl[m] + e * (CS >> 1)] = (uint32_t)e0[e] | ((uint32_t)e1[e] << 16);
+      for (int m = 0; m < MCO; ++m) {
+        uint4 v0, v1;
+        load_dy(m, o, v0, v1);
+        store_dy(m, v0, v1);
+      }
+#pragma unroll
+      for (int m = 0; m < MU; ++m) {
+        uint4 v0, v1;
+        load_x(m, o, v0, v1);
+        store_x(m, v0, v1);
+      }
     }
     __syncthreads();
     if (do_db && (threadIdx.x >> 2) < nco) {
