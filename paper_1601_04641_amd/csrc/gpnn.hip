@@ -33,6 +33,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr float kFMax = 10.0f;   // psi = exp(min(f, kFMax))
 constexpr int kChunkMin = 2048;  // fewest positions per split-K block of the weight gradient
 constexpr int kMaxChunks = 128;  // most split-K blocks (partial sums to reduce) per tap
+constexpr int kConvBlocks = 768;  // blocks of the tiled convolution (about 3 per CU)
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -189,20 +190,22 @@ k_dense_finish(const float* __restrict__ part, int S, int P, int cout, const flo
 }
 
 // 3x3x3 convolution with the input tile staged in LDS, for D^3 grids with D a power of
-// two >= 8.  A block computes a TI x TJ x TK = 256-position brick of one sample (TK =
-// min(D, 16) along z, TJ = 4, TI = 256 / (TJ TK)) for 16 NB output channels: for each chunk
-// of KC input channels it stages the brick's halo ((TI+2)(TJ+2)(TK+2) positions, KC
-// channels, row pitch KC + 8 so the 16 lanes of a fragment hit distinct banks), then runs
-// the 27 taps from LDS.  Each wave owns 4 tiles of 16 positions x NB tiles of 16 output
-// channels, so every A fragment (LDS) feeds NB MFMAs and every B fragment (weights,
-// global/L1) feeds 4.  Latency: a thread's first six halo loads are issued before the
-// barrier that frees the LDS, and the next tap's weight and halo fragments load during
-// the current tap's MFMAs.  Epilogue as k_conv.
+// two >= 8.  Work item: a TI x TJ x TK = 256-position brick of one sample (TK = min(D, 16)
+// along z, TJ = 4, TI = 256 / (TJ TK)), 16 NB output channels (blockIdx.y), one chunk of
+// KC input channels.  For each item a block stages the brick's halo ((TI+2)(TJ+2)(TK+2)
+// positions, KC channels, row pitch KC + 8 so the 16 lanes of a fragment hit distinct
+// banks), then runs the 27 taps from LDS; each wave owns 4 tiles of 16 positions x NB
+// tiles of 16 output channels, so every A fragment (LDS) feeds NB MFMAs and every B
+// fragment (weights, global/L1) feeds 4.  A block walks several bricks; for single output
+// tiles the next item's halo loads are in flight while the current item's MFMAs run, and
+// always the next tap's weight and halo fragments while the current tap's do.  Bricks are dealt so that the blocks on
+// one XCD (workgroups go round-robin to the 8 XCDs) work on one contiguous stretch of the
+// grid at a time, sharing halos through that XCD's L2.  Epilogue as k_conv.
 template <int KC, int TK, int NB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB <= 2 ? 3 : 1)))
 k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const float* __restrict__ bias, int D,
               int cin, int cout, int act, const uint16_t* __restrict__ gate, uint16_t* __restrict__ y,
-              uint16_t* __restrict__ pre) {
+              uint16_t* __restrict__ pre, int nbrick) {
   typedef Frag<KC> F;
   typedef typename F::T FT;
   constexpr int KQ = KC / 4;
@@ -212,21 +215,23 @@ k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, co
   constexpr int HK = TK + 2, HJ = TJ + 2, HI = TI + 2;
   constexpr int nhalo = HI * HJ * HK;
   constexpr int NE = (nhalo * U + 255) / 256;  // staged 16-byte units per thread
-  constexpr int NE1 = NE < 6 ? NE : 6;         // of which loaded before the barrier
   extern __shared__ __align__(16) uint16_t halo[];
-  // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous run of
-  // bricks so that neighbouring halos are read through the same L2
-  int64_t bq = blockIdx.x;
-  const int64_t nbr = gridDim.x, per = nbr / 8;
-  if (bq < per * 8) bq = (bq % 8) * per + bq / 8;
+  // this block's bricks: brick(it) for it = 0, 1, ... while < nmine
+  const int G = gridDim.x, b = blockIdx.x;
+  int first, stride, nmine;
+  if (nbrick % 8 == 0 && G % 8 == 0) {
+    const int per = nbrick / 8, nslot = G / 8, slot = b / 8;
+    first = (b % 8) * per + slot;
+    stride = nslot;
+    nmine = slot < per ? (per - slot + nslot - 1) / nslot : 0;
+  } else {
+    first = b;
+    stride = G;
+    nmine = b < nbrick ? (nbrick - b + G - 1) / G : 0;
+  }
+  const int nchunk = cin / KC;
+  const int nitem = nmine * nchunk;
   const int tkn = D / TK, tjn = D / TJ, tin = D / TI;
-  const int k0 = (int)(bq % tkn) * TK;
-  bq /= tkn;
-  const int j0 = (int)(bq % tjn) * TJ;
-  bq /= tjn;
-  const int i0 = (int)(bq % tin) * TI;
-  const int64_t smp = bq / tin;
-  const int64_t sbase = smp * D * D * D;
   const int co0 = blockIdx.y * 16 * NB;
   const int nb = min(NB, (cout - co0) >> 4);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -238,59 +243,73 @@ k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, co
     const int tk = tp % TK, tj = (tp / TK) % TJ, ti = tp / (TK * TJ);
     hbase[mb] = (((ti + 1) * HJ + (tj + 1)) * HK + (tk + 1)) * PITCH + kq * KQ;
   }
-  // this thread's halo units: grid position within the sample (-1 outside) and LDS offset
-  int gpos[NE], lofs[NE];
+  struct Brick {
+    int i0, j0, k0;
+    int64_t sbase;
+  };
+  auto brick = [&](int it) {
+    Brick o;
+    int q = first + it * stride;
+    o.k0 = (q % tkn) * TK;
+    q /= tkn;
+    o.j0 = (q % tjn) * TJ;
+    q /= tjn;
+    o.i0 = (q % tin) * TI;
+    o.sbase = (int64_t)(q / tin) * D * D * D;
+    return o;
+  };
+  uint4 v[NE];
+  auto load_item = [&](int item, int m0, int m1) {
+    const Brick o = brick(item / nchunk);
+    const int ci0 = (item % nchunk) * KC;
+    const uint16_t* xs = x + o.sbase * cin + ci0;
 #pragma unroll
-  for (int m = 0; m < NE; ++m) {
-    const int e = threadIdx.x + 256 * m;
-    gpos[m] = -1;
-    lofs[m] = -1;
-    if (e < nhalo * U) {
-      const int hp = e / U, u = e % U;
-      const int hk = hp % HK, hj = (hp / HK) % HJ, hi = hp / (HK * HJ);
-      const int gi = i0 - 1 + hi, gj = j0 - 1 + hj, gk = k0 - 1 + hk;
-      lofs[m] = hp * PITCH + u * 8;
-      if ((unsigned)gi < (unsigned)D && (unsigned)gj < (unsigned)D && (unsigned)gk < (unsigned)D)
-        gpos[m] = (gi * D + gj) * D + gk;
+    for (int m = 0; m < NE; ++m) {
+      if (m < m0 || m >= m1) continue;
+      const int e = threadIdx.x + 256 * m;
+      v[m] = make_uint4(0, 0, 0, 0);
+      if (e < nhalo * U) {
+        const int hp = e / U, u = e % U;
+        const int hk = hp % HK, hj = (hp / HK) % HJ, hi = hp / (HK * HJ);
+        const int gi = o.i0 - 1 + hi, gj = o.j0 - 1 + hj, gk = o.k0 - 1 + hk;
+        if ((unsigned)gi < (unsigned)D && (unsigned)gj < (unsigned)D && (unsigned)gk < (unsigned)D)
+          v[m] = *reinterpret_cast<const uint4*>(xs + (int64_t)((gi * D + gj) * D + gk) * cin + u * 8);
+      }
     }
-  }
-  const uint16_t* xs = x + sbase * cin;
+  };
   f32x4 acc[4][NB];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[mb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int ci0 = 0; ci0 < cin; ci0 += KC) {
-    // the first NE1 halo loads and the first tap's weights in flight across the barrier
-    uint4 v[NE1];
+  auto store_item = [&](int m0, int m1) {
 #pragma unroll
-    for (int m = 0; m < NE1; ++m) {
-      v[m] = make_uint4(0, 0, 0, 0);
-      if (gpos[m] >= 0) v[m] = *reinterpret_cast<const uint4*>(xs + (int64_t)gpos[m] * cin + ci0 + (lofs[m] % PITCH));
+    for (int m = 0; m < NE; ++m) {
+      if (m < m0 || m >= m1) continue;
+      const int e = threadIdx.x + 256 * m;
+      if (e < nhalo * U) *reinterpret_cast<uint4*>(halo + (e / U) * PITCH + (e % U) * 8) = v[m];
     }
+  };
+  // prefetching the whole next item costs NE x 4 registers: single output tiles only;
+  // wider tiles issue their first NE1 loads before the barrier that frees the LDS
+  constexpr bool PIPE = NB == 1;
+  constexpr int NE1 = PIPE ? NE : (NE < 6 ? NE : 6);
+  if (PIPE && nitem > 0) load_item(0, 0, NE);
+  for (int item = 0; item < nitem; ++item) {
+    if (!PIPE) load_item(item, 0, NE1);
+    const int ci0 = (item % nchunk) * KC;
     const uint16_t* wbase = w + ((int64_t)co0 + r) * cin + ci0 + kq * KQ;
     FT bv[NB], bn[NB], av[4], an[4];
 #pragma unroll
     for (int j = 0; j < NB; ++j) bv[j] = j < nb ? F::load(wbase + (int64_t)j * 16 * cin) : F::zero();
     __syncthreads();
-#pragma unroll
-    for (int m = 0; m < NE1; ++m)
-      if (lofs[m] >= 0) *reinterpret_cast<uint4*>(halo + lofs[m]) = v[m];
-    if (NE > NE1) {
-      uint4 v2[NE - NE1 > 0 ? NE - NE1 : 1];
-#pragma unroll
-      for (int m = NE1; m < NE; ++m) {
-        v2[m - NE1] = make_uint4(0, 0, 0, 0);
-        if (gpos[m] >= 0)
-          v2[m - NE1] = *reinterpret_cast<const uint4*>(xs + (int64_t)gpos[m] * cin + ci0 + (lofs[m] % PITCH));
-      }
-#pragma unroll
-      for (int m = NE1; m < NE; ++m)
-        if (lofs[m] >= 0) *reinterpret_cast<uint4*>(halo + lofs[m]) = v2[m - NE1];
+    store_item(0, NE1);
+    if (!PIPE && NE > NE1) {
+      load_item(item, NE1, NE);
+      store_item(NE1, NE);
     }
     __syncthreads();
-    // the fragments of tap t + 1 load while tap t's MFMAs run (for one output tile, taps
-    // in pairs with two register sets and no copies between them)
+    if (PIPE && item + 1 < nitem) load_item(item + 1, 0, NE);
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) av[mb] = F::load(halo + hbase[mb] + (((-1) * HJ + (-1)) * HK + (-1)) * PITCH);
     auto fetch = [&](int tn, FT* ax, FT* bx) {
@@ -309,6 +328,7 @@ k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, co
           if (j < nb) acc[mb][j] = F::mma(ac[mb], bc[j], acc[mb][j]);
     };
     if constexpr (NB == 1) {
+      // taps in pairs with two register sets and no copies between them
 #pragma unroll 1
       for (int t = 0; t < 26; t += 2) {
         fetch(t + 1, an, bn);
@@ -329,28 +349,32 @@ k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, co
         for (int mb = 0; mb < 4; ++mb) av[mb] = an[mb];
       }
     }
-  }
+    if (item % nchunk != nchunk - 1) continue;
+    // epilogue of the brick
+    const Brick o = brick(item / nchunk);
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+    for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      if (j >= nb) continue;
-      const int co = co0 + j * 16 + r;
-      const float bvv = bias ? bias[co] : 0.0f;
-      // the 4 rows of a lane are consecutive positions along z
-      const int tp = wave * 64 + mb * 16 + kq * 4;
-      const int tk = tp % TK, tj = (tp / TK) % TJ, ti = tp / (TK * TJ);
-      const int64_t o0 = (sbase + ((int64_t)(i0 + ti) * D + (j0 + tj)) * D + (k0 + tk)) * cout + co;
+      for (int j = 0; j < NB; ++j) {
+        if (j >= nb) continue;
+        const int co = co0 + j * 16 + r;
+        const float bvv = bias ? bias[co] : 0.0f;
+        // the 4 rows of a lane are consecutive positions along z
+        const int tp = wave * 64 + mb * 16 + kq * 4;
+        const int tk = tp % TK, tj = (tp / TK) % TJ, ti = tp / (TK * TJ);
+        const int64_t o0 = (o.sbase + ((int64_t)(o.i0 + ti) * D + (o.j0 + tj)) * D + (o.k0 + tk)) * cout + co;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t o = o0 + (int64_t)i * cout;
-        float v = acc[mb][j][i] + bvv;
-        if (pre) pre[o] = f2bf(v);
-        if (gate) v *= silu_d(bf2f(gate[o]));
-        else if (act) v = silu(v);
-        y[o] = f2bf(v);
+        for (int i = 0; i < 4; ++i) {
+          const int64_t oi = o0 + (int64_t)i * cout;
+          float vv = acc[mb][j][i] + bvv;
+          if (pre) pre[oi] = f2bf(vv);
+          if (gate) vv *= silu_d(bf2f(gate[oi]));
+          else if (act) vv = silu(vv);
+          y[oi] = f2bf(vv);
+        }
+        acc[mb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
-    }
+  }
 }
 
 // Split-K weight gradient: block (chunk of positions, group of 4 taps, 64x64 tile of
@@ -1003,8 +1027,16 @@ hipError_t launch_conv(int ks, int64_t P, int D, int cin, int cout, const uint16
     const int TK = D < 16 ? D : 16, TJ = 4, TI = 256 / (TJ * TK);
     const size_t lds = (size_t)(TI + 2) * (TJ + 2) * (TK + 2) * ((k32 ? 32 : 16) + 8) * sizeof(uint16_t);
     const int nbt = cout <= 16 ? 1 : cout <= 32 ? 2 : 4;  // 16-channel output blocks per wave
-    dim3 tg((unsigned)(P / 256), (unsigned)((cout + 16 * nbt - 1) / (16 * nbt)));
-#define CT(A, B, C) hipLaunchKernelGGL((k_conv3_tiled<A, B, C>), tg, dim3(256), lds, st, x, w, bias, D, cin, cout, act, gate, y, pre)
+    // about three resident blocks per CU walk the bricks (a multiple of 8 blocks so the
+    // XCD dealing applies)
+    const int64_t nbrick = P / 256;
+    const int64_t gy = (cout + 16 * nbt - 1) / (16 * nbt);
+    int64_t gx = (kConvBlocks + gy - 1) / gy;
+    gx = (gx + 7) / 8 * 8;
+    // (measured: 16-channel inputs and four-tile outputs run faster one brick per block)
+    if (gx > nbrick || !k32 || nbt == 4) gx = nbrick;
+    dim3 tg((unsigned)gx, (unsigned)gy);
+#define CT(A, B, C) hipLaunchKernelGGL((k_conv3_tiled<A, B, C>), tg, dim3(256), lds, st, x, w, bias, D, cin, cout, act, gate, y, pre, (int)nbrick)
 #define CTN(A, B)     \
   do {                \
     if (nbt == 1) CT(A, B, 1); \
