@@ -196,6 +196,21 @@ bool pick_lines(int prec, int n, bool nstep, int* m_out, int* sw_out) {
 
 // z mapping: seg threads per line (power of two <= 64), m points per thread (an instance
 // size), seg*m >= nz, block LDS (4 wavefronts x 64/seg lines x nz values + 512 B) <= 64 KiB.
+// z sweep grid: the blocks that fit on the device at once (LDS bound: each block holds
+// 4 L lines of nz points), each walking an equal share of the line groups; a second,
+// partial round of blocks would leave most CUs idle at the tail
+int z_grid(const gp_ctx* c, int segz, int64_t zgroups) {
+  int cus = 0, lds_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1) cus = 256;
+  if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) != hipSuccess ||
+      lds_cu < 65536)
+    lds_cu = 65536;
+  const int64_t lds = (int64_t)4 * (64 / segz) * c->p.nz * (int64_t)c->esize;
+  int64_t per_cu = lds_cu / std::max<int64_t>(lds, 1);
+  per_cu = std::max<int64_t>(1, std::min<int64_t>(per_cu, 8));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(zgroups, per_cu * cus));
+}
+
 bool valid_z(int nz, int seg, int m, size_t esize) {
   if (seg < 2 || seg > 64 || (seg & (seg - 1)) != 0) return false;
   if (!gpk::sweep_z_supported(0, m)) return false;
@@ -549,7 +564,7 @@ int init_body(gp_ctx* c) {
   if ((rc = build_tables(c))) return rc;
   const int64_t zlines = (int64_t)p.nx * p.ny;
   const int64_t zgroups = (zlines + 4 * (64 / c->map.segz) - 1) / (4 * (64 / c->map.segz));
-  c->zgrid = (int)std::min<int64_t>(zgroups, 2048);
+  c->zgrid = z_grid(c, c->map.segz, zgroups);
   const int64_t oblocks = (c->npts + 255) / 256;
   c->ogrid = (int)std::min<int64_t>(oblocks, 2048);
   if ((rc = dalloc(c, &c->zpart, (size_t)c->zgrid * sizeof(double)))) return rc;
@@ -802,7 +817,7 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
   c->map = nm;
   const int64_t zlines = (int64_t)c->p.nx * c->p.ny;
   const int64_t zgroups = (zlines + 4 * (64 / nm.segz) - 1) / (4 * (64 / nm.segz));
-  const int zgrid = (int)std::min<int64_t>(zgroups, 2048);
+  const int zgrid = z_grid(c, nm.segz, zgroups);
   if (zgrid > c->zgrid) {
     double* np = nullptr;
     int rc = dalloc(c, &np, (size_t)zgrid * sizeof(double));
