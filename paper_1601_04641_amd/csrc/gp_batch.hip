@@ -46,6 +46,8 @@ struct BWork {
 };
 
 constexpr int kChunk = 1024;  // points per block of the pointwise batched kernels
+constexpr int kMF = 8;        // points per lane of the fused y+z kernel's in-LDS line solves
+constexpr int kYZThreads = 256;  // threads of a fused y+z block (one plane in LDS; 1024 measured slower)
 
 template <typename R> __device__ __forceinline__ typename VecOf<R>::T dval(const double* c) {
   typename VecOf<R>::T v;
@@ -110,93 +112,117 @@ kb_sweep_z(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__
 }
 
 // Crank-Nicolson solves of nl lines held in LDS (line l, element i at L0 + l * lstride +
-// i * stride, n points), S segments per line, thread t -> line t % nl, segment t / nl
-// (threads past nl * S only join the barriers).  The same elimination as the register
-// sweeps: each segment runs the constant-pivot recurrences from a zero start, the
-// segments' affine maps are composed through small shared arrays, and running powers of
-// a fix up the segment values; the Sherman-Morrison head correction u_i += omega_i u_0
-// (i < nw) comes last.  Boundary neighbours are read before any value is overwritten.
-// Every thread of the block must call this (it contains barriers).
-template <typename R, bool CC>
-__device__ __forceinline__ void lds_lines_solve(typename VecOf<R>::T* L0, int lstride, int stride, int n, int nl,
-                                                int S, const Coef<typename VecOf<R>::T>& cf,
-                                                const typename VecOf<R>::T* __restrict__ omega, int nw,
-                                                typename VecOf<R>::T* sB, typename VecOf<R>::T* sU,
-                                                typename VecOf<R>::T* sPw) {
+// i * stride, n points) in registers, as the register sweeps do it: a wavefront takes
+// 64 / nseg lines at a time, lane = line * nseg + segment, MZ consecutive points per lane
+// (nseg = the smallest power of two with nseg * MZ >= n).  Each segment runs the
+// constant-pivot recurrences from a zero start; the segments of a line are joined by
+// shuffle scans of the affine maps (every segment before an active one is full, so spans
+// multiply by powers of P = a^MZ and only the offsets travel); the Sherman-Morrison head
+// correction u_i += omega_i u_0 (i < nw) comes last.  A lane reads its points and both
+// neighbours before any lane of its wavefront writes, and no two wavefronts share a line,
+// so no barrier is needed inside; the caller separates passes with barriers.
+template <typename R, int MZ, bool CC>
+__device__ __forceinline__ void lds_lines_regs(typename VecOf<R>::T* L0, int lstride, int stride, int n, int nl,
+                                               const Coef<typename VecOf<R>::T>& cf,
+                                               const typename VecOf<R>::T* __restrict__ omega, int nw) {
   typedef typename VecOf<R>::T V;
-  const int t = threadIdx.x;
-  const bool act = t < nl * S;
-  const int line = act ? t % nl : 0, q = act ? t / nl : 0;
-  const int m = (n + S - 1) / S;
-  const int start = min(n, q * m), end = min(n, start + m);
-  V* L = L0 + (int64_t)line * lstride;
-  V pl = vzero<V>(), pr = vzero<V>();
-  if (act) {
-    if (start > 0 && start < n) pl = L[(start - 1) * stride];
-    if (end < n) pr = L[end * stride];
-  }
-  __syncthreads();
-  // forward recurrence from d_{start-1} = 0; B = d at the segment end, Pw = a^len
-  if (act) {
-    V prev = pl, d = vzero<V>(), pw = vone<V>();
-    V cur = start < end ? L[start * stride] : vzero<V>();
-    for (int i = start; i < end; ++i) {
-      const V nxt = (i + 1 < end) ? L[(i + 1) * stride] : pr;
-      d = fwd_point<CC, R, V>(cf, prev, nxt, d, cur);
-      L[i * stride] = d;
-      pw = cmul<CC>(cf.a, pw);
-      prev = cur;
-      cur = nxt;
+  int nseg = 1;
+  while (nseg * MZ < n) nseg *= 2;
+  const int LW = 64 / nseg;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, nwave = (int)(blockDim.x >> 6);
+  const int l = lane / nseg, p = lane % nseg;
+  const int s = p * MZ;
+  const int len = max(0, min(MZ, n - s));
+  V cP = cf.a;  // a^MZ
+#pragma unroll
+  for (int k = 1; k < MZ; ++k) cP = cmul<CC>(cf.a, cP);
+  for (int l0 = 0; l0 < nl; l0 += nwave * LW) {
+    const int line = l0 + w * LW + l;
+    const bool act = line < nl && len > 0;
+    V* row = L0 + (int64_t)(act ? line : 0) * lstride;
+    V v[MZ];
+#pragma unroll
+    for (int t = 0; t < MZ; ++t) {
+      v[t] = vzero<V>();
+      if (act && t < len) v[t] = row[(s + t) * stride];
     }
-    sB[t] = d;
-    sPw[t] = pw;
-  }
-  __syncthreads();
-  // true d_{start-1}: compose the earlier segments' maps D -> a^m D + B_r; add a^(k+1) D
-  if (act && q > 0) {
-    V D = vzero<V>();
-    for (int r = 0; r < q; ++r) D = cfma<CC>(sPw[r * nl + line], D, sB[r * nl + line]);
-    V rr = D;
-    for (int i = start; i < end; ++i) {
-      rr = cmul<CC>(cf.a, rr);
-      L[i * stride] = vadd(L[i * stride], rr);
+    const V left = (act && s > 0) ? row[(s - 1) * stride] : vzero<V>();
+    const V right = (act && s + len < n) ? row[(s + len) * stride] : vzero<V>();
+    V d = vzero<V>();
+    {
+      V prev = left;
+#pragma unroll
+      for (int t = 0; t < MZ; ++t) {
+        V nxt = right;
+        if (t + 1 < MZ) nxt = v[t + 1];
+        // past len: zeros in, values never stored (the backward pass restarts from zero
+        // there and no later segment of the line is active)
+        const V dn = fwd_point<CC, R, V>(cf, prev, nxt, d, v[t]);
+        prev = v[t];
+        v[t] = dn;
+        d = dn;
+      }
     }
-  }
-  __syncthreads();
-  // backward recurrence from u_end = 0; U = u at the segment start
-  if (act) {
+    V B = act ? d : vzero<V>();
+    {
+      V Apow = cP;
+      for (int off = 1; off < nseg; off <<= 1) {
+        const V Bp = shfl_up_v(B, off, nseg);
+        if (p >= off) B = cfma<CC>(Apow, Bp, B);
+        Apow = cmul<CC>(Apow, Apow);
+      }
+    }
+    V D = shfl_up_v(B, 1, nseg);
+    if (p == 0) D = vzero<V>();
+    {
+      V r = D;
+#pragma unroll
+      for (int t = 0; t < MZ; ++t) {
+        r = cmul<CC>(cf.a, r);
+        v[t] = vadd(v[t], r);
+      }
+    }
     V u = vzero<V>();
-    for (int i = end - 1; i >= start; --i) {
-      u = cfma<CC>(cf.a, u, L[i * stride]);
-      L[i * stride] = u;
+#pragma unroll
+    for (int t = MZ - 1; t >= 0; --t) {
+      u = cfma<CC>(cf.a, u, v[t]);
+      if (t >= len) u = vzero<V>();
+      v[t] = u;
     }
-    sU[t] = u;
-  }
-  __syncthreads();
-  // true u_end: compose the later segments' maps U -> u0_start + a^len U; add a^(end-i) U
-  if (act && q < S - 1) {
-    V U = vzero<V>();
-    for (int r = S - 1; r > q; --r) U = cfma<CC>(sPw[r * nl + line], U, sU[r * nl + line]);
-    V rr = U;
-    for (int i = end - 1; i >= start; --i) {
-      rr = cmul<CC>(cf.a, rr);
-      L[i * stride] = vadd(L[i * stride], rr);
+    V Bu = act ? u : vzero<V>();
+    {
+      V Apow = cP;
+      for (int off = 1; off < nseg; off <<= 1) {
+        const V Bp = shfl_down_v(Bu, off, nseg);
+        if (p + off < nseg) Bu = cfma<CC>(Apow, Bp, Bu);
+        Apow = cmul<CC>(Apow, Apow);
+      }
+    }
+    V U = shfl_down_v(Bu, 1, nseg);
+    if (p == nseg - 1) U = vzero<V>();
+    {
+      V r = U;
+#pragma unroll
+      for (int t = MZ - 1; t >= 0; --t) {
+        r = cmul<CC>(cf.a, r);
+        v[t] = vadd(v[t], r);
+      }
+    }
+    if (nw > 0) {
+      const V u0 = vmake<V>(__shfl(v[0].x, l * nseg, 64), __shfl(v[0].y, l * nseg, 64));
+#pragma unroll
+      for (int t = 0; t < MZ; ++t) {
+        const int pos = s + t;
+        const V c = cfma<CC>(omega[min(pos, nw - 1)], u0, v[t]);
+        if (pos < nw) v[t] = c;
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int t = 0; t < MZ; ++t)
+        if (t < len) row[(s + t) * stride] = v[t];
     }
   }
-  __syncthreads();
-  if (act && q == 0 && nw > 0) {
-    const V u0 = L[0];
-    for (int i = 0; i < nw; ++i) L[i * stride] = cfma<CC>(omega[i], u0, L[i * stride]);
-  }
-  __syncthreads();
-}
-
-// segments per line for nl lines of n points on 256 threads: a power of two with
-// nl * S <= 256 and at least 4 points per segment
-__device__ __forceinline__ int lds_segments(int nl, int n) {
-  int S = 1;
-  while (nl * S * 2 <= 256 && (n + 2 * S - 1) / (2 * S) >= 4) S *= 2;
-  return S;
 }
 
 // Fused y and z sweeps of one x-plane of one instance (the plane [y][z] is contiguous in
@@ -205,13 +231,12 @@ __device__ __forceinline__ int lds_segments(int nl, int n) {
 // (imaginary time) the FP64 sum |psi|^2 of the plane.  psi crosses HBM twice per step for
 // y and z together instead of four times.
 template <typename R, bool CC, bool NORM>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kYZThreads)
 kb_sweep_yz(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst, const BWork* __restrict__ work,
             const typename VecOf<R>::T* __restrict__ omega_all, double* __restrict__ partials) {
   typedef typename VecOf<R>::T V;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[4];
-  __shared__ V sB[256], sU[256], sPw[256];
+  __shared__ double red[kYZThreads / 64];
   V* plane = reinterpret_cast<V*>(smem_raw);
   const BWork wk = work[blockIdx.x];
   const BInst& I = inst[wk.inst];
@@ -230,14 +255,14 @@ kb_sweep_yz(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict_
   if (vec) {
     const int nu = np / E;
     const uint4* g4 = reinterpret_cast<const uint4*>(g);
-    for (int base = threadIdx.x; base < nu; base += 256 * 8) {
+    for (int base = threadIdx.x; base < nu; base += kYZThreads * 8) {
       uint4 r[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k)
-        if (base + k * 256 < nu) r[k] = g4[base + k * 256];
+        if (base + k * kYZThreads < nu) r[k] = g4[base + k * kYZThreads];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const int u = base + k * 256;
+        const int u = base + k * kYZThreads;
         if (u < nu) {
           const int q = u * E;
           const V* e = reinterpret_cast<const V*>(&r[k]);
@@ -248,26 +273,26 @@ kb_sweep_yz(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict_
       }
     }
   } else {
-    for (int q = threadIdx.x; q < np; q += 256) plane[(q / nz) * pitch + q % nz] = g[q];
+    for (int q = threadIdx.x; q < np; q += kYZThreads) plane[(q / nz) * pitch + q % nz] = g[q];
   }
   __syncthreads();
   {
     const double* c = I.coef[mode][1];
     const Coef<V> cf{dval<R>(c), dval<R>(c + 2), dval<R>(c + 4)};
-    lds_lines_solve<R, CC>(plane, 1, pitch, ny, nz, lds_segments(nz, ny), cf, omega_all + I.omega_off[mode][1],
-                           I.nw[mode][1], sB, sU, sPw);
+    lds_lines_regs<R, kMF, CC>(plane, 1, pitch, ny, nz, cf, omega_all + I.omega_off[mode][1], I.nw[mode][1]);
   }
+  __syncthreads();
   {
     const double* c = I.coef[mode][2];
     const Coef<V> cf{dval<R>(c), dval<R>(c + 2), dval<R>(c + 4)};
-    lds_lines_solve<R, CC>(plane, pitch, 1, nz, ny, lds_segments(ny, nz), cf, omega_all + I.omega_off[mode][2],
-                           I.nw[mode][2], sB, sU, sPw);
+    lds_lines_regs<R, kMF, CC>(plane, pitch, 1, nz, ny, cf, omega_all + I.omega_off[mode][2], I.nw[mode][2]);
   }
+  __syncthreads();
   double acc = 0.0;
   if (vec) {
     const int nu = np / E;
     uint4* g4 = reinterpret_cast<uint4*>(g);
-    for (int u = threadIdx.x; u < nu; u += 256) {
+    for (int u = threadIdx.x; u < nu; u += kYZThreads) {
       const int q = u * E;
       uint4 w;
       V* e = reinterpret_cast<V*>(&w);
@@ -280,15 +305,22 @@ kb_sweep_yz(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict_
       g4[u] = w;
     }
   } else {
-    for (int q = threadIdx.x; q < np; q += 256) {
+    for (int q = threadIdx.x; q < np; q += kYZThreads) {
       const V u = plane[(q / nz) * pitch + q % nz];
       g[q] = u;
       if (NORM) acc += (double)u.x * (double)u.x + (double)u.y * (double)u.y;
     }
   }
   if (NORM) {
-    const double t = block_sum_256(acc, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    // fixed-order sum over the block's wavefronts
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int k = 0; k < kYZThreads / 64; ++k) t += red[k];
+      partials[blockIdx.x] = t;
+    }
   }
 }
 
@@ -965,7 +997,7 @@ int benqueue_step(gp_batch* b, int mode, hipStream_t s) {
   if (b->nbyz > 0) {  // fused y+z sweeps (timed with the z sweeps)
     rc = btimed(b, s, 2, [&](hipStream_t t) {
       double* part = b->zpart + b->nbz;
-      const dim3 grid(b->nbyz), blk(256);
+      const dim3 grid(b->nbyz), blk(gpk::kYZThreads);
       if (b->prec == GP_C64) {
         if (cc)
           hipLaunchKernelGGL((gpk::kb_sweep_yz<float, true, false>), grid, blk, b->ldsyz, t, (float2*)b->psi, b->dinst,
