@@ -646,6 +646,14 @@ struct gp_batch {
   int nfused = 0;           // instances on the fused path
   size_t max_lds = 65536;   // dynamic LDS per block available to the fused kernel
   size_t ldsyz = 0;
+  // fused y+z launches, one per plane-size class: blocks [start, start + count) of wyz,
+  // dynamic LDS of the class's largest plane
+  struct YZClass {
+    int start, count;
+    size_t lds;
+  };
+  std::vector<YZClass> yzcls;
+  int lds_cu = 65536;  // LDS per CU
   int thrx = 64, thry = 64;
   bool need_hc[2][2] = {{false, false}, {false, false}};  // [mode][axis]: nw > m somewhere
   size_t ldsx = 0, ldsy = 0, ldsz = 0;
@@ -750,6 +758,7 @@ int configure(gp_batch* b) {
   std::vector<BInst> hi(b->n);
   std::vector<BWork> wx, wy, wz, wo, wyz;
   std::vector<int> yzb0(b->n, 0), yzb1(b->n, 0);
+  std::vector<size_t> lyzv(b->n, 0);
   std::vector<unsigned char> omega;
   size_t ldsyz = 0;
   int nfused = 0;
@@ -821,9 +830,7 @@ int configure(gp_batch* b) {
     const int bo = cdiv((int64_t)p.nx * p.ny * p.nz, gpk::kChunk);
     for (int k = 0; k < bx; ++k) wx.push_back({i, k});
     if (fuse) {
-      yzb0[i] = (int)wyz.size();
-      for (int k = 0; k < p.nx; ++k) wyz.push_back({i, k});  // one block per x-plane
-      yzb1[i] = (int)wyz.size();
+      lyzv[i] = lyz;  // blocks added below, grouped by plane-size class
       I.zb0 = I.zb1 = -1;  // set below: fused partials follow the z-sweep partials
     } else {
       for (int k = 0; k < by; ++k) wy.push_back({i, k});
@@ -834,6 +841,29 @@ int configure(gp_batch* b) {
     I.ob0 = (int)wo.size();
     for (int k = 0; k < bo; ++k) wo.push_back({i, k});
     I.ob1 = (int)wo.size();
+  }
+  // fused instances grouped by how many of their blocks fit on a CU (LDS bound), so that
+  // small planes are not launched with the LDS of the largest one; one block per x-plane
+  struct YZClassH {
+    int start, count;
+    size_t lds;
+    int bpc;
+  };
+  std::vector<YZClassH> cls;
+  {
+    std::vector<int> order;
+    for (int i = 0; i < b->n; ++i)
+      if (lyzv[i] > 0) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return lyzv[u] < lyzv[v]; });
+    auto bpc = [&](size_t l) { return (int)std::min<size_t>(8, (size_t)b->lds_cu / l); };
+    for (int i : order) {
+      if (cls.empty() || bpc(lyzv[i]) != cls.back().bpc) cls.push_back({(int)wyz.size(), 0, 0, bpc(lyzv[i])});
+      yzb0[i] = (int)wyz.size();
+      for (int k = 0; k < b->p[i].nx; ++k) wyz.push_back({i, k});
+      yzb1[i] = (int)wyz.size();
+      cls.back().count = (int)wyz.size() - cls.back().start;
+      cls.back().lds = std::max(cls.back().lds, lyzv[i]);
+    }
   }
   for (int i = 0; i < b->n; ++i)
     if (hi[i].zb0 < 0) {
@@ -901,6 +931,8 @@ int configure(gp_batch* b) {
   b->nbo = (int)wo.size();
   b->nbyz = (int)wyz.size();
   b->ldsyz = ldsyz;
+  b->yzcls.clear();
+  for (const YZClassH& c : cls) b->yzcls.push_back({c.start, c.count, c.lds});
   b->nfused = nfused;
   b->thrx = wavesx * 64;
   b->thry = wavesy * 64;
@@ -994,24 +1026,27 @@ int benqueue_step(gp_batch* b, int mode, hipStream_t s) {
     rc = btimed(b, s, 2, [&](hipStream_t t) { return gpk::launch_b_z(b->prec, cc, az, t); });
     if (rc) return rc;
   }
-  if (b->nbyz > 0) {  // fused y+z sweeps (timed with the z sweeps)
+  if (b->nbyz > 0) {  // fused y+z sweeps (timed with the z sweeps), one launch per plane-size class
     rc = btimed(b, s, 2, [&](hipStream_t t) {
-      double* part = b->zpart + b->nbz;
-      const dim3 grid(b->nbyz), blk(gpk::kYZThreads);
-      if (b->prec == GP_C64) {
-        if (cc)
-          hipLaunchKernelGGL((gpk::kb_sweep_yz<float, true, false>), grid, blk, b->ldsyz, t, (float2*)b->psi, b->dinst,
-                             b->wyz, (const float2*)b->omega, part);
-        else
-          hipLaunchKernelGGL((gpk::kb_sweep_yz<float, false, true>), grid, blk, b->ldsyz, t, (float2*)b->psi, b->dinst,
-                             b->wyz, (const float2*)b->omega, part);
-      } else {
-        if (cc)
-          hipLaunchKernelGGL((gpk::kb_sweep_yz<double, true, false>), grid, blk, b->ldsyz, t, (double2*)b->psi,
-                             b->dinst, b->wyz, (const double2*)b->omega, part);
-        else
-          hipLaunchKernelGGL((gpk::kb_sweep_yz<double, false, true>), grid, blk, b->ldsyz, t, (double2*)b->psi,
-                             b->dinst, b->wyz, (const double2*)b->omega, part);
+      for (const auto& c : b->yzcls) {
+        double* part = b->zpart + b->nbz + c.start;
+        const gpk::BWork* wk = b->wyz + c.start;
+        const dim3 grid(c.count), blk(gpk::kYZThreads);
+        if (b->prec == GP_C64) {
+          if (cc)
+            hipLaunchKernelGGL((gpk::kb_sweep_yz<float, true, false>), grid, blk, c.lds, t, (float2*)b->psi, b->dinst,
+                               wk, (const float2*)b->omega, part);
+          else
+            hipLaunchKernelGGL((gpk::kb_sweep_yz<float, false, true>), grid, blk, c.lds, t, (float2*)b->psi,
+                               b->dinst, wk, (const float2*)b->omega, part);
+        } else {
+          if (cc)
+            hipLaunchKernelGGL((gpk::kb_sweep_yz<double, true, false>), grid, blk, c.lds, t, (double2*)b->psi,
+                               b->dinst, wk, (const double2*)b->omega, part);
+          else
+            hipLaunchKernelGGL((gpk::kb_sweep_yz<double, false, true>), grid, blk, c.lds, t, (double2*)b->psi,
+                               b->dinst, wk, (const double2*)b->omega, part);
+        }
       }
       return hipGetLastError();
     });
@@ -1160,7 +1195,13 @@ int gp_batch_init(const gp_params* p, int32_t n, void* psi_dev, const int64_t* o
   if (rc == GP_OK) {
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) == hipSuccess && lds > 0)
-      b->max_lds = (size_t)lds - 3 * 256 * 16 - 512;  // the fused kernel's static shared arrays
+      b->max_lds = (size_t)lds - 512;  // the fused kernel's static shared array
+    else
+      (void)hipGetLastError();
+    int ldc = 0;
+    if (hipDeviceGetAttribute(&ldc, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, b->device) == hipSuccess &&
+        ldc >= 65536)
+      b->lds_cu = ldc;
     else
       (void)hipGetLastError();
   }
