@@ -200,8 +200,10 @@ k_dense_finish(const float* __restrict__ part, int S, int P, int cout, const flo
 // tiles the next item's halo loads are in flight while the current item's MFMAs run, and
 // always the next tap's weight and halo fragments while the current tap's do.  Bricks are dealt so that the blocks on
 // one XCD (workgroups go round-robin to the 8 XCDs) work on one contiguous stretch of the
-// grid at a time, sharing halos through that XCD's L2.  Epilogue as k_conv.
-template <int KC, int TK, int NB>
+// grid at a time, sharing halos through that XCD's L2.  UP: the input is given on the 2x
+// coarser grid (D/2)^3 and read as its nearest-neighbour upsampling, so the upsampled
+// tensor is never stored.  Epilogue as k_conv.
+template <int KC, int TK, int NB, bool UP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB <= 2 ? 3 : 1)))
 k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const float* __restrict__ bias, int D,
               int cin, int cout, int act, const uint16_t* __restrict__ gate, uint16_t* __restrict__ y,
@@ -245,8 +247,10 @@ k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, co
   }
   struct Brick {
     int i0, j0, k0;
-    int64_t sbase;
+    int64_t sbase;  // first output position of the sample
+    int64_t xbase;  // first input position of the sample (UP: on the coarse grid)
   };
+  const int Dc = D >> 1;
   auto brick = [&](int it) {
     Brick o;
     int q = first + it * stride;
@@ -256,13 +260,14 @@ k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, co
     q /= tjn;
     o.i0 = (q % tin) * TI;
     o.sbase = (int64_t)(q / tin) * D * D * D;
+    o.xbase = UP ? (int64_t)(q / tin) * Dc * Dc * Dc : o.sbase;
     return o;
   };
   uint4 v[NE];
   auto load_item = [&](int item, int m0, int m1) {
     const Brick o = brick(item / nchunk);
     const int ci0 = (item % nchunk) * KC;
-    const uint16_t* xs = x + o.sbase * cin + ci0;
+    const uint16_t* xs = x + o.xbase * cin + ci0;
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
       if (m < m0 || m >= m1) continue;
@@ -272,8 +277,11 @@ k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, co
         const int hp = e / U, u = e % U;
         const int hk = hp % HK, hj = (hp / HK) % HJ, hi = hp / (HK * HJ);
         const int gi = o.i0 - 1 + hi, gj = o.j0 - 1 + hj, gk = o.k0 - 1 + hk;
-        if ((unsigned)gi < (unsigned)D && (unsigned)gj < (unsigned)D && (unsigned)gk < (unsigned)D)
-          v[m] = *reinterpret_cast<const uint4*>(xs + (int64_t)((gi * D + gj) * D + gk) * cin + u * 8);
+        if ((unsigned)gi < (unsigned)D && (unsigned)gj < (unsigned)D && (unsigned)gk < (unsigned)D) {
+          // UP: the input is the 2x coarser grid, read as its nearest-neighbour upsampling
+          const int idx = UP ? ((gi >> 1) * Dc + (gj >> 1)) * Dc + (gk >> 1) : (gi * D + gj) * D + gk;
+          v[m] = *reinterpret_cast<const uint4*>(xs + (int64_t)idx * cin + u * 8);
+        }
       }
     }
   };
@@ -528,7 +536,7 @@ k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, int64_t
 // are shared by all of a wave's units.  Partial sums over the block's bricks go to
 // part[chunk][tap][cout][cin]; blocks of the first tap group and input tile also sum the
 // staged dy rows into dbpart[chunk][cout] (nullable).
-template <int MCO, int MCI, int NU>
+template <int MCO, int MCI, int NU, bool UP>
 __global__ void __launch_bounds__(256)
 k_wgrad3_tiled(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, int D, int lg, int cin, int cout,
                int nab, int ntiles, int tpb, float* __restrict__ part, float* __restrict__ dbpart) {
@@ -592,7 +600,8 @@ k_wgrad3_tiled(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, 
   // next brick's loads are in flight while the current one is computed.
   struct Org {
     int i0, j0, k0;
-    int64_t sbase;
+    int64_t sbase;  // first position of the sample (UP: xbase on the coarse grid)
+    int64_t xbase;
   };
   auto origin = [&](int tb) {
     Org o;
@@ -603,6 +612,7 @@ k_wgrad3_tiled(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, 
     q /= tjn;
     o.i0 = (q % tin) * TI;
     o.sbase = (int64_t)(q / tin) << (3 * lg);
+    o.xbase = UP ? (int64_t)(q / tin) << (3 * (lg - 1)) : o.sbase;
     return o;
   };
   // dy: 128 position pairs x (16 MCO / 8) channel groups
@@ -634,10 +644,19 @@ k_wgrad3_tiled(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x, 
     const int gi = o.i0 + (xg[m] & 255) - 1, gj = o.j0 + ((xg[m] >> 8) & 255) - 1;
     const int gk = o.k0 + ((xg[m] >> 16) & 255) - 1, cg = xg[m] >> 24;
     if ((unsigned)gi < (unsigned)D && (unsigned)gj < (unsigned)D) {
-      const int64_t g = o.sbase + ((int64_t)gi << (2 * lg)) + (gj << lg) + gk;
-      const uint16_t* src = x + g * cin + ci0 + cg * 8;
-      if ((unsigned)gk < (unsigned)D) v0 = *reinterpret_cast<const uint4*>(src);
-      if ((unsigned)(gk + 1) < (unsigned)D) v1 = *reinterpret_cast<const uint4*>(src + cin);
+      if (UP) {  // x on the 2x coarser grid, read as its nearest-neighbour upsampling
+        const int lc = lg - 1;
+        const int64_t g = o.xbase + ((int64_t)(gi >> 1) << (2 * lc)) + ((gj >> 1) << lc);
+        const uint16_t* src = x + g * cin + ci0 + cg * 8;
+        if ((unsigned)gk < (unsigned)D) v0 = *reinterpret_cast<const uint4*>(src + (int64_t)(gk >> 1) * cin);
+        if ((unsigned)(gk + 1) < (unsigned)D)
+          v1 = *reinterpret_cast<const uint4*>(src + (int64_t)((gk + 1) >> 1) * cin);
+      } else {
+        const int64_t g = o.sbase + ((int64_t)gi << (2 * lg)) + (gj << lg) + gk;
+        const uint16_t* src = x + g * cin + ci0 + cg * 8;
+        if ((unsigned)gk < (unsigned)D) v0 = *reinterpret_cast<const uint4*>(src);
+        if ((unsigned)(gk + 1) < (unsigned)D) v1 = *reinterpret_cast<const uint4*>(src + cin);
+      }
     }
   };
   auto store_x = [&](int m, const uint4& v0, const uint4& v1) {
@@ -1007,9 +1026,16 @@ int64_t dense_ws_floats(int64_t P, int cin, int cout) {
 
 // ws (nullable): FP32 workspace of ws_floats; with room for dense_ws_floats, one-tap
 // layers over at most 64 positions take the split path
+// tiled 3x3x3 path: D a power of two >= 8 and P a whole number of D^3 samples
+bool conv_tiled(int64_t P, int D) {
+  return D >= 8 && (D & (D - 1)) == 0 && P % ((int64_t)D * D * D) == 0;
+}
+
+// up: x is given on the 2x coarser grid and upsampled on the fly (tiled path only)
 hipError_t launch_conv(int ks, int64_t P, int D, int cin, int cout, const uint16_t* x, const uint16_t* w,
                        const float* bias, int act, const uint16_t* gate, uint16_t* y, uint16_t* pre,
-                       hipStream_t st, float* ws = nullptr, int64_t ws_floats = 0) {
+                       hipStream_t st, float* ws = nullptr, int64_t ws_floats = 0, bool up = false) {
+  if (up && !(ks == 3 && conv_tiled(P, D))) return hipErrorInvalidValue;
   if (ks == 1 && P <= 64 && cin % 32 == 0 && ws && dense_ws_floats(P, cin, cout) <= ws_floats) {
     const int kslice = dense_kslice(cin);
     const int S = (cin + kslice - 1) / kslice;
@@ -1021,9 +1047,7 @@ hipError_t launch_conv(int ks, int64_t P, int D, int cin, int cout, const uint16
   }
   dim3 grid((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64));
   const bool k32 = cin % 32 == 0;
-  // tiled path: D a power of two >= 8 and P a whole number of D^3 samples
-  const bool pow2 = D >= 8 && (D & (D - 1)) == 0 && P % ((int64_t)D * D * D) == 0;
-  if (ks == 3 && pow2) {
+  if (ks == 3 && conv_tiled(P, D)) {
     const int TK = D < 16 ? D : 16, TJ = 4, TI = 256 / (TJ * TK);
     const size_t lds = (size_t)(TI + 2) * (TJ + 2) * (TK + 2) * ((k32 ? 32 : 16) + 8) * sizeof(uint16_t);
     const int nbt = cout <= 16 ? 1 : cout <= 32 ? 2 : 4;  // 16-channel output blocks per wave
@@ -1036,7 +1060,15 @@ hipError_t launch_conv(int ks, int64_t P, int D, int cin, int cout, const uint16
     // (measured: 16-channel inputs and four-tile outputs run faster one brick per block)
     if (gx > nbrick || !k32 || nbt == 4) gx = nbrick;
     dim3 tg((unsigned)gx, (unsigned)gy);
-#define CT(A, B, C) hipLaunchKernelGGL((k_conv3_tiled<A, B, C>), tg, dim3(256), lds, st, x, w, bias, D, cin, cout, act, gate, y, pre, (int)nbrick)
+#define CT(A, B, C)                                                                                         \
+  do {                                                                                                      \
+    if (up)                                                                                                 \
+      hipLaunchKernelGGL((k_conv3_tiled<A, B, C, true>), tg, dim3(256), lds, st, x, w, bias, D, cin, cout, act, \
+                         gate, y, pre, (int)nbrick);                                                        \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_conv3_tiled<A, B, C, false>), tg, dim3(256), lds, st, x, w, bias, D, cin, cout, act, \
+                         gate, y, pre, (int)nbrick);                                                        \
+  } while (0)
 #define CTN(A, B)     \
   do {                \
     if (nbt == 1) CT(A, B, 1); \
@@ -1116,27 +1148,34 @@ int64_t wgrad_part_floats(int ks, int64_t P, int D, int cin, int cout) {
 
 // dw[t][o][i < keep] (row stride keep) and db[o] (nullable) from dy [P][cout], x [P][cin];
 // part holds wgrad_part_floats, cpart wgrad_plan(...).nch * cout floats
+// up: x is given on the 2x coarser grid and upsampled on the fly (tiled path only)
 hipError_t launch_wgrad(int ks, int64_t P, int D, int cin, int cout, int keep, const uint16_t* dy, const uint16_t* x,
-                        float* part, float* dw, float* cpart, float* db, hipStream_t st) {
+                        float* part, float* dw, float* cpart, float* db, hipStream_t st, bool up = false) {
   const int T = ks * ks * ks;
   float* dbp = db ? cpart : nullptr;
   const WgPlan pl = wgrad_plan(ks, P, D, cin, cout);
   const int nch = (int)pl.nch;
+  if (up && !pl.tiled) return hipErrorInvalidValue;
   if (pl.tiled) {
     int lg = 0;
     while ((1 << lg) < D) ++lg;
     dim3 grid((unsigned)nch, (unsigned)pl.groups, (unsigned)pl.zt);
-#define WT(A, B, U)                                                                                             \
-  do {                                                                                                          \
-    static bool attr = false;                                                                                   \
-    if (!attr) {                                                                                                \
-      hipError_t ea = hipFuncSetAttribute((const void*)k_wgrad3_tiled<A, B, U>,                                 \
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);       \
-      if (ea != hipSuccess) return ea;                                                                          \
-      attr = true;                                                                                              \
-    }                                                                                                           \
-    hipLaunchKernelGGL((k_wgrad3_tiled<A, B, U>), grid, dim3(256), pl.lds, st, dy, x, D, lg, cin, cout, pl.nab, \
-                       pl.ntiles, pl.tpb, part, dbp);                                                           \
+#define WT1(A, B, U, UPV)                                                                                      \
+  do {                                                                                                         \
+    static bool attr = false;                                                                                  \
+    if (!attr) {                                                                                               \
+      hipError_t ea = hipFuncSetAttribute((const void*)k_wgrad3_tiled<A, B, U, UPV>,                           \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);      \
+      if (ea != hipSuccess) return ea;                                                                         \
+      attr = true;                                                                                             \
+    }                                                                                                          \
+    hipLaunchKernelGGL((k_wgrad3_tiled<A, B, U, UPV>), grid, dim3(256), pl.lds, st, dy, x, D, lg, cin, cout,   \
+                       pl.nab, pl.ntiles, pl.tpb, part, dbp);                                                  \
+  } while (0)
+#define WT(A, B, U)          \
+  do {                       \
+    if (up) WT1(A, B, U, true); \
+    else WT1(A, B, U, false); \
   } while (0)
     if (pl.mco == 1) {
       if (pl.mci == 2) WT(1, 2, 5);
@@ -1149,6 +1188,7 @@ hipError_t launch_wgrad(int ks, int64_t P, int D, int cin, int cout, int keep, c
       else WT(4, 1, 1);
     }
 #undef WT
+#undef WT1
   } else {
   const int64_t chunk = wgrad_chunk(P);
   dim3 grid((unsigned)nch, (unsigned)((T + 3) / 4), (unsigned)(((cout + 63) / 64) * ((cin + 63) / 64)));
@@ -1301,7 +1341,7 @@ int gpnn_create(const gpnn_arch* a, void* hip_stream, gpnn** out) {
     const int64_t P = (int64_t)B * vol(D);
     A(&m->Cb[s], (int64_t)27 * a->ch[s] * a->ch[s - 1]);
     A(&m->Ct[s], (int64_t)27 * a->ch[s] * a->ch[s - 1]);
-    A(&m->u[s], P * a->ch[s - 1]);
+    if (!conv_tiled(P, D)) A(&m->u[s], P * a->ch[s - 1]);  // tiled layers upsample on the fly
     A(&m->h[s], P * a->ch[s]);
     A(&m->act[s], P * a->ch[s]);
     maxd = std::max(maxd, P * a->ch[s]);
@@ -1386,10 +1426,16 @@ int gpnn_forward(gpnn* m, const float* prm, int32_t n, void* out, int32_t out_co
   const uint16_t* prev = m->a2;
   for (int s = 1; s <= m->S && e == hipSuccess; ++s) {
     const int Dc = a.base << (s - 1), D = a.base << s;
-    const int64_t tot = (int64_t)n * vol(D) * (a.ch[s - 1] / 8);
-    hipLaunchKernelGGL(k_up2, dim3(nblk(tot)), dim3(256), 0, st, prev, n, Dc, a.ch[s - 1], m->u[s]);
-    e = launch_conv(3, (int64_t)n * vol(D), D, a.ch[s - 1], a.ch[s], m->u[s], m->Cb[s], m->w + m->oc[s], 1, nullptr,
-                    m->act[s], m->h[s], st);
+    const int64_t Ps = (int64_t)n * vol(D);
+    if (conv_tiled(Ps, D)) {  // nearest x2 upsampling read on the fly by the convolution
+      e = launch_conv(3, Ps, D, a.ch[s - 1], a.ch[s], prev, m->Cb[s], m->w + m->oc[s], 1, nullptr, m->act[s], m->h[s],
+                      st, nullptr, 0, true);
+    } else {
+      const int64_t tot = Ps * (a.ch[s - 1] / 8);
+      hipLaunchKernelGGL(k_up2, dim3(nblk(tot)), dim3(256), 0, st, prev, n, Dc, a.ch[s - 1], m->u[s]);
+      e = launch_conv(3, Ps, D, a.ch[s - 1], a.ch[s], m->u[s], m->Cb[s], m->w + m->oc[s], 1, nullptr, m->act[s],
+                      m->h[s], st);
+    }
     prev = m->act[s];
   }
   if (e == hipSuccess) {
@@ -1439,8 +1485,10 @@ int gpnn_loss_backward(gpnn* m, const float* tgt, double* loss) {
   for (int s = S; s >= 1 && e == hipSuccess; --s) {
     const int D = a.base << s, Dc = a.base << (s - 1);
     const int64_t Ps = (int64_t)n * vol(D);
-    e = launch_wgrad(3, Ps, D, a.ch[s - 1], a.ch[s], a.ch[s - 1], dh, m->u[s], m->part, m->g + m->oC[s], m->cpart,
-                     m->g + m->oc[s], st);
+    const bool up = conv_tiled(Ps, D);  // the layer's input: the coarse activations, upsampled on the fly
+    const uint16_t* xin = up ? (s > 1 ? m->act[s - 1] : m->a2) : m->u[s];
+    e = launch_wgrad(3, Ps, D, a.ch[s - 1], a.ch[s], a.ch[s - 1], dh, xin, m->part, m->g + m->oC[s], m->cpart,
+                     m->g + m->oc[s], st, up);
     if (e != hipSuccess) break;
     e = launch_conv(3, Ps, D, a.ch[s], a.ch[s - 1], dh, m->Ct[s], nullptr, 0, nullptr, m->dU, nullptr, st);
     if (e != hipSuccess) break;
