@@ -335,7 +335,39 @@ k_conv3_tiled(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, co
         for (int j = 0; j < NB; ++j)
           if (j < nb) acc[mb][j] = F::mma(ac[mb], bc[j], acc[mb][j]);
     };
-    if constexpr (NB == 1) {
+    if constexpr (KC == 16) {
+      // 16 input channels: two taps per 16x16x32 MFMA (lanes kq < 2 carry tap 2p, kq >= 2
+      // tap 2p + 1, 8 channels each), 14 steps instead of 27 K = 16 ones; the missing
+      // 28th tap has zero weights (its A fragment repeats tap 26, finite times zero)
+      const uint16_t* wpair = w + ((int64_t)co0 + r) * cin + ci0 + (kq & 1) * 8;
+      bf16x8 pa[4], pna[4], pb[NB], pnb[NB];
+      auto pfetch = [&](int pn, bf16x8* ax, bf16x8* bx) {
+        const int mt = 2 * pn + (kq >> 1);
+        const int ta = mt < 27 ? mt : 26;
+        const int toffa = ((ta / 9 - 1) * HJ + ((ta / 3) % 3 - 1)) * HK + (ta % 3 - 1);
+        const uint16_t* wt = wpair + (int64_t)ta * cout * cin;
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          bx[j] = (j < nb && mt < 27) ? *reinterpret_cast<const bf16x8*>(wt + (int64_t)j * 16 * cin) : bf16x8{};
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+          ax[mb] = *reinterpret_cast<const bf16x8*>(halo + hbase[mb] - kq * KQ + toffa * PITCH + (kq & 1) * 8);
+      };
+      pfetch(0, pa, pb);
+#pragma unroll 1
+      for (int pn = 0; pn < 14; ++pn) {
+        if (pn + 1 < 14) pfetch(pn + 1, pna, pnb);
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            if (j < nb) acc[mb][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa[mb], pb[j], acc[mb][j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) pb[j] = pnb[j];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) pa[mb] = pna[mb];
+      }
+    } else if constexpr (NB == 1) {
       // taps in pairs with two register sets and no copies between them
 #pragma unroll 1
       for (int t = 0; t < 26; t += 2) {
