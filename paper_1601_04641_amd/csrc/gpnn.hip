@@ -1194,12 +1194,10 @@ hipError_t launch_wgrad(int ks, int64_t P, int D, int cin, int cout, int keep, c
     dim3 grid((unsigned)nch, (unsigned)pl.groups, (unsigned)pl.zt);
 #define WT1(A, B, U, UPV)                                                                                      \
   do {                                                                                                         \
-    static bool attr = false;                                                                                  \
-    if (!attr) {                                                                                               \
+    if (pl.lds > 65536) { /* opt in to the large LDS allocation (on the current device) */                    \
       hipError_t ea = hipFuncSetAttribute((const void*)k_wgrad3_tiled<A, B, U, UPV>,                           \
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);      \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);            \
       if (ea != hipSuccess) return ea;                                                                         \
-      attr = true;                                                                                             \
     }                                                                                                          \
     hipLaunchKernelGGL((k_wgrad3_tiled<A, B, U, UPV>), grid, dim3(256), pl.lds, st, dy, x, D, lg, cin, cout,   \
                        pl.nab, pl.ntiles, pl.tpb, part, dbp);                                                  \
