@@ -114,8 +114,6 @@ struct gp_ctx {
   int nw[2][3] = {{0}};
   double coef[2][3][8] = {{{0}}};  // a, b, b_lo, P = a^m as (re, im)
   void* vtab[3] = {nullptr};      // storage-precision 1/2 nu^2 a^2
-  double* vd[3] = {nullptr};      // FP64 potential tables
-  double* a2[3] = {nullptr};      // FP64 coordinate squares
   double* zpart = nullptr;
   int zgrid = 0;
   double* opart = nullptr;
@@ -447,12 +445,9 @@ int observe(gp_ctx* c, double raw[9]) {
   o.nx = c->p.nx;
   o.ny = c->p.ny;
   o.nz = c->p.nz;
-  o.x2 = c->a2[0];
-  o.y2 = c->a2[1];
-  o.z2 = c->a2[2];
-  o.vx = c->vd[0];
-  o.vy = c->vd[1];
-  o.vz = c->vd[2];
+  o.ax = gpk::AxisQ{0.5 * c->p.nux * c->p.nux, 0.5 * (c->p.nx - 1), c->p.dx};
+  o.ay = gpk::AxisQ{0.5 * c->p.nuy * c->p.nuy, 0.5 * (c->p.ny - 1), c->p.dy};
+  o.az = gpk::AxisQ{0.5 * c->p.nuz * c->p.nuz, 0.5 * (c->p.nz - 1), c->p.dz};
   o.partials = c->opart;
   o.grid = c->ogrid;
   o.out = c->oout;
@@ -494,8 +489,6 @@ void release(gp_ctx* c) {
     for (auto p : m) hipFree(p);
   for (int a = 0; a < 3; ++a) {
     (void)hipFree(c->vtab[a]);
-    (void)hipFree(c->vd[a]);
-    (void)hipFree(c->a2[a]);
   }
   (void)hipFree(c->zpart);
   (void)hipFree(c->opart);
@@ -544,18 +537,13 @@ int init_body(gp_ctx* c) {
       if ((rc = dalloc(c, &c->tab[mode][a], (size_t)n[a] * c->esize))) return rc;
   for (int a = 0; a < 3; ++a) {
     if ((rc = dalloc(c, &c->vtab[a], (size_t)n[a] * c->esize / 2))) return rc;
-    if ((rc = dalloc(c, &c->vd[a], (size_t)n[a] * sizeof(double)))) return rc;
-    if ((rc = dalloc(c, &c->a2[a], (size_t)n[a] * sizeof(double)))) return rc;
-    std::vector<double> x2(n[a]), v(n[a]);
+    std::vector<double> v(n[a]);
     std::vector<float> vf(n[a]);
     for (int i = 0; i < n[a]; ++i) {
       const double x = (i - 0.5 * (n[a] - 1)) * d[a];
-      x2[i] = x * x;
       v[i] = 0.5 * nu[a] * nu[a] * x * x;
       vf[i] = (float)v[i];
     }
-    HIPCHK(c, hipMemcpy(c->a2[a], x2.data(), n[a] * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->vd[a], v.data(), n[a] * sizeof(double), hipMemcpyHostToDevice));
     if (prec == GP_C128)
       HIPCHK(c, hipMemcpy(c->vtab[a], v.data(), n[a] * sizeof(double), hipMemcpyHostToDevice));
     else

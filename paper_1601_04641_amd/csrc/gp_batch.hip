@@ -45,9 +45,15 @@ struct BWork {
   int blk;
 };
 
-constexpr int kChunk = 1024;  // points per block of the pointwise batched kernels
+constexpr int kChunk = 8192;  // points per block of the pointwise batched kernels (32 per thread:
+                              // amortises the per-block FP64 reductions of the observables)
 constexpr int kMF = 8;        // points per lane of the fused y+z kernel's in-LDS line solves
 constexpr int kYZThreads = 256;  // threads of a fused y+z block (one plane in LDS; 1024 measured slower)
+
+// coordinate and potential of point i along axis a of instance I, from their closed forms
+// with rounded operations (no contraction): the same values as the host's FP64 tables
+__device__ __forceinline__ double bcoord(const BInst& I, int a, int i) { return ((double)i - I.pc[a]) * I.pd[a]; }
+__device__ __forceinline__ double bpot(const BInst& I, int a, double x) { return __dmul_rn(__dmul_rn(I.ph[a], x), x); }
 
 template <typename R> __device__ __forceinline__ typename VecOf<R>::T dval(const double* c) {
   typename VecOf<R>::T v;
@@ -398,25 +404,20 @@ __global__ void kb_reset_scale(const BInst* __restrict__ inst, DevState* st, int
 template <typename R>
 __global__ void __launch_bounds__(256)
 kb_observables(const typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst,
-               const BWork* __restrict__ work, const double* __restrict__ a2, const double* __restrict__ vd,
-               double* __restrict__ partials) {
+               const BWork* __restrict__ work, double* __restrict__ partials) {
   __shared__ double red[4];
   const BWork wk = work[blockIdx.x];
   const BInst& I = inst[wk.inst];
   const int nx = I.nx, ny = I.ny, nz = I.nz;
   const int64_t npts = (int64_t)nx * ny * nz, sx = (int64_t)ny * nz;
   const typename VecOf<R>::T* psi = psi_all + I.off;
-  const double *x2 = a2 + I.v_off[0], *y2 = a2 + I.v_off[1], *z2 = a2 + I.v_off[2];
-  const double *vx = vd + I.v_off[0], *vy = vd + I.v_off[1], *vz = vd + I.v_off[2];
   double acc[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = 0.0;
   const int64_t q0 = (int64_t)wk.blk * kChunk, q1 = min(q0 + kChunk, npts);
-  for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
-    const int k = (int)(q % nz);
-    const int64_t r = q / nz;
-    const int j = (int)(r % ny);
-    const int i = (int)(r / ny);
+  Idx3 ix(q0 + threadIdx.x, 256, ny, nz);
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += 256, ix.advance()) {
+    const int i = ix.i, j = ix.j, k = ix.k;
     const double re = psi[q].x, im = psi[q].y;
     const double n2 = re * re + im * im;
     double ex = 0, ey = 0, ez = 0, fx = 0, fy = 0, fz = 0;
@@ -433,11 +434,12 @@ kb_observables(const typename VecOf<R>::T* __restrict__ psi_all, const BInst* __
     acc[1] += lx;
     acc[2] += ly;
     acc[3] += lz;
-    acc[4] += (vx[i] + vy[j] + vz[k]) * n2;
+    const double xi = bcoord(I, 0, i), yj = bcoord(I, 1, j), zk = bcoord(I, 2, k);
+    acc[4] += __dadd_rn(__dadd_rn(bpot(I, 0, xi), bpot(I, 1, yj)), bpot(I, 2, zk)) * n2;
     acc[5] += n2 * n2;
-    acc[6] += x2[i] * n2;
-    acc[7] += y2[j] * n2;
-    acc[8] += z2[k] * n2;
+    acc[6] += __dmul_rn(xi, xi) * n2;
+    acc[7] += __dmul_rn(yj, yj) * n2;
+    acc[8] += __dmul_rn(zk, zk) * n2;
   }
   for (int c = 0; c < 9; ++c) {
     const double t = block_sum_256(acc[c], red);
@@ -465,23 +467,20 @@ constexpr int kResSums = 6;
 template <typename R>
 __global__ void __launch_bounds__(256)
 kb_residual(const typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst,
-            const BWork* __restrict__ work, const double* __restrict__ vd, double* __restrict__ partials) {
+            const BWork* __restrict__ work, double* __restrict__ partials) {
   __shared__ double red[4];
   const BWork wk = work[blockIdx.x];
   const BInst& I = inst[wk.inst];
   const int nx = I.nx, ny = I.ny, nz = I.nz;
   const int64_t npts = (int64_t)nx * ny * nz, sx = (int64_t)ny * nz;
   const typename VecOf<R>::T* psi = psi_all + I.off;
-  const double *vx = vd + I.v_off[0], *vy = vd + I.v_off[1], *vz = vd + I.v_off[2];
   double acc[kResSums];
 #pragma unroll
   for (int c = 0; c < kResSums; ++c) acc[c] = 0.0;
   const int64_t q0 = (int64_t)wk.blk * kChunk, q1 = min(q0 + kChunk, npts);
-  for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
-    const int k = (int)(q % nz);
-    const int64_t r = q / nz;
-    const int j = (int)(r % ny);
-    const int i = (int)(r / ny);
+  Idx3 ix(q0 + threadIdx.x, 256, ny, nz);
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += 256, ix.advance()) {
+    const int i = ix.i, j = ix.j, k = ix.k;
     const double re = psi[q].x, im = psi[q].y;
     double sr[3] = {0, 0, 0}, si[3] = {0, 0, 0};  // neighbour sums per axis
     if (i > 0) { sr[0] += psi[q - sx].x; si[0] += psi[q - sx].y; }
@@ -490,7 +489,8 @@ kb_residual(const typename VecOf<R>::T* __restrict__ psi_all, const BInst* __res
     if (j + 1 < ny) { sr[1] += psi[q + nz].x; si[1] += psi[q + nz].y; }
     if (k > 0) { sr[2] += psi[q - 1].x; si[2] += psi[q - 1].y; }
     if (k + 1 < nz) { sr[2] += psi[q + 1].x; si[2] += psi[q + 1].y; }
-    const double v = vx[i] + vy[j] + vz[k];
+    const double v =
+        __dadd_rn(__dadd_rn(bpot(I, 0, bcoord(I, 0, i)), bpot(I, 1, bcoord(I, 1, j))), bpot(I, 2, bcoord(I, 2, k)));
     double lr = v * re, li = v * im;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -637,8 +637,6 @@ struct gp_batch {
   BInst* dinst = nullptr;
   DevState* st = nullptr;
   void* vtab = nullptr;    // storage precision potentials, per instance x | y | z
-  double* vd = nullptr;    // FP64 potentials, same layout
-  double* a2 = nullptr;    // FP64 coordinate squares, same layout
   void* omega = nullptr;   // storage precision, per instance [mode][axis]
   BWork *wx = nullptr, *wy = nullptr, *wz = nullptr, *wo = nullptr, *wyz = nullptr;
   int nbx = 0, nby = 0, nbz = 0, nbo = 0, nbyz = 0;
@@ -712,8 +710,6 @@ void bfree(gp_batch* b) {
   (void)hipFree(b->dinst);
   (void)hipFree(b->st);
   (void)hipFree(b->vtab);
-  (void)hipFree(b->vd);
-  (void)hipFree(b->a2);
   (void)hipFree(b->omega);
   (void)hipFree(b->wx);
   (void)hipFree(b->wy);
@@ -870,8 +866,8 @@ int configure(gp_batch* b) {
       hi[i].zb0 = (int)wz.size() + yzb0[i];
       hi[i].zb1 = (int)wz.size() + yzb1[i];
     }
-  // potential and coordinate tables
-  std::vector<double> vd(voff), a2(voff);
+  // potential tables (storage precision; the FP64 reductions evaluate the closed forms)
+  std::vector<double> vd(voff);
   std::vector<float> vf(voff);
   for (int i = 0; i < b->n; ++i) {
     const gp_params& p = b->p[i];
@@ -880,13 +876,11 @@ int configure(gp_batch* b) {
     for (int a = 0; a < 3; ++a)
       for (int k = 0; k < n[a]; ++k) {
         const double x = (k - 0.5 * (n[a] - 1)) * d[a];
-        a2[hi[i].v_off[a] + k] = x * x;
         vd[hi[i].v_off[a] + k] = 0.5 * nu[a] * nu[a] * x * x;
         vf[hi[i].v_off[a] + k] = (float)(0.5 * nu[a] * nu[a] * x * x);
       }
   }
   int rc;
-  if ((rc = upload(b, &b->vd, vd)) || (rc = upload(b, &b->a2, a2))) return rc;
   (void)hipFree(b->vtab);
   b->vtab = nullptr;
   if (f32) {
@@ -1124,10 +1118,10 @@ int bobserve(gp_batch* b) {
   int rc = btimed(b, b->stream, 4, [&](hipStream_t t) {
     if (b->prec == GP_C64)
       hipLaunchKernelGGL(gpk::kb_observables<float>, dim3(b->nbo), dim3(256), 0, t, (const float2*)b->psi, b->dinst,
-                         b->wo, b->a2, b->vd, b->opart);
+                         b->wo, b->opart);
     else
       hipLaunchKernelGGL(gpk::kb_observables<double>, dim3(b->nbo), dim3(256), 0, t, (const double2*)b->psi,
-                         b->dinst, b->wo, b->a2, b->vd, b->opart);
+                         b->dinst, b->wo, b->opart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gpk::kb_obs_final, dim3(b->n), dim3(256), 0, t, b->opart, b->dinst, b->oout);
@@ -1298,10 +1292,10 @@ int gp_batch_residual(gp_batch* b, double* res, double* mu) {
   int rc = btimed(b, b->stream, 4, [&](hipStream_t t) {
     if (b->prec == GP_C64)
       hipLaunchKernelGGL(gpk::kb_residual<float>, dim3(b->nbo), dim3(256), 0, t, (const float2*)b->psi, b->dinst,
-                         b->wo, b->vd, b->opart);
+                         b->wo, b->opart);
     else
       hipLaunchKernelGGL(gpk::kb_residual<double>, dim3(b->nbo), dim3(256), 0, t, (const double2*)b->psi, b->dinst,
-                         b->wo, b->vd, b->opart);
+                         b->wo, b->opart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gpk::kb_res_final, dim3(b->n), dim3(256), 0, t, b->opart, b->dinst, b->oout);

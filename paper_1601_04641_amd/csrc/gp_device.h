@@ -530,6 +530,34 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
 }
 
 
+// (i, j, k) of a flat index q = (i ny + j) nz + k, advanced by a fixed stride without a
+// division per point: the stride's own (di, dj, dk) digits are added with carries (each
+// digit below its radix, so at most one carry per digit)
+struct Idx3 {
+  int i, j, k;
+  int di, dj, dk;
+  int ny, nz;
+  __device__ __forceinline__ Idx3(int64_t q, int64_t stride, int ny_, int nz_) : ny(ny_), nz(nz_) {
+    k = (int)(q % nz);
+    const int64_t r = q / nz;
+    j = (int)(r % ny);
+    i = (int)(r / ny);
+    dk = (int)(stride % nz);
+    const int64_t rs = stride / nz;
+    dj = (int)(rs % ny);
+    di = (int)(rs / ny);
+  }
+  __device__ __forceinline__ void advance() {
+    k += dk;
+    int c = k >= nz;
+    k -= c ? nz : 0;
+    j += dj + c;
+    c = j >= ny;
+    j -= c ? ny : 0;
+    i += di + c;
+  }
+};
+
 __device__ __forceinline__ double block_sum_256(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   const int w = threadIdx.x >> 6;

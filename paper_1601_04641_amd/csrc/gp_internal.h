@@ -58,15 +58,16 @@ hipError_t launch_scale(int precision, void* psi, int64_t n, DevState* st, hipSt
 
 // Observables: 9 FP64 sums per block into partials[nb][9], then a fixed-order final sum
 // into out[9] (raw, without dV or 1/(2 d^2) factors).
+// One axis of the harmonic potential in FP64: x_i = (i - c) d, V_i = (h x_i) x_i with
+// h = nu^2 / 2 and c = (n - 1) / 2 (the host tables' operations in the same order).
+struct AxisQ {
+  double h, c, d;
+};
+
 struct ObsLaunch {
   const void* psi;
   int nx, ny, nz;
-  const double* x2;  // coordinate squares per axis (FP64)
-  const double* y2;
-  const double* z2;
-  const double* vx;  // FP64 potential tables
-  const double* vy;
-  const double* vz;
+  AxisQ ax, ay, az;  // coordinates and potentials evaluated in place (no table loads)
   double* partials;
   int grid;
   double* out;

@@ -109,20 +109,18 @@ __global__ void k_reset_scale(DevState* st) {
 
 template <typename R>
 __global__ void __launch_bounds__(256)
-k_observables(const typename VecOf<R>::T* __restrict__ psi, int nx, int ny, int nz, const double* __restrict__ x2,
-              const double* __restrict__ y2, const double* __restrict__ z2, const double* __restrict__ vxt,
-              const double* __restrict__ vyt, const double* __restrict__ vzt, double* __restrict__ partials) {
+k_observables(const typename VecOf<R>::T* __restrict__ psi, int nx, int ny, int nz, AxisQ ax, AxisQ ay, AxisQ az,
+              double* __restrict__ partials) {
   __shared__ double red[4];
   const int64_t total = (int64_t)nx * ny * nz;
   const int64_t sx = (int64_t)ny * nz;
   double acc[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = 0.0;
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256) {
-    const int k = (int)(q % nz);
-    const int64_t r = q / nz;
-    const int j = (int)(r % ny);
-    const int i = (int)(r / ny);
+  const int64_t qs = (int64_t)gridDim.x * 256;
+  Idx3 ix((int64_t)blockIdx.x * 256 + threadIdx.x, qs, ny, nz);
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += qs, ix.advance()) {
+    const int i = ix.i, j = ix.j, k = ix.k;
     const double re = psi[q].x, im = psi[q].y;
     const double n2 = re * re + im * im;
     double ex = 0, ey = 0, ez = 0, fx = 0, fy = 0, fz = 0;
@@ -139,11 +137,17 @@ k_observables(const typename VecOf<R>::T* __restrict__ psi, int nx, int ny, int 
     acc[1] += lx;
     acc[2] += ly;
     acc[3] += lz;
-    acc[4] += (vxt[i] + vyt[j] + vzt[k]) * n2;
+    // coordinates and potentials from their closed forms: six FP64 table loads per point
+    // made this kernel bound by its load instructions
+    // (rounded operations, no contraction: the same values as the host's FP64 tables)
+    const double xi = ((double)i - ax.c) * ax.d, yj = ((double)j - ay.c) * ay.d, zk = ((double)k - az.c) * az.d;
+    const double v = __dadd_rn(__dadd_rn(__dmul_rn(__dmul_rn(ax.h, xi), xi), __dmul_rn(__dmul_rn(ay.h, yj), yj)),
+                               __dmul_rn(__dmul_rn(az.h, zk), zk));
+    acc[4] += v * n2;
     acc[5] += n2 * n2;
-    acc[6] += x2[i] * n2;
-    acc[7] += y2[j] * n2;
-    acc[8] += z2[k] * n2;
+    acc[6] += __dmul_rn(xi, xi) * n2;
+    acc[7] += __dmul_rn(yj, yj) * n2;
+    acc[8] += __dmul_rn(zk, zk) * n2;
   }
   for (int c = 0; c < 9; ++c) {
     const double t = block_sum_256(acc[c], red);
@@ -298,10 +302,10 @@ hipError_t launch_scale(int precision, void* psi, int64_t n, DevState* st, hipSt
 hipError_t launch_observables(int precision, const ObsLaunch& a, hipStream_t s) {
   if (precision == 0)
     hipLaunchKernelGGL(k_observables<float>, dim3(a.grid), dim3(256), 0, s, (const float2*)a.psi, a.nx, a.ny, a.nz,
-                       a.x2, a.y2, a.z2, a.vx, a.vy, a.vz, a.partials);
+                       a.ax, a.ay, a.az, a.partials);
   else
     hipLaunchKernelGGL(k_observables<double>, dim3(a.grid), dim3(256), 0, s, (const double2*)a.psi, a.nx, a.ny,
-                       a.nz, a.x2, a.y2, a.z2, a.vx, a.vy, a.vz, a.partials);
+                       a.nz, a.ax, a.ay, a.az, a.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, s, a.partials, a.grid, a.out);
