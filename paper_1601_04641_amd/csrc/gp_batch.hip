@@ -30,7 +30,7 @@ struct BInst {
   int nseg[3];           // segments per line: x, y (m points each), z (power of two)
   int nw[2][3];          // Sherman-Morrison correction length [imag, real][axis]
   int omega_off[2][3];   // element offsets into the omega table
-  int v_off[3];          // element offsets of the x, y, z potential / coordinate tables
+  int v_off[3];          // element offsets of the x, y, z potential tables
   int zb0, zb1;          // z-sweep blocks of this instance (norm partials)
   int ob0, ob1;          // observables / scale blocks of this instance
   double dt, dV;
@@ -51,7 +51,7 @@ constexpr int kMF = 8;        // points per lane of the fused y+z kernel's in-LD
 constexpr int kYZThreads = 256;  // threads of a fused y+z block (one plane in LDS; 1024 measured slower)
 
 // coordinate and potential of point i along axis a of instance I, from their closed forms
-// with rounded operations (no contraction): the same values as the host's FP64 tables
+// with rounded operations (no contraction): the values the host computes in FP64
 __device__ __forceinline__ double bcoord(const BInst& I, int a, int i) { return ((double)i - I.pc[a]) * I.pd[a]; }
 __device__ __forceinline__ double bpot(const BInst& I, int a, double x) { return __dmul_rn(__dmul_rn(I.ph[a], x), x); }
 

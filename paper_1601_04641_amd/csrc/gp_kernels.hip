@@ -139,7 +139,7 @@ k_observables(const typename VecOf<R>::T* __restrict__ psi, int nx, int ny, int 
     acc[3] += lz;
     // coordinates and potentials from their closed forms: six FP64 table loads per point
     // made this kernel bound by its load instructions
-    // (rounded operations, no contraction: the same values as the host's FP64 tables)
+    // (rounded operations, no contraction: the values the host computes in FP64)
     const double xi = ((double)i - ax.c) * ax.d, yj = ((double)j - ay.c) * ay.d, zk = ((double)k - az.c) * az.d;
     const double v = __dadd_rn(__dadd_rn(__dmul_rn(__dmul_rn(ax.h, xi), xi), __dmul_rn(__dmul_rn(ay.h, yj), yj)),
                                __dmul_rn(__dmul_rn(az.h, zk), zk));
