@@ -48,6 +48,7 @@ struct BWork {
 constexpr int kChunk = 8192;  // points per block of the pointwise batched kernels (32 per thread:
                               // amortises the per-block FP64 reductions of the observables)
 constexpr int kMF = 8;        // points per lane of the fused y+z kernel's in-LDS line solves
+constexpr int kZGroups = 4;   // consecutive line groups per block of the batched z sweep
 constexpr int kYZThreads = 256;  // threads of a fused y+z block (one plane in LDS; 1024 measured slower)
 
 // coordinate and potential of point i along axis a of instance I, from their closed forms
@@ -108,9 +109,10 @@ kb_sweep_z(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__
   if (EPI != 0) g = (R)st[wk.inst].g;
   const double acc = z_body<R, MZ, CC, NORM, EPI>(
       psi_all + I.off, dval<R>(cf), dval<R>(cf + 2), dval<R>(cf + 4), dval<R>(cf + 6),
-      omega_all + I.omega_off[mode][2], I.nw[mode][2], I.nz, I.nseg[2], (int64_t)I.nx * I.ny, vtab + I.v_off[0],
-      vtab + I.v_off[1], Pot1D<R>{(R)I.ph[2], (R)I.pc[2], (R)I.pd[2]}, I.ny, (R)(0.5 * I.dt), g, wk.blk,
-      (int64_t)1 << 62, smem_raw);
+      omega_all + I.omega_off[mode][2], I.nw[mode][2], I.nz, I.nseg[2],
+      min((int64_t)I.nx * I.ny, (int64_t)(wk.blk + 1) * kZGroups * 4 * (64 / I.nseg[2])), vtab + I.v_off[0],
+      vtab + I.v_off[1], Pot1D<R>{(R)I.ph[2], (R)I.pc[2], (R)I.pd[2]}, I.ny, (R)(0.5 * I.dt), g,
+      (int64_t)wk.blk * kZGroups, 1, smem_raw);
   if (NORM) {
     const double t = block_sum_256(acc, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -822,7 +824,7 @@ int configure(gp_batch* b) {
       voff += n[a];
     }
     const int bx = cdiv((int64_t)p.ny * p.nz, 64 / swx), by = cdiv((int64_t)p.nx * p.nz, 64 / swy);
-    const int bz = cdiv((int64_t)p.nx * p.ny, 4 * (64 / seg));
+    const int bz = cdiv((int64_t)p.nx * p.ny, 4 * (64 / seg) * gpk::kZGroups);
     const int bo = cdiv((int64_t)p.nx * p.ny * p.nz, gpk::kChunk);
     for (int k = 0; k < bx; ++k) wx.push_back({i, k});
     if (fuse) {
