@@ -486,7 +486,7 @@ void release(gp_ctx* c) {
   if (c->cap) (void)hipStreamDestroy(c->cap);
   (void)hipFree(c->st);
   for (auto& m : c->tab)
-    for (auto p : m) hipFree(p);
+    for (auto p : m) (void)hipFree(p);
   for (int a = 0; a < 3; ++a) {
     (void)hipFree(c->vtab[a]);
   }

@@ -152,7 +152,6 @@ k_dense_sk(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, int P
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const uint16_t* xr = x + (int64_t)(pv ? p : 0) * cin + kq * 8;
   const uint16_t* wr = w + (int64_t)(co0 + r) * cin + kq * 8;
-#pragma unroll 4
   for (int k0 = kb + wave * 32; k0 < ke; k0 += 128) {
     const bf16x8 av = pv ? *reinterpret_cast<const bf16x8*>(xr + k0) : bf16x8{};
 #pragma unroll
@@ -167,7 +166,8 @@ k_dense_sk(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, int P
     for (int i = 0; i < 4; ++i) red[wave][kq * 4 + i][j * 16 + r] = acc[j][i];
   __syncthreads();
 #pragma unroll
-  for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+  for (int it = 0; it < 4; ++it) {
+    const int e = threadIdx.x + 256 * it;
     const int pr = e >> 6, c = e & 63;
     if (p0 + pr < P && c < nb * 16)
       part[((int64_t)blockIdx.z * P + p0 + pr) * cout + co0 + c] = red[0][pr][c] + red[1][pr][c] + red[2][pr][c] +
