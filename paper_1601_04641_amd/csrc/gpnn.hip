@@ -1082,10 +1082,12 @@ hipError_t launch_conv(int ks, int64_t P, int D, int cin, int cout, const uint16
   if (ks == 3 && conv_tiled(P, D)) {
     const int TK = D < 16 ? D : 16, TJ = 4, TI = 256 / (TJ * TK);
     const size_t lds = (size_t)(TI + 2) * (TJ + 2) * (TK + 2) * ((k32 ? 32 : 16) + 8) * sizeof(uint16_t);
-    const int nbt = cout <= 16 ? 1 : cout <= 32 ? 2 : 4;  // 16-channel output blocks per wave
+    const int64_t nbrick = P / 256;
+    // 16-channel output blocks per wave; on small grids (fewer bricks than about two per
+    // CU) one per block, so that more blocks share the work
+    const int nbt = nbrick * ((cout + 63) / 64) < 512 ? 1 : cout <= 16 ? 1 : cout <= 32 ? 2 : 4;
     // about three resident blocks per CU walk the bricks (a multiple of 8 blocks so the
     // XCD dealing applies)
-    const int64_t nbrick = P / 256;
     const int64_t gy = (cout + 16 * nbt - 1) / (16 * nbt);
     int64_t gx = (kConvBlocks + gy - 1) / gy;
     gx = (gx + 7) / 8 * 8;
