@@ -1157,9 +1157,9 @@ WgPlan wgrad_plan(int ks, int64_t P, int D, int cin, int cout) {
     return w;
   }
   const int tco = cout < 64 ? cout : 64;
-  w.mco = tco <= 16 ? 1 : tco <= 32 ? 2 : 4;
+  w.mco = tco <= 16 ? 1 : 2;  // 32-channel output tiles at most: the wider tile measured slower
   w.mci = cin >= 32 ? 2 : 1;
-  w.nab = w.mco <= 2 ? 9 : 3;
+  w.nab = 9;
   w.nu = (w.nab * w.mci + 3) / 4;
   w.groups = (9 + w.nab - 1) / w.nab;
   w.zt = ((cout + 16 * w.mco - 1) / (16 * w.mco)) * ((cin + 16 * w.mci - 1) / (16 * w.mci));
@@ -1212,12 +1212,9 @@ hipError_t launch_wgrad(int ks, int64_t P, int D, int cin, int cout, int keep, c
     if (pl.mco == 1) {
       if (pl.mci == 2) WT(1, 2, 5);
       else WT(1, 1, 3);
-    } else if (pl.mco == 2) {
+    } else {
       if (pl.mci == 2) WT(2, 2, 5);
       else WT(2, 1, 3);
-    } else {
-      if (pl.mci == 2) WT(4, 2, 2);
-      else WT(4, 1, 1);
     }
 #undef WT
 #undef WT1
