@@ -59,7 +59,11 @@ enum { GP_FLAG_NONFINITE = 1, GP_FLAG_ZERO_NORM = 2 }; /* gp_status flags */
 typedef struct gp_ctx gp_ctx;
 
 typedef struct {
-  int32_t nx, ny, nz;     /* 3 <= n <= 1024 grid points per axis */
+  int32_t nx, ny, nz;     /* 3 <= n <= 2048 grid points per axis (gp_batch: <= 1024);
+                           * gp_init returns GP_ERR_UNSUPPORTED where no kernel mapping
+                           * covers a line (complex128: x and y lines <= 1024 points,
+                           * z lines <= 1016) or a wavefront's rows of an x/y sweep would
+                           * span 2 GiB or more (x: 64-128 planes of ny*nz points) */
   double dx, dy, dz;      /* > 0 spacings */
   double nux, nuy, nuz;   /* >= 0 trap frequencies */
   double g;               /* nonlinearity, any finite real */

@@ -162,28 +162,48 @@ bool bad_params(const gp_params* p) {
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Lines of one sweep axis: n points per line, element i of line l at
+// (l / inner) n inner + l % inner + i inner.
+struct AxisLines {
+  int n;
+  int64_t inner, nlines;
+  size_t esize;
+};
+
+AxisLines axis_lines(const gp_params& p, int axis) {
+  const size_t es = p.precision == GP_C128 ? 16 : 8;
+  if (axis == 0) return AxisLines{p.nx, (int64_t)p.ny * p.nz, (int64_t)p.ny * p.nz, es};
+  return AxisLines{p.ny, (int64_t)p.nz, (int64_t)p.nx * p.nz, es};
+}
+
 // x/y line mapping: m points per thread (the kernel instance's register count) and sw
-// segments per wavefront; a block holds ceil(ceil(n/m)/sw) <= 16 wavefronts.
-bool valid_lines(int prec, int n, int m, int sw) {
+// segments per wavefront; a block holds ceil(ceil(n/m)/sw) <= 16 wavefronts.  A
+// wavefront addresses its points by 32-bit byte offsets from its first point: its sw*m
+// rows plus the spread of its 64/sw lines (which cross into the next plane of the y
+// sweep) must stay below 2 GiB.
+bool valid_lines(int prec, const AxisLines& a, int m, int sw) {
   if (!gpk::sweep_lines_supported(prec, m, sw)) return false;
-  return ceil_div(ceil_div(n, m), sw) <= 16;
+  if (ceil_div(ceil_div(a.n, m), sw) > 16) return false;
+  const int64_t lw = 64 / sw;
+  const int64_t spread = a.nlines > a.inner ? ((lw - 1) / a.inner + 1) * a.inner * a.n : lw - 1;
+  return (spread + (int64_t)sw * m * a.inner) * (int64_t)a.esize < ((int64_t)1 << 31);
 }
 
 // Default: 16 points per thread; 4 segments per wavefront once a line has >= 16 segments
 // (16-line bundles, 8 wavefronts per block), else the fewest wavefronts-per-segment that
 // fit.  complex128 with the fused potential step uses 8 points per thread (register
 // budget).  gp_set_mapping / the autotuner can override this.
-bool pick_lines(int prec, int n, bool nstep, int* m_out, int* sw_out) {
+bool pick_lines(int prec, const AxisLines& a, bool nstep, int* m_out, int* sw_out) {
   const int m0 = (prec == GP_C128 && nstep) ? 8 : 16;
-  const int pref_sw = ceil_div(n, m0) >= 16 ? 4 : 1;
+  const int pref_sw = ceil_div(a.n, m0) >= 16 ? 4 : 1;
   for (int m = m0; m <= 32; m *= 2) {
-    if (valid_lines(prec, n, m, pref_sw)) {
+    if (valid_lines(prec, a, m, pref_sw)) {
       *m_out = m;
       *sw_out = pref_sw;
       return true;
     }
-    for (int sw : {1, 2, 4})
-      if (valid_lines(prec, n, m, sw)) {
+    for (int sw : {1, 2, 4, 8})
+      if (valid_lines(prec, a, m, sw)) {
         *m_out = m;
         *sw_out = sw;
         return true;
@@ -211,13 +231,13 @@ int z_grid(const gp_ctx* c, int segz, int64_t zgroups) {
 
 bool valid_z(int nz, int seg, int m, size_t esize) {
   if (seg < 2 || seg > 64 || (seg & (seg - 1)) != 0) return false;
-  if (!gpk::sweep_z_supported(0, m)) return false;
+  if (!gpk::sweep_z_supported(esize == 16 ? 1 : 0, m)) return false;
   if ((size_t)4 * (64 / seg) * nz * esize + 512 > 65536) return false;
   return (int64_t)seg * m >= nz;  // trailing positions are zero-coefficient padding
 }
 
 bool pick_z(int nz, size_t esize, int* seg_out, int* m_out) {
-  const int ms[] = {2, 4, 6, 7, 8, 12, 14, 16};
+  const int ms[] = {2, 4, 6, 7, 8, 12, 14, 16, 20, 24, 32};
   int best_seg = 0, best_m = 0;
   long best_score = -1;
   for (int seg = 64; seg >= 2; seg >>= 1)
@@ -275,7 +295,7 @@ gpk::SweepLaunch lines_args(gp_ctx* c, int axis, int mode) {
   gpk::SweepLaunch a{};
   const gp_params& p = c->p;
   a.psi = c->psi;
-  a.psi_bytes = (uint32_t)(c->npts * (int64_t)c->esize);
+  a.psi_bytes = c->npts * (int64_t)c->esize;
   a.n = axis == 0 ? p.nx : p.ny;
   a.m = axis == 0 ? c->map.mx : c->map.my;
   a.sw = axis == 0 ? c->map.swx : c->map.swy;
@@ -519,11 +539,16 @@ int check_psi(gp_ctx* c, void* psi) {
   return GP_OK;
 }
 
+// default mapping of a grid; false where no kernel instance covers one of its axes
+bool pick_mapping(const gp_params& p, Mapping* m) {
+  return pick_lines(p.precision, axis_lines(p, 0), true, &m->mx, &m->swx) &&
+         pick_lines(p.precision, axis_lines(p, 1), false, &m->my, &m->swy) &&
+         pick_z(p.nz, p.precision == GP_C128 ? 16 : 8, &m->segz, &m->mz);
+}
+
 int init_body(gp_ctx* c) {
   const gp_params& p = c->p;
-  const int prec = p.precision;
-  if (!pick_lines(prec, p.nx, true, &c->map.mx, &c->map.swx) || !pick_lines(prec, p.ny, false, &c->map.my, &c->map.swy) ||
-      !pick_z(p.nz, c->esize, &c->map.segz, &c->map.mz)) {
+  if (!pick_mapping(p, &c->map)) {
     snprintf(c->err, sizeof(c->err), "grid %dx%dx%d exceeds the supported line lengths", p.nx, p.ny, p.nz);
     return GP_ERR_UNSUPPORTED;
   }
@@ -544,7 +569,7 @@ int init_body(gp_ctx* c) {
       v[i] = 0.5 * nu[a] * nu[a] * x * x;
       vf[i] = (float)v[i];
     }
-    if (prec == GP_C128)
+    if (p.precision == GP_C128)
       HIPCHK(c, hipMemcpy(c->vtab[a], v.data(), n[a] * sizeof(double), hipMemcpyHostToDevice));
     else
       HIPCHK(c, hipMemcpy(c->vtab[a], vf.data(), n[a] * sizeof(float), hipMemcpyHostToDevice));
@@ -575,10 +600,9 @@ int gp_init(const gp_params* p, void* psi_dev, void* hip_stream, gp_ctx** out) {
   if (!out) return GP_ERR_INVALID;
   *out = nullptr;
   if (bad_params(p) || !psi_dev) return GP_ERR_INVALID;
-  if (p->nx > 1024 || p->ny > 1024 || p->nz > 1024) return GP_ERR_UNSUPPORTED;
-  // the sweeps address psi through 32-bit buffer offsets
-  if ((int64_t)p->nx * p->ny * p->nz * (p->precision == GP_C128 ? 16 : 8) >= (int64_t)1 << 32)
-    return GP_ERR_UNSUPPORTED;
+  if (p->nx > 2048 || p->ny > 2048 || p->nz > 2048) return GP_ERR_UNSUPPORTED;
+  Mapping m0{};
+  if (!pick_mapping(*p, &m0)) return GP_ERR_UNSUPPORTED;
   gp_ctx* c = new (std::nothrow) gp_ctx;
   if (!c) return GP_ERR_OOM;
   c->p = *p;
@@ -768,30 +792,31 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
   Mapping nm = c->map;
   const int prec = c->p.precision;
   // x and y: points per thread and segments per wavefront (0 keeps the current value)
-  auto lines = [&](int n, int m_in, int sw_in, int* m, int* sw) {
+  auto lines = [&](int axis, int m_in, int sw_in, int* m, int* sw) {
+    const AxisLines al = axis_lines(c->p, axis);
     const int mm = m_in > 0 ? m_in : *m;  // must be an instance size (8, 16, 32)
     if (sw_in > 0) {
-      if (!valid_lines(prec, n, mm, sw_in)) return false;
+      if (!valid_lines(prec, al, mm, sw_in)) return false;
       *m = mm;
       *sw = sw_in;
       return true;
     }
-    for (int s : {1, 2, 4})
-      if (valid_lines(prec, n, mm, s)) {
+    for (int s : {1, 2, 4, 8})
+      if (valid_lines(prec, al, mm, s)) {
         *m = mm;
         *sw = s;
         return true;
       }
     return false;
   };
-  if ((map[0] > 0 || map[1] > 0) && !lines(c->p.nx, map[0], map[1], &nm.mx, &nm.swx)) return GP_ERR_INVALID;
-  if ((map[2] > 0 || map[3] > 0) && !lines(c->p.ny, map[2], map[3], &nm.my, &nm.swy)) return GP_ERR_INVALID;
+  if ((map[0] > 0 || map[1] > 0) && !lines(0, map[0], map[1], &nm.mx, &nm.swx)) return GP_ERR_INVALID;
+  if ((map[2] > 0 || map[3] > 0) && !lines(1, map[2], map[3], &nm.my, &nm.swy)) return GP_ERR_INVALID;
   if (map[4] > 0 || map[5] > 0) {
     const int seg = map[4] > 0 ? map[4] : nm.segz;
     int m = map[5];
     if (m <= 0) {  // smallest instance size that covers the line
-      for (int cand : {2, 4, 6, 7, 8, 12, 14, 16})
-        if ((int64_t)seg * cand >= c->p.nz) {
+      for (int cand : {2, 4, 6, 7, 8, 12, 14, 16, 20, 24, 32})
+        if ((int64_t)seg * cand >= c->p.nz && gpk::sweep_z_supported(c->esize == 16 ? 1 : 0, cand)) {
           m = cand;
           break;
         }
@@ -902,10 +927,10 @@ extern "C" int gp_autotune(gp_ctx* c, int32_t mode, int32_t steps, const char* c
   double best_ms[3] = {1e300, 1e300, 1e300};
   const int ms_lines[] = {8, 10, 12, 16, 32};
   for (int axis = 0; axis < 2 && rc == GP_OK; ++axis) {
-    const int n = axis == 0 ? c->p.nx : c->p.ny;
+    const AxisLines al = axis_lines(c->p, axis);
     for (int m : ms_lines)
-      for (int sw : {1, 2, 4}) {
-        if (!valid_lines(prec, n, m, sw)) continue;
+      for (int sw : {1, 2, 4, 8}) {
+        if (!valid_lines(prec, al, m, sw)) continue;
         int32_t cand[6];
         for (int q = 0; q < 6; ++q) cand[q] = best[q];
         cand[2 * axis] = m;
@@ -921,7 +946,7 @@ extern "C" int gp_autotune(gp_ctx* c, int32_t mode, int32_t steps, const char* c
       }
   }
   for (int seg = 2; seg <= 64 && rc == GP_OK; seg <<= 1)
-    for (int m : {2, 4, 6, 7, 8, 12, 14, 16}) {
+    for (int m : {2, 4, 6, 7, 8, 12, 14, 16, 20, 24, 32}) {
       if (!valid_z(c->p.nz, seg, m, c->esize)) continue;
       if ((int64_t)seg * m - c->p.nz >= m) continue;  // a whole trailing segment would be empty
       int32_t cand[6];

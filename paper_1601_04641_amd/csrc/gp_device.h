@@ -227,9 +227,13 @@ template <typename R> struct Pot1D {
 // identical values); element i of line l sits at base(l) + i*inner.  Each thread holds M
 // consecutive points of one line in registers.  nwi > 0: the omega correction is applied
 // here (nwi <= M, so it stays inside segment 0); otherwise k_head_correction follows.
+// Each wavefront addresses psi from its own first point (first line of the block, first
+// segment of the wavefront: the smallest element index any of its lanes touches), so the
+// 32-bit byte offsets span only the wavefront's own rows and lines, whatever the size of
+// psi; the host keeps that span below 2 GiB.
 // ---------------------------------------------------------------------------------------
 template <typename R, int M, int SW, bool CC, int NSTEP>
-__device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ psi, uint32_t psi_bytes,
+__device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ psi, int64_t psi_bytes,
                                            typename VecOf<R>::T ca, typename VecOf<R>::T cb,
                                            typename VecOf<R>::T cbl, typename VecOf<R>::T cP,
                                            const typename VecOf<R>::T* __restrict__ omega, int nwi, int n,
@@ -257,8 +261,11 @@ __device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ ps
   cf.b = cb;
   cf.bl = cbl;
 
-  const __amdgpu_buffer_rsrc_t rs = make_rsrc(psi, psi_bytes);
-  const uint32_t voff = (uint32_t)((base + (int64_t)s * inner) * (int64_t)sizeof(V));
+  const int64_t line0 = min(bidx * LW, nlines - 1);
+  const int64_t e0 = (line0 / inner) * (inner * n) + (line0 % inner) + (int64_t)(w * SW * M) * inner;
+  const int64_t left_bytes = psi_bytes - e0 * (int64_t)sizeof(V);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(psi + e0, (uint32_t)min(left_bytes, (int64_t)0xffffffff));
+  const uint32_t voff = (uint32_t)((base + (int64_t)s * inner - e0) * (int64_t)sizeof(V));
   const uint32_t srow = (uint32_t)(inner * (int64_t)sizeof(V));
   V v[M];
 #pragma unroll

@@ -25,7 +25,7 @@ struct DevState {
 // device) the Sherman-Morrison head correction.
 struct SweepLaunch {
   void* psi;
-  uint32_t psi_bytes;  // size of psi in bytes (< 4 GiB: buffer addressing)
+  int64_t psi_bytes;  // size of psi in bytes
   double coef[8];
   const void* omega;
   int nw;

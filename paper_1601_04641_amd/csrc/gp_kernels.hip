@@ -38,7 +38,7 @@ namespace gpk {
 // ---------------------------------------------------------------------------------------
 template <typename R, int M, int SW, bool CC, int NSTEP>
 __global__ void __launch_bounds__(1024)
-k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, uint32_t psi_bytes, typename VecOf<R>::T ca,
+k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, int64_t psi_bytes, typename VecOf<R>::T ca,
               typename VecOf<R>::T cb, typename VecOf<R>::T cbl, typename VecOf<R>::T cP,
               const typename VecOf<R>::T* __restrict__ omega, int nwi, int n, int nseg, int64_t nlines,
               int64_t inner, Pot1D<R> px, const R* __restrict__ vy, const R* __restrict__ vz, int nz,
@@ -203,9 +203,10 @@ static hipError_t go_lines_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
 
 // Instances: complex64 M in {8, 10, 12, 16, 32}, complex128 M in {8, 16} (32 complex
 // doubles per thread would not fit the 128-VGPR budget of 1024-thread blocks); SW in
-// {1, 2, 4}.  M = 10 and 12 keep the real-time x sweep (with the phase factor) at <= 64
+// {1, 2, 4}, and SW = 8 with complex64 M = 16.  M = 10 and 12 keep the real-time x sweep (with the phase factor) at <= 64
 // VGPRs, i.e. 8 waves per SIMD, where M = 16 needs 80 (6 waves).
 bool sweep_lines_supported(int precision, int m, int sw) {
+  if (sw == 8) return precision == 0 && m == 16;  // lines of up to 2048 points without M = 32's spills
   if (sw != 1 && sw != 2 && sw != 4) return false;
   if (precision == 0) return m == 8 || m == 10 || m == 12 || m == 16 || m == 32;
   return m == 8 || m == 16;
@@ -221,6 +222,7 @@ bool sweep_lines_supported(int precision, int m, int sw) {
 hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipStream_t s) {
   if (precision == 0) {
     if (a.m == 8) GP_LINES_SW(float, 8);
+    if (a.m == 16 && a.sw == 8) return go_lines_mode<float, 16, 8>(cc, a, s);
     if (a.m == 16) GP_LINES_SW(float, 16);
     if (a.m == 12) GP_LINES_SW(float, 12);
     if (a.m == 10) GP_LINES_SW(float, 10);
@@ -253,9 +255,11 @@ static hipError_t go_z_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
   return a.nstep ? go_z<R, MZ, true, false, 2>(a, s) : go_z<R, MZ, true, false, 0>(a, s);
 }
 
-// z instances: points per thread MZ in {2, 4, 6, 7, 8, 12, 14, 16}
+// z instances: points per thread MZ in {2, 4, 6, 7, 8, 12, 14, 16}; complex64 also
+// {20, 24, 32} for lines longer than 1024 points (64 segments; the block's 4 lines of a
+// complex128 line that long would not fit 64 KiB of LDS)
 bool sweep_z_supported(int precision, int mz) {
-  (void)precision;
+  if (precision == 0 && (mz == 20 || mz == 24 || mz == 32)) return true;
   return mz == 2 || mz == 4 || mz == 6 || mz == 7 || mz == 8 || mz == 12 || mz == 14 || mz == 16;
 }
 
@@ -275,7 +279,12 @@ bool sweep_z_supported(int precision, int mz) {
   } while (0)
 
 hipError_t launch_sweep_z(int precision, bool cc, const SweepLaunch& a, hipStream_t s) {
-  if (precision == 0) GP_Z_M(float);
+  if (precision == 0) {
+    if (a.m == 20) return go_z_mode<float, 20>(cc, a, s);
+    if (a.m == 24) return go_z_mode<float, 24>(cc, a, s);
+    if (a.m == 32) return go_z_mode<float, 32>(cc, a, s);
+    GP_Z_M(float);
+  }
   GP_Z_M(double);
 }
 #undef GP_Z_M

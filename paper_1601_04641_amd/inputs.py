@@ -26,6 +26,13 @@ WORKLOADS = {
     "quench_512x480x448": dict(nx=512, ny=480, nz=448, dx=0.05, dy=0.05, dz=0.05, nux=1.0,
                                nuy=1.4142, nuz=1.7321, g=100.0, dt=0.01 * 0.05 ** 2,
                                dt_imag=0.1 * 0.05 ** 2, g_quench=50.0, steps=1000),
+    # the paper's large run grids (1000 iterations each) with the quench workload's box and
+    # trap: imaginary time on 1920x1600x1280, real time on 1600x1280x960 (complex64)
+    "paper_imag_1920x1600x1280": dict(nx=1920, ny=1600, nz=1280, dx=0.05 * 512 / 1920, dy=0.05 * 512 / 1920,
+                                      dz=0.05 * 512 / 1920, nux=1.0, nuy=1.4142, nuz=1.7321, g=100.0,
+                                      dt=0.1 * (0.05 * 512 / 1920) ** 2, steps=1000),
+    "paper_real_1600x1280x960": dict(nx=1600, ny=1280, nz=960, dx=0.016, dy=0.016, dz=0.016, nux=1.0,
+                                     nuy=1.4142, nuz=1.7321, g=100.0, dt=0.01 * 0.016 ** 2, steps=1000),
     # precision form: 384^3, dx = 0.08, imaginary time (trap drawn per seed)
     "imag_384cube": dict(nx=384, ny=384, nz=384, dx=0.08, dy=0.08, dz=0.08, dt=0.1 * 0.08 ** 2,
                          steps=20000),
@@ -48,6 +55,18 @@ def gaussian_psi(nx, ny, nz, dx, dy, dz, nux, nuy, nuz, dtype=np.complex128) -> 
     psi = parts[0][:, None, None] * parts[1][None, :, None] * parts[2][None, None, :]
     psi = psi / math.sqrt(float(np.sum(psi * psi)) * dx * dy * dz)
     return psi.astype(dtype)
+
+
+def gaussian_factors(nx, ny, nz, dx, dy, dz, nux, nuy, nuz):
+    """The three 1D factors whose outer product is gaussian_psi (each normalised on its
+    own axis), for grids too large to build on the host."""
+    out = []
+    for n, d, nu in ((nx, dx, nux), (ny, dy, nuy), (nz, dz, nuz)):
+        w = nu if nu > 0 else 1.0
+        a = axis(n, d)
+        f = np.exp(-0.5 * w * a * a)
+        out.append(f / math.sqrt(float(np.sum(f * f)) * d))
+    return out
 
 
 def gaussian_cube_batch(prm, n: int, d: float, out: np.ndarray | None = None, dtype=np.complex64) -> np.ndarray:

@@ -53,12 +53,19 @@ def test_init_rejects_bad_params_without_device(lib, field, value):
 
 
 def test_init_rejects_oversized_grids_without_device(lib):
-    p = gp.make_params(2048, 8, 8, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001)
-    rc, _ = gp.gp_init(p, 0x1000, 0)
-    assert rc == gp.GP_ERR_UNSUPPORTED
-    p = gp.make_params(1024, 1024, 600, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001, gp.GP_C128)
-    rc, _ = gp.gp_init(p, 0x1000, 0)
-    assert rc == gp.GP_ERR_UNSUPPORTED
+    # more than 2048 points on an axis; complex128 lines over 1024 points (no instance);
+    # complex64 2048^3, where every x mapping's wavefront would span over 2 GiB of rows
+    for n, prec in [((2049, 8, 8), gp.GP_C64), ((8, 8, 4096), gp.GP_C64), ((1100, 8, 8), gp.GP_C128),
+                    ((8, 8, 1020), gp.GP_C128), ((2048, 2048, 2048), gp.GP_C64)]:
+        p = gp.make_params(*n, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001, prec)
+        rc, _ = gp.gp_init(p, 0x1000, 0)
+        assert rc == gp.GP_ERR_UNSUPPORTED, n
+    # the paper's large grids in complex64 have a mapping: init goes on to the device
+    # (and fails there only for want of one)
+    for n in [(1920, 1600, 1280), (1600, 1280, 960), (2048, 3, 5), (4, 3, 2032)]:
+        p = gp.make_params(*n, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001, gp.GP_C64)
+        rc, _ = gp.gp_init(p, 0x1000, 0)
+        assert rc != gp.GP_ERR_UNSUPPORTED, n
 
 
 def test_null_arguments(lib):

@@ -1,0 +1,141 @@
+"""GPU: lines longer than 1024 points and psi beyond 4 GiB (the paper's large run grids,
+1920x1600x1280 imaginary time and 1600x1280x960 real time, on one device).
+
+* Lines of 1025-2048 points: every point against the CPU FP64 oracle on grids whose
+  other axes are short, both time kinds, complex64 (complex128 lines that long are
+  rejected with GP_ERR_UNSUPPORTED).
+* 1920x1600x1280 complex64 (31.5 GB): sampled points against a property that holds at
+  any size.  With g = 0 the potential factor of a Lie step is the product of three 1D
+  factors and each sweep acts on its own axis only, so one step maps a product state
+  f(x) g(y) h(z) to the product of the three 1D results; each 1D result is the oracle's
+  potential step and sweep on a grid three points wide in the other two axes (whose
+  centre row has zero potential there).  In imaginary time the library also
+  renormalises, so both sides are compared at unit norm.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_04641_amd import gp, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gp.load()
+    yield
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+LONG_SHAPES = [(1100, 4, 1090), (2048, 3, 5), (5, 1300, 9), (3, 2048, 4), (4, 3, 2032), (6, 5, 1500)]
+
+
+@pytest.mark.parametrize("shape", LONG_SHAPES)
+@pytest.mark.parametrize("imag", [True, False])
+def test_long_lines_match_oracle(shape, imag):
+    nx, ny, nz = shape
+    prm = dict(nx=nx, ny=ny, nz=nz, dx=0.03, dy=0.031, dz=0.029, nux=1.2, nuy=1.4, nuz=1.1, g=30.0, dt=4e-4)
+    psi0 = inputs.perturbed_psi(nx, ny, nz, prm["dx"], prm["dy"], prm["dz"], 0.02, 0.025, 0.015,
+                                seed=nx + 3 * ny + 7 * nz, amp=0.2)
+    say(f"case: long lines {shape} imag {imag}")
+    psi = torch.from_numpy(np.ascontiguousarray(psi0)).to(device="cuda", dtype=torch.complex64)
+    with gp.Solver.from_workload(psi, prm) as s:
+        say(f"  mapping {s.get_mapping()}")
+        (s.step_imag if imag else s.step_real)(3)
+        torch.cuda.synchronize()
+        out = psi.cpu().numpy().astype(np.complex128)
+    o = oracle.Oracle.from_params(prm, psi0)
+    (o.step_imag if imag else o.step_real)(3)
+    err = rel_err(out, o.psi)
+    say(f"  rel err {err:.2e}")
+    assert err <= 2e-6
+
+
+def test_long_complex128_lines_rejected():
+    prm = dict(nx=1100, ny=4, nz=6, dx=0.03, dy=0.03, dz=0.03, nux=1.0, nuy=1.0, nuz=1.0, g=1.0, dt=4e-4)
+    psi = torch.zeros((1100, 4, 6), dtype=torch.complex128, device="cuda")
+    with pytest.raises(gp.GPError):
+        gp.Solver.from_workload(psi, prm)
+
+
+def factor_1d(n, d, seed):
+    """Seeded smooth complex profile with a random phase ripple (test input)."""
+    rng = np.random.default_rng(seed)
+    x = (np.arange(n) - 0.5 * (n - 1)) * d
+    w = 0.22 * (n - 1) * d
+    amp = np.exp(-(x / w) ** 2) * (1.0 + 0.1 * np.sin(rng.uniform(2, 6) * x / w))
+    return amp * np.exp(1j * rng.uniform(0.5, 1.5) * np.cos(x / w))
+
+
+def oracle_1d(axis, f, prm, imag):
+    """Potential step then the sweep along `axis` of the oracle, on a grid three points
+    wide in the other axes holding f on its centre row; returns that row."""
+    shp = [3, 3, 3]
+    shp[axis] = f.size
+    psi0 = np.zeros(shp, dtype=np.complex128)
+    idx = [1, 1, 1]
+    idx[axis] = slice(None)
+    psi0[tuple(idx)] = f
+    p = dict(prm, nx=shp[0], ny=shp[1], nz=shp[2], g=0.0)
+    o = oracle.Oracle.from_params(p, psi0)
+    o.substep(0, imag, p["dt"])
+    o.substep(axis + 1, imag, p["dt"])
+    out = o.psi[tuple(idx)].copy()
+    o.close()
+    return out
+
+
+@pytest.mark.parametrize("imag", [False, True])
+def test_31gb_separable_step(imag):
+    nx, ny, nz = 1920, 1600, 1280
+    d = 0.05
+    prm = dict(nx=nx, ny=ny, nz=nz, dx=d, dy=d, dz=d, nux=1.0, nuy=1.4142, nuz=1.7321, g=0.0,
+               dt=1e-3 if not imag else 2.5e-4)
+    f = [factor_1d(n, d, 11 + a) for a, n in enumerate((nx, ny, nz))]
+    say(f"case: separable {nx}x{ny}x{nz} complex64 imag {imag}: building psi on the device")
+    t0 = time.time()
+    fx, fy, fz = (torch.from_numpy(v.astype(np.complex64)).to("cuda") for v in f)
+    psi = (fx[:, None, None] * fy[None, :, None]) * fz[None, None, :]
+    del fx, fy, fz
+    torch.cuda.synchronize()
+    say(f"  built ({time.time() - t0:.1f}s, {psi.numel() * 8 / 1e9:.1f} GB)")
+    with gp.Solver.from_workload(psi, prm) as s:
+        say(f"  mapping {s.get_mapping()}")
+        (s.step_imag if imag else s.step_real)(1)
+        norm = s.norm()
+        torch.cuda.synchronize()
+    say(f"  stepped ({time.time() - t0:.1f}s)")
+    X, Y, Z = (oracle_1d(a, f[a], prm, imag) for a in range(3))
+    nX, nY, nZ = (float(np.sum(np.abs(v) ** 2)) * d for v in (X, Y, Z))
+    scale = 1.0 / np.sqrt(nX * nY * nZ) if imag else 1.0
+    rng = np.random.default_rng(5)
+    m = 20000
+    i = np.concatenate([rng.integers(0, nx, m), [0, nx - 1, nx - 1, nx - 1, 0], np.full(nz, nx - 1)])
+    j = np.concatenate([rng.integers(0, ny, m), [0, ny - 1, 0, ny - 1, ny - 1], np.full(nz, ny // 2)])
+    k = np.concatenate([rng.integers(0, nz, m), [0, nz - 1, 0, 0, nz - 1], np.arange(nz)])
+    it, jt, kt = (torch.from_numpy(a).to("cuda") for a in (i, j, k))
+    got = psi[it, jt, kt].cpu().numpy().astype(np.complex128)
+    want = X[i] * Y[j] * Z[k] * scale
+    peak = float(np.max(np.abs(X)) * np.max(np.abs(Y)) * np.max(np.abs(Z))) * scale
+    err = float(np.max(np.abs(got - want))) / peak
+    say(f"  sampled rel err {err:.2e}; norm {norm:.10f}")
+    assert err <= 2e-6
+    want_norm = 1.0 if imag else nX * nY * nZ
+    assert abs(norm - want_norm) <= 1e-5 * want_norm
+    del psi, it, jt, kt
+    torch.cuda.empty_cache()

@@ -446,3 +446,37 @@ def test_residual_matches_brute_force_on_a_tiny_grid():
     want = np.sqrt(dV * np.sum(np.abs(h - mu * phi) ** 2))
     r, m = residual(psi, prm)
     assert abs(m - mu) <= 1e-12 * abs(mu) and abs(r - want) <= 1e-12 * want
+
+
+# ----------------------------------------------------------------------------------------
+# P13: with g = 0 a Lie step maps a product state to the product of 1D results (the
+# potential factor is a product of 1D factors, each sweep acts on its own axis); the 1D
+# result of an axis is the potential step and sweep on a grid three points wide in the
+# other axes, read on its centre row (zero potential there).  The large-grid GPU test
+# builds its expected values this way.
+# ----------------------------------------------------------------------------------------
+def _centre_row_step(axis, f, prm, imag):
+    shp = [3, 3, 3]
+    shp[axis] = f.size
+    psi0 = np.zeros(shp, dtype=np.complex128)
+    idx = [1, 1, 1]
+    idx[axis] = slice(None)
+    psi0[tuple(idx)] = f
+    o = oracle.Oracle.from_params(dict(prm, nx=shp[0], ny=shp[1], nz=shp[2], g=0.0), psi0)
+    o.substep(0, imag, prm["dt"])
+    o.substep(axis + 1, imag, prm["dt"])
+    return o.psi[tuple(idx)].copy()
+
+
+@pytest.mark.parametrize("imag", [False, True])
+def test_lie_step_of_product_state_factorises(imag):
+    nx, ny, nz, d = 23, 17, 12, 0.3
+    prm = dict(nx=nx, ny=ny, nz=nz, dx=d, dy=d, dz=d, nux=1.0, nuy=1.4142, nuz=1.7321, g=0.0, dt=0.02)
+    rng = np.random.default_rng(3)
+    f = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for n in (nx, ny, nz)]
+    o = oracle.Oracle.from_params(prm, np.einsum("i,j,k->ijk", *f))
+    (o.step_imag if imag else o.step_real)(1)
+    want = np.einsum("i,j,k->ijk", *(_centre_row_step(a, f[a], prm, imag) for a in range(3)))
+    if imag:
+        want /= math.sqrt(float(np.sum(np.abs(want) ** 2)) * d ** 3)
+    assert np.max(np.abs(o.psi - want)) <= 1e-13 * np.max(np.abs(want))
