@@ -217,13 +217,13 @@ bool pick_lines(int prec, const AxisLines& a, bool nstep, int* m_out, int* sw_ou
 // z sweep grid: the blocks that fit on the device at once (LDS bound: each block holds
 // 4 L lines of nz points), each walking an equal share of the line groups; a second,
 // partial round of blocks would leave most CUs idle at the tail
-int z_grid(const gp_ctx* c, int segz, int64_t zgroups) {
+int z_grid(const gp_ctx* c, int segz, int mz, int64_t zgroups) {
   int cus = 0, lds_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1) cus = 256;
   if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) != hipSuccess ||
       lds_cu < 65536)
     lds_cu = 65536;
-  const int64_t lds = (int64_t)4 * (64 / segz) * c->p.nz * (int64_t)c->esize;
+  const int64_t lds = (int64_t)gpk::z_lds(c->p.nz, segz, mz, gpk::z_pad(c->p.nz, segz, mz, c->esize), c->esize);
   int64_t per_cu = lds_cu / std::max<int64_t>(lds, 1);
   per_cu = std::max<int64_t>(1, std::min<int64_t>(per_cu, 8));
   return (int)std::max<int64_t>(1, std::min<int64_t>(zgroups, per_cu * cus));
@@ -347,6 +347,7 @@ gpk::SweepLaunch z_args(gp_ctx* c, int mode) {
   a.st = c->st;
   a.partials = mode == 0 ? c->zpart : nullptr;
   a.grid = c->zgrid;
+  a.zpad = gpk::z_pad(p.nz, a.nseg, a.m, c->esize);
   return a;
 }
 
@@ -577,7 +578,7 @@ int init_body(gp_ctx* c) {
   if ((rc = build_tables(c))) return rc;
   const int64_t zlines = (int64_t)p.nx * p.ny;
   const int64_t zgroups = (zlines + 4 * (64 / c->map.segz) - 1) / (4 * (64 / c->map.segz));
-  c->zgrid = z_grid(c, c->map.segz, zgroups);
+  c->zgrid = z_grid(c, c->map.segz, c->map.mz, zgroups);
   const int64_t oblocks = (c->npts + 255) / 256;
   c->ogrid = (int)std::min<int64_t>(oblocks, 2048);
   if ((rc = dalloc(c, &c->zpart, (size_t)c->zgrid * sizeof(double)))) return rc;
@@ -830,7 +831,7 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
   c->map = nm;
   const int64_t zlines = (int64_t)c->p.nx * c->p.ny;
   const int64_t zgroups = (zlines + 4 * (64 / nm.segz) - 1) / (4 * (64 / nm.segz));
-  const int zgrid = z_grid(c, nm.segz, zgroups);
+  const int zgrid = z_grid(c, nm.segz, nm.mz, zgroups);
   if (zgrid > c->zgrid) {
     double* np = nullptr;
     int rc = dalloc(c, &np, (size_t)zgrid * sizeof(double));

@@ -27,6 +27,7 @@ struct BInst {
   int64_t off;     // element offset of this instance's psi in the concatenated buffer
   uint32_t bytes;  // size of this instance's psi in bytes
   int split;
+  int zpad;              // z sweep LDS layout (z_pad)
   int nseg[3];           // segments per line: x, y (m points each), z (power of two)
   int nw[2][3];          // Sherman-Morrison correction length [imag, real][axis]
   int omega_off[2][3];   // element offsets into the omega table
@@ -112,7 +113,7 @@ kb_sweep_z(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__
       omega_all + I.omega_off[mode][2], I.nw[mode][2], I.nz, I.nseg[2],
       min((int64_t)I.nx * I.ny, (int64_t)(wk.blk + 1) * kZGroups * 4 * (64 / I.nseg[2])), vtab + I.v_off[0],
       vtab + I.v_off[1], Pot1D<R>{(R)I.ph[2], (R)I.pc[2], (R)I.pd[2]}, I.ny, (R)(0.5 * I.dt), g,
-      (int64_t)wk.blk * kZGroups, 1, smem_raw);
+      (int64_t)wk.blk * kZGroups, 1, I.zpad, smem_raw);
   if (NORM) {
     const double t = block_sum_256(acc, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -799,7 +800,8 @@ int configure(gp_batch* b) {
     const size_t lyz = (size_t)p.ny * (p.nz + 1) * b->esize;
     const bool fuse = b->yz_fuse && p.split == GP_SPLIT_LIE && p.ny <= 256 && p.nz <= 256 && lyz <= b->max_lds;
     if (cdiv(I.nseg[0], swx) > 16 || (!fuse && cdiv(I.nseg[1], swy) > 16)) return GP_ERR_UNSUPPORTED;
-    const size_t lz = (size_t)4 * (64 / seg) * p.nz * b->esize;
+    I.zpad = gpk::z_pad(p.nz, seg, mz, b->esize);
+    const size_t lz = gpk::z_lds(p.nz, seg, mz, I.zpad, b->esize);
     if (!fuse && lz + 512 > 65536) return GP_ERR_UNSUPPORTED;
     if (!fuse) ldsz = std::max(ldsz, lz);
     if (fuse) ldsyz = std::max(ldsyz, lyz);

@@ -386,9 +386,14 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
                                          typename VecOf<R>::T cP, const typename VecOf<R>::T* __restrict__ omega,
                                          int nwi, int nz, int nseg, int64_t nlines, const R* __restrict__ vx,
                                          const R* __restrict__ vy, Pot1D<R> pz, int ny, R tau, R g,
-                                         int64_t grp_begin, int64_t grp_step, unsigned char* smem_raw) {
+                                         int64_t grp_begin, int64_t grp_step, int zpad,
+                                         unsigned char* smem_raw) {
   typedef typename VecOf<R>::T V;
   V* sdata = reinterpret_cast<V*>(smem_raw);
+  // LDS rows of `pitch` values; with zp = 1 point q of a line sits at q + q / MZ (one empty
+  // slot after each segment, even MZ only, so the two points of a 16-byte pair share one)
+  const int zp = (MZ % 2 == 0) ? zpad : 0;
+  const int pitch = z_pitch(nz, MZ, zp);
 
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int L = 64 / nseg;
@@ -396,38 +401,75 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
   const int lines_per_grp = 4 * L;
   const int64_t ngrp = (nlines + lines_per_grp - 1) / lines_per_grp;
   const int s = p * MZ;
+  const int ss = s + zp * p;  // LDS position of the segment's first point
   const int len = max(0, min(MZ, nz - s));
   Coef<V> cf;
   cf.a = ca;
   cf.b = cb;
   cf.bl = cbl;
   double acc = 0.0;
+  // this thread's copy positions advance by 256 points (or pairs) per iteration: their
+  // (line, point) digits advance by the step's own digits with one carry
+  const int half = nz >> 1;
+  const bool pairs = sizeof(V) == 8 && (nz & 1) == 0;  // with zp = 1 (MZ even)
+  const int cn = pairs ? half : nz;
+  const int dl = 256 / cn, dq = 256 % cn;
 
   for (int64_t grp = grp_begin; grp < ngrp; grp += grp_step) {
     const int64_t line0 = grp * lines_per_grp;
     const int nl = (int)min((int64_t)lines_per_grp, nlines - line0);
     const int cnt = nl * nz;
     const V* src = psi + line0 * nz;
-    if (sizeof(V) == 8 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {  // 16-byte copies
+    if (zp == 0) {
+      if (sizeof(V) == 8 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {  // 16-byte copies
+        const float4* s4 = reinterpret_cast<const float4*>(src);
+        float4* d4 = reinterpret_cast<float4*>(sdata);
+        for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];
+      } else {
+        for (int q = tid; q < cnt; q += 256) sdata[q] = src[q];
+      }
+    } else if (pairs) {  // 16-byte global loads; a pair never straddles a line or segment
       const float4* s4 = reinterpret_cast<const float4*>(src);
-      float4* d4 = reinterpret_cast<float4*>(sdata);
-      for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];
+      int cl = tid / cn, cq = tid % cn;
+      for (int f = tid; f < (cnt >> 1); f += 256) {
+        const int q = 2 * cq, at = cl * pitch + q + q / MZ;
+        const float4 x = s4[f];
+        sdata[at] = vmake<V>(x.x, x.y);
+        sdata[at + 1] = vmake<V>(x.z, x.w);
+        cq += dq;
+        cl += dl;
+        if (cq >= cn) {
+          cq -= cn;
+          ++cl;
+        }
+      }
     } else {
-      for (int q = tid; q < cnt; q += 256) sdata[q] = src[q];
+      int cl = tid / cn, cq = tid % cn;
+      for (int f = tid; f < cnt; f += 256) {
+        sdata[cl * pitch + cq + cq / MZ] = src[f];
+        cq += dq;
+        cl += dl;
+        if (cq >= cn) {
+          cq -= cn;
+          ++cl;
+        }
+      }
     }
     __syncthreads();
 
     const int ll = w * L + l;
     const bool act = (ll < nl) && (len > 0);
-    V* row = sdata + (act ? ll * nz : 0);
+    V* row = sdata + (act ? ll * pitch : 0);
     V v[MZ];
 #pragma unroll
     for (int t = 0; t < MZ; ++t) {
       v[t] = vzero<V>();
-      if (act && t < len) v[t] = row[s + t];
+      if (act && t < len) v[t] = row[ss + t];
     }
-    const V left = (act && s > 0) ? row[s - 1] : vzero<V>();
-    const V right = (act && s + len < nz) ? row[s + len] : vzero<V>();
+    // neighbours: the previous segment's last point and (for a full segment) the next
+    // segment's first point
+    const V left = (act && s > 0) ? row[ss - 1 - zp] : vzero<V>();
+    const V right = (act && s + len < nz) ? row[ss + len + zp] : vzero<V>();
 
     V d = vzero<V>();
     {
@@ -518,18 +560,45 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
         if (t < len) {
           if (EPI != 0) v[t] = nstep<EPI, R, V>(v[t], (R)1, vxy + pz.at(s + t), g, tau);
           if (NORM) acc = fma((double)v[t].x, (double)v[t].x, fma((double)v[t].y, (double)v[t].y, acc));
-          row[s + t] = v[t];
+          row[ss + t] = v[t];
         }
       }
     }
     __syncthreads();
     V* dst = psi + line0 * nz;
-    if (sizeof(V) == 8 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {
+    if (zp == 0) {
+      if (sizeof(V) == 8 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {
+        float4* d4 = reinterpret_cast<float4*>(dst);
+        const float4* s4 = reinterpret_cast<const float4*>(sdata);
+        for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];
+      } else {
+        for (int q = tid; q < cnt; q += 256) dst[q] = sdata[q];
+      }
+    } else if (pairs) {
       float4* d4 = reinterpret_cast<float4*>(dst);
-      const float4* s4 = reinterpret_cast<const float4*>(sdata);
-      for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];
+      int cl = tid / cn, cq = tid % cn;
+      for (int f = tid; f < (cnt >> 1); f += 256) {
+        const int q = 2 * cq, at = cl * pitch + q + q / MZ;
+        const V a = sdata[at], b = sdata[at + 1];
+        d4[f] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+        cq += dq;
+        cl += dl;
+        if (cq >= cn) {
+          cq -= cn;
+          ++cl;
+        }
+      }
     } else {
-      for (int q = tid; q < cnt; q += 256) dst[q] = sdata[q];
+      int cl = tid / cn, cq = tid % cn;
+      for (int f = tid; f < cnt; f += 256) {
+        dst[f] = sdata[cl * pitch + cq + cq / MZ];
+        cq += dq;
+        cl += dl;
+        if (cq >= cn) {
+          cq -= cn;
+          ++cl;
+        }
+      }
     }
     __syncthreads();
   }

@@ -23,6 +23,23 @@ struct DevState {
 // Per-axis Crank-Nicolson constants of the constant-pivot solve (see gp_kernels.hip):
 // coef = {a, b, b_lo, P} as (re, im) pairs, P = a^m; omega[nw] (storage precision,
 // device) the Sherman-Morrison head correction.
+// z sweep LDS layout.  A block holds 4 L lines of nz values (L = 64 / seg lines per
+// wavefront); lane p of a line reads and writes points p*mz .. p*mz + mz - 1, so with
+// packed rows the lanes of a wavefront are mz values apart and an even mz puts many of
+// them on the same LDS banks (mz = 16: every lane of a half-wavefront on two banks).
+// zpad = 1 leaves one empty slot after each segment: segments start mz + 1 (odd) values
+// apart and a wavefront's accesses spread over all banks.  Taken for mz a multiple of 4
+// (4-way or worse conflicts when packed; 1280-point lines: z sweep 20.2 -> 15.2 ms)
+// whenever the padded block still fits 64 KiB; other even mz conflict 2-way at most,
+// which measured no slower packed.
+__host__ __device__ inline int z_pitch(int nz, int mz, int zpad) { return nz + zpad * ((nz + mz - 1) / mz); }
+inline size_t z_lds(int nz, int seg, int mz, int zpad, size_t esize) {
+  return (size_t)4 * (64 / seg) * (size_t)z_pitch(nz, mz, zpad) * esize;
+}
+inline int z_pad(int nz, int seg, int mz, size_t esize) {
+  return (mz % 4 == 0 && z_lds(nz, seg, mz, 1, esize) + 512 <= 65536) ? 1 : 0;
+}
+
 struct SweepLaunch {
   void* psi;
   int64_t psi_bytes;  // size of psi in bytes
@@ -46,6 +63,7 @@ struct SweepLaunch {
   const DevState* st;
   double* partials; // z sweep: per-block FP64 sum |psi|^2 (imaginary time), else null
   int grid;         // z sweep: number of blocks
+  int zpad;         // z sweep: one empty LDS slot after each segment (z_pad)
 };
 
 // precision: 0 complex64, 1 complex128; cc: complex coefficients (real time)

@@ -58,13 +58,13 @@ __global__ void __launch_bounds__(256)
 k_sweep_z(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typename VecOf<R>::T cb,
           typename VecOf<R>::T cbl, typename VecOf<R>::T cP, const typename VecOf<R>::T* __restrict__ omega, int nwi,
           int nz, int nseg, int64_t nlines, double* __restrict__ partials, const R* __restrict__ vx,
-          const R* __restrict__ vy, Pot1D<R> pz, int ny, R tau, const DevState* __restrict__ st) {
+          const R* __restrict__ vy, Pot1D<R> pz, int ny, R tau, const DevState* __restrict__ st, int zpad) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[4];
   R g = 0;
   if (EPI != 0) g = (R)st->g;
   const double acc = z_body<R, MZ, CC, NORM, EPI>(psi, ca, cb, cbl, cP, omega, nwi, nz, nseg, nlines, vx, vy, pz, ny,
-                                                  tau, g, blockIdx.x, gridDim.x, smem_raw);
+                                                  tau, g, blockIdx.x, gridDim.x, zpad, smem_raw);
   if (NORM) {
     const double t = block_sum_256(acc, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -238,12 +238,12 @@ hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipS
 template <typename R, int MZ, bool CC, bool NORM, int EPI>
 static hipError_t go_z(const SweepLaunch& a, hipStream_t s) {
   typedef typename VecOf<R>::T V;
-  const int L = 64 / a.nseg;
-  const size_t lds = (size_t)4 * L * a.nz * sizeof(V);
+  const int zpad = (MZ % 2 == 0) ? a.zpad : 0;
+  const size_t lds = z_lds(a.nz, a.nseg, MZ, zpad, sizeof(V));
   hipLaunchKernelGGL((k_sweep_z<R, MZ, CC, NORM, EPI>), dim3(a.grid), dim3(256), lds, s, (V*)a.psi,
                      cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4), cval<R>(a.coef + 6),
                      (const V*)a.omega, a.nw, a.nz, a.nseg, a.nlines, a.partials, (const R*)a.vx, (const R*)a.vy,
-                     Pot1D<R>{(R)a.ph, (R)a.pc, (R)a.pd}, a.ny, (R)a.tau, a.st);
+                     Pot1D<R>{(R)a.ph, (R)a.pc, (R)a.pd}, a.ny, (R)a.tau, a.st, zpad);
   return hipGetLastError();
 }
 
