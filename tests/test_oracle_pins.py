@@ -449,7 +449,7 @@ def test_residual_matches_brute_force_on_a_tiny_grid():
 
 
 # ----------------------------------------------------------------------------------------
-# P13: with g = 0 a Lie step maps a product state to the product of 1D results (the
+# P14: with g = 0 a Lie step maps a product state to the product of 1D results (the
 # potential factor is a product of 1D factors, each sweep acts on its own axis); the 1D
 # result of an axis is the potential step and sweep on a grid three points wide in the
 # other axes, read on its centre row (zero potential there).  The large-grid GPU test
