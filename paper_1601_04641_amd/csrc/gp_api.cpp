@@ -926,7 +926,7 @@ extern "C" int gp_autotune(gp_ctx* c, int32_t mode, int32_t steps, const char* c
   const int prec = c->p.precision;
   gp_get_mapping(c, best);
   double best_ms[3] = {1e300, 1e300, 1e300};
-  const int ms_lines[] = {8, 10, 12, 16, 32};
+  const int ms_lines[] = {8, 10, 12, 16, 30, 32};
   for (int axis = 0; axis < 2 && rc == GP_OK; ++axis) {
     const AxisLines al = axis_lines(c->p, axis);
     for (int m : ms_lines)

@@ -203,10 +203,11 @@ static hipError_t go_lines_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
 
 // Instances: complex64 M in {8, 10, 12, 16, 32}, complex128 M in {8, 16} (32 complex
 // doubles per thread would not fit the 128-VGPR budget of 1024-thread blocks); SW in
-// {1, 2, 4}, and SW = 8 with complex64 M = 16.  M = 10 and 12 keep the real-time x sweep (with the phase factor) at <= 64
+// {1, 2, 4}, and SW = 8 with complex64 M = 16, SW = 4 with complex64 M = 30.  M = 10 and 12 keep the real-time x sweep (with the phase factor) at <= 64
 // VGPRs, i.e. 8 waves per SIMD, where M = 16 needs 80 (6 waves).
 bool sweep_lines_supported(int precision, int m, int sw) {
   if (sw == 8) return precision == 0 && m == 16;  // lines of up to 2048 points without M = 32's spills
+  if (m == 30) return precision == 0 && sw == 4;  // 1920-point lines in 16 wavefronts, 128-byte line chunks
   if (sw != 1 && sw != 2 && sw != 4) return false;
   if (precision == 0) return m == 8 || m == 10 || m == 12 || m == 16 || m == 32;
   return m == 8 || m == 16;
@@ -223,6 +224,7 @@ hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipS
   if (precision == 0) {
     if (a.m == 8) GP_LINES_SW(float, 8);
     if (a.m == 16 && a.sw == 8) return go_lines_mode<float, 16, 8>(cc, a, s);
+    if (a.m == 30 && a.sw == 4) return go_lines_mode<float, 30, 4>(cc, a, s);
     if (a.m == 16) GP_LINES_SW(float, 16);
     if (a.m == 12) GP_LINES_SW(float, 12);
     if (a.m == 10) GP_LINES_SW(float, 10);

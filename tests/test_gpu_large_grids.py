@@ -66,6 +66,35 @@ def test_long_lines_match_oracle(shape, imag):
     assert err <= 2e-6
 
 
+LONG_MAPPINGS = [(16, 8), (30, 4), (32, 4)]
+
+
+@pytest.mark.parametrize("mp", LONG_MAPPINGS)
+@pytest.mark.parametrize("shape,axis,imag", [((1920, 3, 4), 0, True), ((1920, 3, 4), 0, False),
+                                             ((1600, 4, 3), 0, False), ((4, 1600, 5), 1, True)])
+def test_long_line_mappings_match_oracle(mp, shape, axis, imag):
+    """Every x/y instance that covers lines of more than 1024 points (the autotuner picks
+    among them on the paper's grids)."""
+    nx, ny, nz = shape
+    prm = dict(nx=nx, ny=ny, nz=nz, dx=0.03, dy=0.031, dz=0.029, nux=1.2, nuy=1.4, nuz=1.1, g=30.0, dt=4e-4)
+    psi0 = inputs.perturbed_psi(nx, ny, nz, prm["dx"], prm["dy"], prm["dz"], 0.02, 0.025, 0.015,
+                                seed=2 * nx + ny + nz, amp=0.2)
+    say(f"case: long-line mapping {mp} axis {axis} shape {shape} imag {imag}")
+    psi = torch.from_numpy(np.ascontiguousarray(psi0)).to(device="cuda", dtype=torch.complex64)
+    with gp.Solver.from_workload(psi, prm) as s:
+        s.set_mapping(*((mp[0], mp[1], 0, 0) if axis == 0 else (0, 0, mp[0], mp[1])), 0, 0)
+        got = s.get_mapping()
+        assert tuple(got[2 * axis:2 * axis + 2]) == mp
+        (s.step_imag if imag else s.step_real)(3)
+        torch.cuda.synchronize()
+        out = psi.cpu().numpy().astype(np.complex128)
+    o = oracle.Oracle.from_params(prm, psi0)
+    (o.step_imag if imag else o.step_real)(3)
+    err = rel_err(out, o.psi)
+    say(f"  rel err {err:.2e}")
+    assert err <= 2e-6
+
+
 def test_long_complex128_lines_rejected():
     prm = dict(nx=1100, ny=4, nz=6, dx=0.03, dy=0.03, dz=0.03, nux=1.0, nuy=1.0, nuz=1.0, g=1.0, dt=4e-4)
     psi = torch.zeros((1100, 4, 6), dtype=torch.complex128, device="cuda")
