@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--paper-scale", action="store_true",
                     help="instead of the default run: 1000 iterations on each of the paper's large "
                          "grids (1920x1600x1280 imaginary, 1600x1280x960 real time), complex64")
+    ap.add_argument("--paper-iterations", type=int, default=1000,
+                    help="timed iterations per grid in --paper-scale (the paper's runs: 1000)")
     return ap.parse_args()
 
 
@@ -261,7 +263,7 @@ def run_paper_scale(torch, gp, inputs, args):
     out = {}
     for name, imag in (("paper_imag_1920x1600x1280", True), ("paper_real_1600x1280x960", False)):
         w = dict(inputs.WORKLOADS[name])
-        nx, ny, nz, K = w["nx"], w["ny"], w["nz"], w["steps"]
+        nx, ny, nz, K = w["nx"], w["ny"], w["nz"], args.paper_iterations
         npts = nx * ny * nz
         f = [torch.from_numpy(v.astype(np.complex64)).to("cuda")
              for v in inputs.gaussian_factors(nx, ny, nz, w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"], w["nuz"])]
