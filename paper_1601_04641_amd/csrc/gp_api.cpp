@@ -237,7 +237,7 @@ bool valid_z(int nz, int seg, int m, size_t esize) {
 }
 
 bool pick_z(int nz, size_t esize, int* seg_out, int* m_out) {
-  const int ms[] = {2, 4, 6, 7, 8, 12, 14, 16, 20, 24, 32};
+  const int ms[] = {2, 4, 6, 7, 8, 12, 14, 15, 16, 20, 24, 32};
   int best_seg = 0, best_m = 0;
   long best_score = -1;
   for (int seg = 64; seg >= 2; seg >>= 1)
@@ -816,7 +816,7 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
     const int seg = map[4] > 0 ? map[4] : nm.segz;
     int m = map[5];
     if (m <= 0) {  // smallest instance size that covers the line
-      for (int cand : {2, 4, 6, 7, 8, 12, 14, 16, 20, 24, 32})
+      for (int cand : {2, 4, 6, 7, 8, 12, 14, 15, 16, 20, 24, 32})
         if ((int64_t)seg * cand >= c->p.nz && gpk::sweep_z_supported(c->esize == 16 ? 1 : 0, cand)) {
           m = cand;
           break;
@@ -947,7 +947,7 @@ extern "C" int gp_autotune(gp_ctx* c, int32_t mode, int32_t steps, const char* c
       }
   }
   for (int seg = 2; seg <= 64 && rc == GP_OK; seg <<= 1)
-    for (int m : {2, 4, 6, 7, 8, 12, 14, 16, 20, 24, 32}) {
+    for (int m : {2, 4, 6, 7, 8, 12, 14, 15, 16, 20, 24, 32}) {
       if (!valid_z(c->p.nz, seg, m, c->esize)) continue;
       if ((int64_t)seg * m - c->p.nz >= m) continue;  // a whole trailing segment would be empty
       int32_t cand[6];

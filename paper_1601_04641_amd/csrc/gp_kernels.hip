@@ -259,9 +259,10 @@ static hipError_t go_z_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
 
 // z instances: points per thread MZ in {2, 4, 6, 7, 8, 12, 14, 16}; complex64 also
 // {20, 24, 32} for lines longer than 1024 points (64 segments; the block's 4 lines of a
-// complex128 line that long would not fit 64 KiB of LDS)
+// complex128 line that long would not fit 64 KiB of LDS) and 15 (960 = 64 x 15 with
+// packed, conflict-free LDS rows and 5 blocks per CU)
 bool sweep_z_supported(int precision, int mz) {
-  if (precision == 0 && (mz == 20 || mz == 24 || mz == 32)) return true;
+  if (precision == 0 && (mz == 15 || mz == 20 || mz == 24 || mz == 32)) return true;
   return mz == 2 || mz == 4 || mz == 6 || mz == 7 || mz == 8 || mz == 12 || mz == 14 || mz == 16;
 }
 
@@ -282,6 +283,7 @@ bool sweep_z_supported(int precision, int mz) {
 
 hipError_t launch_sweep_z(int precision, bool cc, const SweepLaunch& a, hipStream_t s) {
   if (precision == 0) {
+    if (a.m == 15) return go_z_mode<float, 15>(cc, a, s);
     if (a.m == 20) return go_z_mode<float, 20>(cc, a, s);
     if (a.m == 24) return go_z_mode<float, 24>(cc, a, s);
     if (a.m == 32) return go_z_mode<float, 32>(cc, a, s);

@@ -42,7 +42,7 @@ def rel_err(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-LONG_SHAPES = [(1100, 4, 1090), (2048, 3, 5), (5, 1300, 9), (3, 2048, 4), (4, 3, 2032), (6, 5, 1500)]
+LONG_SHAPES = [(1100, 4, 1090), (2048, 3, 5), (5, 1300, 9), (3, 2048, 4), (4, 3, 2032), (6, 5, 1500), (3, 4, 960)]
 
 
 @pytest.mark.parametrize("shape", LONG_SHAPES)
