@@ -61,8 +61,9 @@ typedef struct gp_ctx gp_ctx;
 typedef struct {
   int32_t nx, ny, nz;     /* 3 <= n <= 2048 grid points per axis (gp_batch: <= 1024);
                            * gp_init returns GP_ERR_UNSUPPORTED where no kernel mapping
-                           * covers a line (complex128: x and y lines <= 1024 points,
-                           * z lines <= 1016) or a wavefront's rows of an x/y sweep would
+                           * covers a line (z lines: a block's 4 lines must fit 64 KiB
+                           * of LDS, <= 2032 points complex64, <= 1016 complex128; x and
+                           * y lines of complex128 <= 1024) or a wavefront's rows of an x/y sweep would
                            * span 2 GiB or more (x: 64-128 planes of ny*nz points) */
   double dx, dy, dz;      /* > 0 spacings */
   double nux, nuy, nuz;   /* >= 0 trap frequencies */

@@ -55,7 +55,8 @@ def test_init_rejects_bad_params_without_device(lib, field, value):
 def test_init_rejects_oversized_grids_without_device(lib):
     # more than 2048 points on an axis; complex128 lines over 1024 points (no instance);
     # complex64 2048^3, where every x mapping's wavefront would span over 2 GiB of rows
-    for n, prec in [((2049, 8, 8), gp.GP_C64), ((8, 8, 4096), gp.GP_C64), ((1100, 8, 8), gp.GP_C128),
+    for n, prec in [((2049, 8, 8), gp.GP_C64), ((8, 8, 4096), gp.GP_C64), ((8, 8, 2040), gp.GP_C64),
+                    ((1100, 8, 8), gp.GP_C128),
                     ((8, 8, 1020), gp.GP_C128), ((2048, 2048, 2048), gp.GP_C64)]:
         p = gp.make_params(*n, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001, prec)
         rc, _ = gp.gp_init(p, 0x1000, 0)
