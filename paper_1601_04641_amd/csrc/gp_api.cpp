@@ -192,24 +192,28 @@ bool valid_lines(int prec, const AxisLines& a, int m, int sw) {
 // Default: 16 points per thread; 4 segments per wavefront once a line has >= 16 segments
 // (16-line bundles, 8 wavefronts per block), else the fewest wavefronts-per-segment that
 // fit.  complex128 with the fused potential step uses 8 points per thread (register
-// budget).  gp_set_mapping / the autotuner can override this.
+// budget).  Lines beyond 1024 points (complex64) take 30 or 32 points per thread with 4
+// segments per wavefront (128-byte line chunks: 18.7 and 13.5 ms for the x and y sweeps
+// of the 1920x1600x1280 grid) before 16 points with 8 segments (64-byte chunks: 31.7 and
+// 18.3 ms).  gp_set_mapping / the autotuner can override this.
 bool pick_lines(int prec, const AxisLines& a, bool nstep, int* m_out, int* sw_out) {
   const int m0 = (prec == GP_C128 && nstep) ? 8 : 16;
   const int pref_sw = ceil_div(a.n, m0) >= 16 ? 4 : 1;
-  for (int m = m0; m <= 32; m *= 2) {
-    if (valid_lines(prec, a, m, pref_sw)) {
-      *m_out = m;
-      *sw_out = pref_sw;
-      return true;
-    }
-    for (int sw : {1, 2, 4, 8})
-      if (valid_lines(prec, a, m, sw)) {
-        *m_out = m;
-        *sw_out = sw;
-        return true;
-      }
+  auto take = [&](int m, int sw) {
+    if (!valid_lines(prec, a, m, sw)) return false;
+    *m_out = m;
+    *sw_out = sw;
+    return true;
+  };
+  for (int m = m0; m <= 16; m *= 2) {
+    if (take(m, pref_sw)) return true;
+    for (int sw : {1, 2, 4})
+      if (take(m, sw)) return true;
   }
-  return false;
+  for (int m : {30, 32})
+    for (int sw : {1, 2, 4})
+      if (take(m, sw)) return true;
+  return take(16, 8);
 }
 
 // z mapping: seg threads per line (power of two <= 64), m points per thread (an instance
