@@ -799,7 +799,7 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
   // x and y: points per thread and segments per wavefront (0 keeps the current value)
   auto lines = [&](int axis, int m_in, int sw_in, int* m, int* sw) {
     const AxisLines al = axis_lines(c->p, axis);
-    const int mm = m_in > 0 ? m_in : *m;  // must be an instance size (8, 16, 32)
+    const int mm = m_in > 0 ? m_in : *m;  // must be an instance size (sweep_lines_supported)
     if (sw_in > 0) {
       if (!valid_lines(prec, al, mm, sw_in)) return false;
       *m = mm;
