@@ -104,10 +104,16 @@ int gp_set_psi(gp_ctx* c, void* psi_dev);
  * the imaginary-time renormalisation, and GP_FLAG_* bits.  Synchronises. */
 int gp_status(gp_ctx* c, int64_t* steps_done, double* mu_est, int32_t* flags);
 
-/* Imaginary-time propagation until |mu_n - mu_{n-K}| <= tol |mu_n| holds at two successive
- * checks (one check can straddle a turning point of mu(t) when the start is already close),
- * mu evaluated every check_every = K steps (K <= 0 selects ceil(0.25/dt)), at most
- * max_steps steps.
+/* Imaginary-time propagation to the ground state at relative tolerance tol, checking every
+ * check_every = K steps (K <= 0 selects ceil(0.25/dt)), at most max_steps steps.
+ * Stopping rule, on the sequence of checked values m_n with d_n = m_n - m_{n-1}: while
+ * m approaches its limit geometrically (d_n / d_{n-1} = r in (0, 1)), stop when |d_n| and
+ * the extrapolated distance to the limit |d_n| r / (1 - r) (Aitken) are both <= tol |m_n|;
+ * otherwise (m(t) turning, as from an already close start, or at its rounding floor) when
+ * |d_n| <= tol |m_n| at two successive checks.  complex64: m = mu (the observables pass) at
+ * every check.  complex128: m = mu_est = -ln(N_pre)/(2 dt) from the renormalisation (no
+ * extra pass); when it stops, mu is evaluated and must change by at most tol |mu| (with the
+ * same predicted tail) over one more interval, else monitoring resumes.
  * Returns the steps taken and the final mu.  GP_OK also when max_steps is reached;
  * *converged tells which.  Synchronises at every check. */
 int gp_converge_imag(gp_ctx* c, double tol, int32_t check_every, int64_t max_steps,
@@ -167,9 +173,9 @@ int gp_batch_status(gp_batch* b, int64_t* steps_done, double* mu_est, int32_t* f
  * Zero exactly at a discrete ground state; used to judge a starting state before
  * imaginary-time propagation.  Synchronises. */
 int gp_batch_residual(gp_batch* b, double* res, double* mu);
-/* Imaginary time until every instance meets |mu_n - mu_{n-K}| <= tol |mu_n| at two
- * successive checks (every K steps, K <= 0 selects ceil(0.25/min dt)), as
- * gp_converge_imag; converged instances are masked off
+/* Imaginary time until every instance meets gp_converge_imag's stopping rule on its mu
+ * (observables every K steps, K <= 0 selects ceil(0.25/min dt)); converged instances are
+ * masked off
  * while the rest continue.  Per-instance steps taken, final mu and converged flag. */
 int gp_batch_converge_imag(gp_batch* b, double tol, int32_t check_every, int64_t max_steps,
                            int64_t* steps_taken, double* mu, int32_t* converged);
@@ -187,13 +193,35 @@ int gp_batch_set_yz_fusion(gp_batch* b, int32_t enable);
 int gp_batch_get_yz_fusion(gp_batch* b, int32_t* enabled, int32_t* fused_instances);
 int gp_batch_get_mapping(gp_batch* b, int32_t map[5]);
 int gp_batch_set_mapping(gp_batch* b, const int32_t map[5]);
-int gp_batch_autotune(gp_batch* b, int32_t mode, int32_t steps, int32_t map_out[5]);
+/* cache_path (nullable): a text file of earlier results keyed by the instances' grid sizes
+ * (in order), their count, precision, splitting and step kind mode (0 imaginary, 1 real);
+ * a hit applies the stored mapping and y+z fusion choice without timing, a miss appends
+ * the new result. */
+int gp_batch_autotune(gp_batch* b, int32_t mode, int32_t steps, const char* cache_path, int32_t map_out[5]);
 int gp_batch_set_timing(gp_batch* b, int32_t enable);
 int gp_batch_get_timing(gp_batch* b, double ms_mean[5], int64_t launches[5]);
 const char* gp_batch_last_error(gp_batch* b);
 
 const char* gp_strerror(int code);
 const char* gp_last_error(gp_ctx* c);
+
+/* ---------------------------------------------------------------------------------------
+ * Test and measurement support (not part of the method).
+ * ------------------------------------------------------------------------------------- */
+/* Failure injection: every later device allocation the library makes for its own buffers
+ * (contexts, batches, networks, autotuner copies) that asks for more than `bytes` fails
+ * with GP_ERR_OOM (networks: GPNN_ERR_OOM) without reaching the runtime.  bytes < 0
+ * removes the cap (the default).  Process-wide; not thread-safe against concurrent
+ * init calls. */
+int gp_set_alloc_cap(int64_t bytes);
+/* The sin and cos the real-time potential step uses for its phase factor, on n device
+ * arguments x_dev (float for GP_C64, double for GP_C128), written to sin_dev and cos_dev
+ * (same type and length; caller-owned device buffers).  Stream-ordered, no sync. */
+int gp_eval_sincos(int32_t precision, const void* x_dev, int64_t n, void* sin_dev, void* cos_dev, void* hip_stream);
+/* Plain device-to-device copy of `bytes` (a multiple of 16; both pointers 16-byte
+ * aligned) with the 16-byte raw buffer loads and stores the sweeps use for their rows: the
+ * practical HBM ceiling the sweep bandwidths are compared with.  Stream-ordered. */
+int gp_stream_copy(const void* src_dev, void* dst_dev, int64_t bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -69,15 +69,22 @@ int gpnn_get_grads(gpnn* m, float* host, int64_t n);
 
 /* Forward pass for n <= max_batch problems.  params_dev: n x 4 FP32 device array of raw
  * (nu_x, nu_y, nu_z, g), nu > 0, g > 0.  out_dev: n x N^3 values, FP32
- * (out_complex64 = 0) or complex64 with zero imaginary part (out_complex64 = 1), laid out
- * as the solver's psi ([x][y][z], z fastest).  The activations are kept for
- * gpnn_loss_backward; out_dev must stay valid until then. */
+ * (out_complex64 = 0), complex64 (1) or complex128 (2) with zero imaginary part, laid out
+ * as the solver's psi ([x][y][z], z fastest), so a complex output can start the solver
+ * in place.  The activations are kept for gpnn_loss_backward / gpnn_backward (FP32
+ * output only); out_dev must stay valid until then. */
 int gpnn_forward(gpnn* m, const float* params_dev, int32_t n, void* out_dev, int32_t out_complex64);
 /* Loss against target_dev (n x N^3 FP32, same layout) for the last forward pass (which
  * must have written FP32 output), and the gradient of the loss with respect to every
  * parameter (overwritten, not accumulated).  loss (nullable, host): the loss;
  * synchronises when given. */
 int gpnn_loss_backward(gpnn* m, const float* target_dev, double* loss);
+/* Backward pass of the last forward pass (which must have written FP32 output) from an
+ * upstream gradient: grad_psi_dev (n x N^3 FP32, the output's layout) holds dL/dpsi for
+ * whatever loss the caller computes.  Every parameter gradient is overwritten (not
+ * accumulated; the caller sums several passes on the host if it needs to).  With
+ * dL/dpsi = 2 (psi - t) dx^3 / n it gives gpnn_loss_backward's gradients.  No sync. */
+int gpnn_backward(gpnn* m, const void* grad_psi_dev);
 /* One Adam update of every parameter with the gradients of the last backward pass;
  * t >= 1 is the update count (bias correction).  Refreshes the BF16 copies. */
 int gpnn_adam_step(gpnn* m, float lr, float beta1, float beta2, float eps, int64_t t);

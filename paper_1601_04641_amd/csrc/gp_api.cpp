@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -63,6 +64,20 @@ void cn_axis_constants(int n, double d, double dt, int mode, int m, bool f32, Ax
   out->omega.resize(nw);
   for (int i = 0; i < nw; ++i) out->omega[i] = beta * w[i];
 }
+
+// per-request cap on the library's own device allocations (gp_set_alloc_cap); < 0: none
+static std::atomic<int64_t> g_alloc_cap{-1};
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+  const int64_t cap = g_alloc_cap.load();
+  if (cap >= 0 && (int64_t)bytes > cap) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+void set_alloc_cap(int64_t bytes) { g_alloc_cap.store(bytes < 0 ? -1 : bytes); }
 
 void pack_complex(const std::vector<std::complex<double>>& v, bool f32, std::vector<unsigned char>& out) {
   if (f32) {
@@ -181,12 +196,18 @@ AxisLines axis_lines(const gp_params& p, int axis) {
 // wavefront addresses its points by 32-bit byte offsets from its first point: its sw*m
 // rows plus the spread of its 64/sw lines (which cross into the next plane of the y
 // sweep) must stay below 2 GiB.
-bool valid_lines(int prec, const AxisLines& a, int m, int sw) {
-  if (!gpk::sweep_lines_supported(prec, m, sw)) return false;
-  if (ceil_div(ceil_div(a.n, m), sw) > 16) return false;
+// Wavefronts whose rows span 2 GiB or more run the 64-bit addressed (WIDE) instances.
+bool needs_wide(const AxisLines& a, int m, int sw) {
   const int64_t lw = 64 / sw;
   const int64_t spread = a.nlines > a.inner ? ((lw - 1) / a.inner + 1) * a.inner * a.n : lw - 1;
-  return (spread + (int64_t)sw * m * a.inner) * (int64_t)a.esize < ((int64_t)1 << 31);
+  return (spread + (int64_t)sw * m * a.inner) * (int64_t)a.esize >= ((int64_t)1 << 31);
+}
+
+bool valid_lines(int prec, const AxisLines& a, int m, int sw) {
+  if (sw < 1 || sw > 8 || m < 1) return false;
+  if (ceil_div(ceil_div(a.n, m), sw) > 16) return false;
+  return needs_wide(a, m, sw) ? gpk::sweep_lines_wide_supported(prec, m, sw)
+                              : gpk::sweep_lines_supported(prec, m, sw);
 }
 
 // Default: 16 points per thread; 4 segments per wavefront once a line has >= 16 segments
@@ -221,13 +242,15 @@ bool pick_lines(int prec, const AxisLines& a, bool nstep, int* m_out, int* sw_ou
 // z sweep grid: the blocks that fit on the device at once (LDS bound: each block holds
 // 4 L lines of nz points), each walking an equal share of the line groups; a second,
 // partial round of blocks would leave most CUs idle at the tail
+int zpad_of(int nz, int seg, int m, size_t esize) { return gpk::z_pad(nz, seg, m, esize, gpk::kMaxLdsBlock); }
+
 int z_grid(const gp_ctx* c, int segz, int mz, int64_t zgroups) {
   int cus = 0, lds_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1) cus = 256;
   if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) != hipSuccess ||
       lds_cu < 65536)
     lds_cu = 65536;
-  const int64_t lds = (int64_t)gpk::z_lds(c->p.nz, segz, mz, gpk::z_pad(c->p.nz, segz, mz, c->esize), c->esize);
+  const int64_t lds = (int64_t)gpk::z_lds(c->p.nz, segz, mz, zpad_of(c->p.nz, segz, mz, c->esize), c->esize) + 512;
   int64_t per_cu = lds_cu / std::max<int64_t>(lds, 1);
   per_cu = std::max<int64_t>(1, std::min<int64_t>(per_cu, 8));
   return (int)std::max<int64_t>(1, std::min<int64_t>(zgroups, per_cu * cus));
@@ -236,9 +259,10 @@ int z_grid(const gp_ctx* c, int segz, int mz, int64_t zgroups) {
 bool valid_z(int nz, int seg, int m, size_t esize) {
   if (seg < 2 || seg > 64 || (seg & (seg - 1)) != 0) return false;
   if (!gpk::sweep_z_supported(esize == 16 ? 1 : 0, m)) return false;
-  if ((size_t)4 * (64 / seg) * nz * esize + 512 > 65536) return false;
+  if ((size_t)4 * (64 / seg) * nz * esize + 512 > gpk::kMaxLdsBlock) return false;
   return (int64_t)seg * m >= nz;  // trailing positions are zero-coefficient padding
 }
+
 
 bool pick_z(int nz, size_t esize, int* seg_out, int* m_out) {
   const int ms[] = {2, 4, 6, 7, 8, 12, 14, 15, 16, 20, 24, 32};
@@ -309,6 +333,7 @@ gpk::SweepLaunch lines_args(gp_ctx* c, int axis, int mode) {
   a.nw = c->nw[mode][axis];
   a.nlines = axis == 0 ? (int64_t)p.ny * p.nz : (int64_t)p.nx * p.nz;
   a.inner = axis == 0 ? (int64_t)p.ny * p.nz : (int64_t)p.nz;
+  a.wide = needs_wide(axis_lines(p, axis), a.m, a.sw);
   a.nstep = 0;
   if (axis == 0) {
     a.nstep = mode == 0 ? 1 : 2;
@@ -351,7 +376,7 @@ gpk::SweepLaunch z_args(gp_ctx* c, int mode) {
   a.st = c->st;
   a.partials = mode == 0 ? c->zpart : nullptr;
   a.grid = c->zgrid;
-  a.zpad = gpk::z_pad(p.nz, a.nseg, a.m, c->esize);
+  a.zpad = zpad_of(p.nz, a.nseg, a.m, c->esize);
   return a;
 }
 
@@ -493,7 +518,7 @@ int observe(gp_ctx* c, double raw[9]) {
 
 template <typename T>
 int dalloc(gp_ctx* c, T** p, size_t bytes) {
-  hipError_t e = hipMalloc((void**)p, bytes);
+  hipError_t e = gpk::dev_alloc((void**)p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
     return fail_hip(c, e, "hipMalloc");
@@ -540,6 +565,20 @@ int check_psi(gp_ctx* c, void* psi) {
   if (reinterpret_cast<uintptr_t>(psi) % c->esize != 0) {
     snprintf(c->err, sizeof(c->err), "psi is not aligned to its complex element size");
     return GP_ERR_INVALID;
+  }
+  // the grid must end inside the device allocation that holds psi (when the runtime
+  // can name that allocation)
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, psi) == hipSuccess && base) {
+    const uintptr_t end = reinterpret_cast<uintptr_t>(base) + size;
+    if (reinterpret_cast<uintptr_t>(psi) + (uintptr_t)c->npts * c->esize > end) {
+      snprintf(c->err, sizeof(c->err), "psi's allocation is smaller than the %lld-point grid",
+               (long long)c->npts);
+      return GP_ERR_INVALID;
+    }
+  } else {
+    (void)hipGetLastError();
   }
   return GP_OK;
 }
@@ -734,24 +773,54 @@ int gp_converge_imag(gp_ctx* c, double tol, int32_t check_every, int64_t max_ste
   if (!c || !(tol > 0) || max_steps < 0) return GP_ERR_INVALID;
   int32_t K = check_every > 0 ? check_every : (int32_t)std::ceil(0.25 / c->p.dt);
   if (K < 1) K = 1;
+  // complex128: the per-check value is the free estimate mu_est = -ln(N_pre)/(2 dt) of the
+  // renormalisation (a 40-byte read instead of an observables pass); when it meets the
+  // stopping rule, mu itself is evaluated now and after one more check interval, and that
+  // change (with the tail the estimate's contraction ratio predicts) must meet tol too.
+  // complex64: mu every check (the FP32 rounding of N_pre makes mu_est too noisy).
+  const bool est = c->p.precision == GP_C128;
+  gpk::StopRule rule;
   int64_t done = 0;
-  double prev = NAN, cur = NAN, e = 0;
-  int32_t conv = 0, hits = 0;
+  double cur = NAN, e = 0;
+  int32_t conv = 0;
+  bool have_mu = false;
+  int rc = GP_OK;
+  auto advance = [&](int64_t* d) {
+    const int32_t n = (int32_t)std::min<int64_t>(K, max_steps - *d);
+    int r2 = gp_step_imag(c, n);
+    *d += n;
+    return r2;
+  };
   while (done < max_steps) {
-    const int32_t n = (int32_t)std::min<int64_t>(K, max_steps - done);
-    int rc = gp_step_imag(c, n);
-    if (rc) return rc;
-    done += n;
-    rc = gp_energy_mu(c, &e, &cur);
-    if (rc) return rc;
-    // two successive checks within tol: one check can straddle a turning point of mu(t)
-    hits = (std::isfinite(prev) && std::fabs(cur - prev) <= tol * std::fabs(cur)) ? hits + 1 : 0;
-    if (hits >= 2) {
+    if ((rc = advance(&done))) return rc;
+    double v = NAN;
+    have_mu = false;
+    if (est) {
+      if ((rc = gp_status(c, nullptr, &v, nullptr))) return rc;
+    } else {
+      if ((rc = gp_energy_mu(c, &e, &cur))) return rc;
+      v = cur;
+      have_mu = true;
+    }
+    if (!rule.update(v, tol)) continue;
+    if (!est) {
       conv = 1;
       break;
     }
-    prev = cur;
+    if ((rc = gp_energy_mu(c, &e, &cur))) return rc;
+    have_mu = true;
+    if (done >= max_steps) break;
+    const double m0 = cur;
+    if ((rc = advance(&done))) return rc;
+    if ((rc = gp_energy_mu(c, &e, &cur))) return rc;
+    const double d = cur - m0, lim = tol * std::fabs(cur);
+    if (std::fabs(d) <= lim && rule.tail(d) <= lim) {
+      conv = 1;
+      break;
+    }
+    rule.reset();  // not yet: monitor again from fresh estimates
   }
+  if (!have_mu && (rc = gp_energy_mu(c, &e, &cur))) return rc;
   if (steps_taken) *steps_taken = done;
   if (mu) *mu = cur;
   if (converged) *converged = conv;
@@ -846,9 +915,16 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
     (void)hipFree(c->zpart);
     c->zpart = np;
   }
+  const int old_zgrid = c->zgrid;
   c->zgrid = zgrid;
   destroy_graphs(c);
-  return build_tables(c);
+  int rc = build_tables(c);
+  if (rc) {  // back to the previous mapping (its tables fit: they were built before)
+    c->map = old;
+    c->zgrid = old_zgrid;
+    (void)build_tables(c);
+  }
+  return rc;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -917,18 +993,26 @@ extern "C" int gp_autotune(gp_ctx* c, int32_t mode, int32_t steps, const char* c
       return GP_OK;
     }
   }
-  // work on the caller's psi, then restore it and the device state
-  void* saved = nullptr;
+  // work on the caller's psi, then restore it, the device state, the step count, the
+  // mapping and the timing switch on every path out
+  int32_t orig[6];
+  gp_get_mapping(c, orig);
+  const bool timing0 = c->timing;
+  const int64_t steps_done = c->steps_done;
   const size_t bytes = (size_t)c->npts * c->esize;
+  void* saved = nullptr;
   int rc = dalloc(c, &saved, bytes);
   if (rc) return rc;
   DevState st0{};
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  HIPCHK(c, hipMemcpy(&st0, c->st, sizeof(st0), hipMemcpyDeviceToHost));
-  HIPCHK(c, hipMemcpyAsync(saved, c->psi, bytes, hipMemcpyDeviceToDevice, c->stream));
-  const int64_t steps_done = c->steps_done;
+  bool have_copy = false;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemcpy(&st0, c->st, sizeof(st0), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpyAsync(saved, c->psi, bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) rc = fail_hip(c, e, "autotune: saving psi");
+  else have_copy = true;
   const int prec = c->p.precision;
-  gp_get_mapping(c, best);
+  for (int q = 0; q < 6; ++q) best[q] = orig[q];
   double best_ms[3] = {1e300, 1e300, 1e300};
   const int ms_lines[] = {8, 10, 12, 16, 30, 32};
   for (int axis = 0; axis < 2 && rc == GP_OK; ++axis) {
@@ -967,18 +1051,49 @@ extern "C" int gp_autotune(gp_ctx* c, int32_t mode, int32_t steps, const char* c
         best[5] = m;
       }
     }
+  // timing off (drops any pending events), then the winner or, on failure, the original
+  (void)gp_set_timing(c, 0);
   if (rc == GP_OK) rc = gp_set_mapping(c, best);
-  // restore psi and state whatever happened
-  (void)hipMemcpyAsync(c->psi, saved, bytes, hipMemcpyDeviceToDevice, c->stream);
-  (void)hipMemcpyAsync(c->st, &st0, sizeof(st0), hipMemcpyHostToDevice, c->stream);
+  if (rc != GP_OK) (void)gp_set_mapping(c, orig);
+  if (have_copy) {
+    (void)hipMemcpyAsync(c->psi, saved, bytes, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(c->st, &st0, sizeof(st0), hipMemcpyHostToDevice, c->stream);
+  }
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(saved);
   c->steps_done = steps_done;
+  (void)gp_set_timing(c, timing0 ? 1 : 0);
   if (rc) return rc;
   cache_store(cache_path, key, best);
   if (map_out)
     for (int q = 0; q < 6; ++q) map_out[q] = best[q];
   return GP_OK;
+}
+
+int gp_set_alloc_cap(int64_t bytes) {
+  gpk::set_alloc_cap(bytes);
+  return GP_OK;
+}
+
+int gp_eval_sincos(int32_t precision, const void* x_dev, int64_t n, void* sin_dev, void* cos_dev, void* hip_stream) {
+  if ((precision != GP_C64 && precision != GP_C128) || n < 0) return GP_ERR_INVALID;
+  if (n == 0) return GP_OK;
+  if (!x_dev || !sin_dev || !cos_dev) return GP_ERR_INVALID;
+  const size_t es = precision == GP_C128 ? 8 : 4;
+  for (const void* q : {x_dev, (const void*)sin_dev, (const void*)cos_dev})
+    if (reinterpret_cast<uintptr_t>(q) % es != 0) return GP_ERR_INVALID;
+  hipError_t e = gpk::launch_eval_sincos(precision, x_dev, n, sin_dev, cos_dev, (hipStream_t)hip_stream);
+  return e == hipSuccess ? GP_OK : GP_ERR_HIP;
+}
+
+int gp_stream_copy(const void* src_dev, void* dst_dev, int64_t bytes, void* hip_stream) {
+  if (bytes < 0 || bytes % 16 != 0) return GP_ERR_INVALID;
+  if (bytes == 0) return GP_OK;
+  if (!src_dev || !dst_dev || reinterpret_cast<uintptr_t>(src_dev) % 16 != 0 ||
+      reinterpret_cast<uintptr_t>(dst_dev) % 16 != 0)
+    return GP_ERR_INVALID;
+  hipError_t e = gpk::launch_stream_copy(src_dev, dst_dev, bytes, (hipStream_t)hip_stream);
+  return e == hipSuccess ? GP_OK : GP_ERR_HIP;
 }
 
 const char* gp_strerror(int code) {

@@ -260,7 +260,7 @@ kb_sweep_yz(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict_
   // plane in: 16-byte units (E values each), 8 loads in flight per thread; a unit never
   // straddles a row when nz is a multiple of E (else the scalar loop)
   constexpr int E = 16 / (int)sizeof(V);
-  const bool vec = (nz % E) == 0 && ((I.off + (int64_t)wk.blk * np) % E) == 0;
+  const bool vec = (nz % E) == 0 && (reinterpret_cast<uintptr_t>(g) & 15) == 0;
   if (vec) {
     const int nu = np / E;
     const uint4* g4 = reinterpret_cast<const uint4*>(g);
@@ -727,7 +727,7 @@ void bfree(gp_batch* b) {
 
 template <typename T>
 int bdalloc(gp_batch* b, T** ptr, size_t bytes) {
-  hipError_t e = hipMalloc((void**)ptr, bytes > 0 ? bytes : 16);
+  hipError_t e = gpk::dev_alloc((void**)ptr, bytes > 0 ? bytes : 16);
   if (e != hipSuccess) {
     *ptr = nullptr;
     return bfail(b, e, "hipMalloc");
@@ -1162,11 +1162,30 @@ int gp_batch_init(const gp_params* p, int32_t n, void* psi_dev, const int64_t* o
   if (!p || n < 1 || !psi_dev || !offsets) return GP_ERR_INVALID;
   const int prec = p[0].precision;
   if (prec != GP_C64 && prec != GP_C128) return GP_ERR_INVALID;
+  const int64_t es = prec == GP_C128 ? 16 : 8;
+  if (reinterpret_cast<uintptr_t>(psi_dev) % (uintptr_t)es != 0) return GP_ERR_INVALID;
   for (int i = 0; i < n; ++i) {
     if (bad_inst(p[i]) || p[i].precision != prec || p[i].split != p[0].split) return GP_ERR_INVALID;
     if (offsets[i] < 0) return GP_ERR_INVALID;
-    if ((int64_t)p[i].nx * p[i].ny * p[i].nz * (prec == GP_C128 ? 16 : 8) >= (int64_t)1 << 32)
-      return GP_ERR_UNSUPPORTED;
+    if ((int64_t)p[i].nx * p[i].ny * p[i].nz * es >= (int64_t)1 << 32) return GP_ERR_UNSUPPORTED;
+  }
+  // instance regions [off, off + size) must not overlap, and must lie inside the device
+  // allocation that holds psi_dev (when the runtime can name it)
+  {
+    std::vector<std::pair<int64_t, int64_t>> reg(n);
+    for (int i = 0; i < n; ++i) reg[i] = {offsets[i], offsets[i] + (int64_t)p[i].nx * p[i].ny * p[i].nz};
+    std::sort(reg.begin(), reg.end());
+    for (int i = 1; i < n; ++i)
+      if (reg[i].first < reg[i - 1].second) return GP_ERR_INVALID;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, psi_dev) == hipSuccess && base) {
+      const uintptr_t end = reinterpret_cast<uintptr_t>(base) + size;
+      const uintptr_t last = reinterpret_cast<uintptr_t>(psi_dev) + (uintptr_t)(reg[n - 1].second * es);
+      if (last > end) return GP_ERR_INVALID;
+    } else {
+      (void)hipGetLastError();
+    }
   }
   gp_batch* b = new (std::nothrow) gp_batch;
   if (!b) return GP_ERR_OOM;
@@ -1362,10 +1381,11 @@ int gp_batch_converge_imag(gp_batch* b, double tol, int32_t check_every, int64_t
     K = std::max(1, (int32_t)std::ceil(0.25 / dtmin));
   }
   const int n = b->n;
-  std::vector<double> prev(n, NAN), cur(n, NAN), e(n);
+  std::vector<double> cur(n, NAN), e(n);
   std::vector<uint8_t> act(n, 1);
   std::vector<int64_t> taken(n, 0);
-  std::vector<int32_t> conv(n, 0), hits(n, 0);
+  std::vector<int32_t> conv(n, 0);
+  std::vector<gpk::StopRule> rule(n);
   int rc = bset_active(b, act.data());
   if (rc) return rc;
   int64_t done = 0;
@@ -1381,9 +1401,8 @@ int gp_batch_converge_imag(gp_batch* b, double tol, int32_t check_every, int64_t
     rc = GP_OK;
     for (int i = 0; i < n; ++i) {
       if (!act[i]) continue;
-      // two successive checks within tol (as gp_converge_imag)
-      hits[i] = (std::isfinite(prev[i]) && std::fabs(cur[i] - prev[i]) <= tol * std::fabs(cur[i])) ? hits[i] + 1 : 0;
-      if (hits[i] >= 2) {
+      // the stopping rule of gp_converge_imag on mu of every check
+      if (rule[i].update(cur[i], tol)) {
         conv[i] = 1;
         act[i] = 0;
         --remaining;
@@ -1391,7 +1410,6 @@ int gp_batch_converge_imag(gp_batch* b, double tol, int32_t check_every, int64_t
         act[i] = 0;  // diverged: stop it, report not converged
         --remaining;
       }
-      prev[i] = cur[i];
     }
   }
   std::vector<uint8_t> all(n, 1);
@@ -1472,8 +1490,75 @@ int gp_batch_get_timing(gp_batch* b, double ms_mean[5], int64_t launches[5]) {
   return GP_OK;
 }
 
-int gp_batch_autotune(gp_batch* b, int32_t mode, int32_t steps, int32_t map_out[5]) {
+}  // extern "C"
+
+namespace {
+
+// Autotuner cache key of a batch: FNV-1a over the instances' grid sizes, in order, with
+// the instance count, precision, splitting and step kind beside it.
+uint64_t batch_key(const gp_batch* b) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int q = 0; q < 8; ++q) {
+      h ^= (uint64_t)((v >> (8 * q)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  for (const gp_params& p : b->p) {
+    mix(p.nx);
+    mix(p.ny);
+    mix(p.nz);
+  }
+  return h;
+}
+
+bool bcache_lookup(const char* path, const gp_batch* b, int mode, int32_t map[5], int* fuse) {
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  const unsigned long long key = batch_key(b);
+  char line[256];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    unsigned long long k = 0;
+    int n = 0, prec = 0, split = 0, md = 0, m[5], fz = 0;
+    if (sscanf(line, "gfx950-batch %llx %d %d %d %d : %d %d %d %d %d %d", &k, &n, &prec, &split, &md, &m[0], &m[1],
+               &m[2], &m[3], &m[4], &fz) == 11 &&
+        k == key && n == b->n && prec == b->prec && split == b->p[0].split && md == mode) {
+      for (int q = 0; q < 5; ++q) map[q] = m[q];
+      *fuse = fz;
+      found = true;  // the last matching entry wins
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void bcache_store(const char* path, const gp_batch* b, int mode, const int32_t map[5], int fuse) {
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "gfx950-batch %llx %d %d %d %d : %d %d %d %d %d %d\n", (unsigned long long)batch_key(b), b->n, b->prec,
+          b->p[0].split, mode, map[0], map[1], map[2], map[3], map[4], fuse);
+  fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+int gp_batch_autotune(gp_batch* b, int32_t mode, int32_t steps, const char* cache_path, int32_t map_out[5]) {
   if (!b || (mode != 0 && mode != 1) || steps < 1) return GP_ERR_INVALID;
+  {
+    int32_t cm[5];
+    int cf = 0;
+    if (bcache_lookup(cache_path, b, mode, cm, &cf) && gp_batch_set_mapping(b, cm) == GP_OK &&
+        gp_batch_set_yz_fusion(b, cf) == GP_OK) {
+      if (map_out)
+        for (int q = 0; q < 5; ++q) map_out[q] = b->map[q];
+      return GP_OK;
+    }
+  }
   // tune on a copy of psi; restore psi, state and step counts afterwards
   int64_t total = 0;
   for (int i = 0; i < b->n; ++i)
@@ -1483,9 +1568,15 @@ int gp_batch_autotune(gp_batch* b, int32_t mode, int32_t steps, int32_t map_out[
   int rc = bdalloc(b, &saved, bytes);
   if (rc) return rc;
   std::vector<DevState> st0(b->n);
-  BCHK(b, hipStreamSynchronize(b->stream));
-  BCHK(b, hipMemcpy(st0.data(), b->st, b->n * sizeof(DevState), hipMemcpyDeviceToHost));
-  BCHK(b, hipMemcpy(saved, b->psi, bytes, hipMemcpyDeviceToDevice));
+  {
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipMemcpy(st0.data(), b->st, b->n * sizeof(DevState), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(saved, b->psi, bytes, hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(saved);
+      return bfail(b, e, "autotune: saving psi");
+    }
+  }
   const std::vector<int64_t> steps0 = b->steps;
   int best[5];
   for (int q = 0; q < 5; ++q) best[q] = b->map[q];
@@ -1569,6 +1660,7 @@ int gp_batch_autotune(gp_batch* b, int32_t mode, int32_t steps, int32_t map_out[
   (void)hipFree(saved);
   b->steps = steps0;
   if (rc) return rc;
+  bcache_store(cache_path, b, mode, best, b->yz_fuse);
   if (map_out)
     for (int q = 0; q < 5; ++q) map_out[q] = best[q];
   return GP_OK;

@@ -230,9 +230,11 @@ template <typename R> struct Pot1D {
 // Each wavefront addresses psi from its own first point (first line of the block, first
 // segment of the wavefront: the smallest element index any of its lanes touches), so the
 // 32-bit byte offsets span only the wavefront's own rows and lines, whatever the size of
-// psi; the host keeps that span below 2 GiB.
+// psi; the host keeps that span below 2 GiB.  WIDE instances (for wavefronts whose rows
+// span more, e.g. complex128 x lines of the paper's 1920x1600x1280 grid: 128 rows of
+// 32.8 MB) address every point with a 64-bit pointer instead.
 // ---------------------------------------------------------------------------------------
-template <typename R, int M, int SW, bool CC, int NSTEP>
+template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE = false>
 __device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ psi, int64_t psi_bytes,
                                            typename VecOf<R>::T ca, typename VecOf<R>::T cb,
                                            typename VecOf<R>::T cbl, typename VecOf<R>::T cP,
@@ -267,11 +269,15 @@ __device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ ps
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(psi + e0, (uint32_t)min(left_bytes, (int64_t)0xffffffff));
   const uint32_t voff = (uint32_t)((base + (int64_t)s * inner - e0) * (int64_t)sizeof(V));
   const uint32_t srow = (uint32_t)(inner * (int64_t)sizeof(V));
+  V* const lp = psi + base + (int64_t)s * inner;  // WIDE: this lane's first point
   V v[M];
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     v[t] = vzero<V>();
-    if (t < len) bload(v[t], rs, voff, (uint32_t)t * srow);
+    if (t < len) {
+      if (WIDE) v[t] = lp[(int64_t)t * inner];
+      else bload(v[t], rs, voff, (uint32_t)t * srow);
+    }
   }
   if (NSTEP != 0) {
     const R vyz = vy[line / nz] + vz[line % nz];  // x-sweep line index = j*nz + k
@@ -354,7 +360,19 @@ __device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ ps
 
 #pragma unroll
   for (int t = 0; t < M; ++t)
-    if (t < len) bstore(v[t], rs, voff, (uint32_t)t * srow);
+    if (t < len) {
+      if (WIDE) lp[(int64_t)t * inner] = v[t];
+      else bstore(v[t], rs, voff, (uint32_t)t * srow);
+    }
+}
+
+// Line bundle of block b when blocks are dealt to the XCDs round-robin (block b runs on
+// XCD b mod 8): XCD x takes one contiguous stretch of bundles, so the blocks resident on
+// one XCD (sharing its L2 and address-translation caches) read adjacent row chunks
+// instead of chunks eight bundles apart.  A bijection of [0, nb).
+__device__ __forceinline__ int64_t xcd_bundle(int64_t b, int64_t nb) {
+  const int64_t x = b & 7, k = b >> 3, per = nb >> 3, rem = nb & 7;
+  return x * per + min(x, rem) + k;
 }
 
 // Sherman-Morrison head correction u_i += omega_i u_0, i < nw, one thread per line, for
@@ -411,7 +429,10 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
   // this thread's copy positions advance by 256 points (or pairs) per iteration: their
   // (line, point) digits advance by the step's own digits with one carry
   const int half = nz >> 1;
-  const bool pairs = sizeof(V) == 8 && (nz & 1) == 0;  // with zp = 1 (MZ even)
+  // 16-byte copies need a 16-byte aligned grid base (a batched instance may start at any
+  // complex64 element); otherwise every copy moves one 8-byte value
+  const bool al16 = (reinterpret_cast<uintptr_t>(psi) & 15) == 0;
+  const bool pairs = sizeof(V) == 8 && (nz & 1) == 0 && al16;  // with zp = 1 (MZ even)
   const int cn = pairs ? half : nz;
   const int dl = 256 / cn, dq = 256 % cn;
 
@@ -421,7 +442,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
     const int cnt = nl * nz;
     const V* src = psi + line0 * nz;
     if (zp == 0) {
-      if (sizeof(V) == 8 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {  // 16-byte copies
+      if (sizeof(V) == 8 && al16 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {  // 16-byte copies
         const float4* s4 = reinterpret_cast<const float4*>(src);
         float4* d4 = reinterpret_cast<float4*>(sdata);
         for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];
@@ -567,7 +588,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
     __syncthreads();
     V* dst = psi + line0 * nz;
     if (zp == 0) {
-      if (sizeof(V) == 8 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {
+      if (sizeof(V) == 8 && al16 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {
         float4* d4 = reinterpret_cast<float4*>(dst);
         const float4* s4 = reinterpret_cast<const float4*>(sdata);
         for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];

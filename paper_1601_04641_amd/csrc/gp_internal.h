@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <cmath>
 #include <complex>
 #include <vector>
 
@@ -36,9 +38,16 @@ __host__ __device__ inline int z_pitch(int nz, int mz, int zpad) { return nz + z
 inline size_t z_lds(int nz, int seg, int mz, int zpad, size_t esize) {
   return (size_t)4 * (64 / seg) * (size_t)z_pitch(nz, mz, zpad) * esize;
 }
-inline int z_pad(int nz, int seg, int mz, size_t esize) {
-  return (mz % 4 == 0 && z_lds(nz, seg, mz, 1, esize) + 512 <= 65536) ? 1 : 0;
+// Blocks whose packed rows already need more than 64 KiB (complex128 lines beyond 1016
+// points, complex64 beyond 2032) take the padded layout whenever it fits max_lds.
+inline int z_pad(int nz, int seg, int mz, size_t esize, size_t max_lds = 65536) {
+  if (mz % 4 != 0) return 0;
+  const size_t packed = z_lds(nz, seg, mz, 0, esize) + 512, padded = z_lds(nz, seg, mz, 1, esize) + 512;
+  if (padded <= 65536) return 1;
+  return (packed > 65536 && padded <= max_lds) ? 1 : 0;
 }
+// LDS one workgroup may hold on gfx950 (160 KiB); z blocks above 64 KiB opt in per kernel
+constexpr size_t kMaxLdsBlock = 163840;
 
 struct SweepLaunch {
   void* psi;
@@ -52,6 +61,7 @@ struct SweepLaunch {
   int64_t nlines;   // number of lines
   int64_t inner;    // x sweep: ny*nz; y sweep: nz (line l -> base (l/inner)*n*inner + l%inner)
   int sw;           // segments per wavefront (x/y kernels)
+  bool wide;        // x/y kernels: 64-bit addressing (a wavefront's rows span >= 2 GiB)
   // potential step fused into the load (x sweep) or store (z sweep, Strang)
   double ph, pc, pd;  // potential of the swept axis: V(i) = ph ((i - pc) pd)^2
   int nstep;        // 0 none, 1 imaginary, 2 real
@@ -101,8 +111,66 @@ struct AxisConst {
 void cn_axis_constants(int n, double d, double dt, int mode, int m, bool f32, AxisConst* out);
 void pack_complex(const std::vector<std::complex<double>>& v, bool f32, std::vector<unsigned char>& out);
 
+// Device allocation of the library's own buffers (contexts, batches, networks).  Fails
+// with hipErrorOutOfMemory, without calling the runtime, when a cap set by
+// gp_set_alloc_cap is exceeded by this one request.
+hipError_t dev_alloc(void** p, size_t bytes);
+void set_alloc_cap(int64_t bytes);
+
+// Device sin/cos of the real-time phase factor on n arguments (gp_eval_sincos)
+hipError_t launch_eval_sincos(int precision, const void* x, int64_t n, void* s, void* c, hipStream_t st);
+// Plain streaming copy with 16-byte buffer loads and stores (gp_stream_copy)
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
+// raw observable sums -> the scaled raw[9] of gp_raw_sums, on the device
+hipError_t launch_obs_scale(const double* sums, double* raw, double dV, const double d2[3], hipStream_t st);
+
+// Stopping rule of the imaginary-time convergence loops, fed one value (mu) per check.
+// delta_n = mu_n - mu_{n-1}.  While two successive deltas have the same sign and shrink
+// (r = delta_n / delta_{n-1} in (0, 1): mu approaches its limit geometrically), the
+// distance of mu_n to that limit is estimated as |delta_n| r / (1 - r) (Aitken's
+// extrapolation) and must be at most tol |mu_n|, as must |delta_n|.  Otherwise (mu turning,
+// or at its rounding floor) |delta_n| <= tol |mu_n| must hold at two successive checks.
+struct StopRule {
+  double prev = NAN, prev2 = NAN;
+  double r = -1.0;  // last contraction ratio (-1: none, or not in (0, 1))
+  int hits = 0;
+  void reset() {
+    prev = prev2 = NAN;
+    r = -1.0;
+    hits = 0;
+  }
+  // distance to the limit that the ratio r predicts for a change d (0 outside (0, 1))
+  double tail(double d) const { return (r > 0.0 && r < 1.0) ? std::fabs(d) * r / (1.0 - r) : 0.0; }
+  bool update(double cur, double tol) {
+    bool done = false;
+    if (std::isfinite(prev) && std::isfinite(cur)) {
+      const double d1 = cur - prev, lim = tol * std::fabs(cur);
+      const bool small = std::fabs(d1) <= lim;
+      hits = small ? hits + 1 : 0;
+      r = -1.0;
+      if (std::isfinite(prev2)) {
+        const double d0 = prev - prev2;
+        const double q = d0 != 0.0 ? d1 / d0 : -1.0;
+        if (q > 0.0 && q < 1.0) {
+          r = q;
+          done = small && tail(d1) <= lim;
+        } else {
+          done = hits >= 2;
+        }
+      }
+    } else {
+      hits = 0;
+      r = -1.0;
+    }
+    prev2 = prev;
+    prev = cur;
+    return done;
+  }
+};
+
 // Supported line mappings (x/y kernels: points per thread and segments per wavefront)
 bool sweep_lines_supported(int precision, int m, int sw);
+bool sweep_lines_wide_supported(int precision, int m, int sw);
 bool sweep_z_supported(int precision, int mz);
 
 }  // namespace gpk

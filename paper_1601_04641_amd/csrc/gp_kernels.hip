@@ -31,12 +31,18 @@
 // segment held in registers, so psi is read once and written once per sweep.
 #include "gp_device.h"
 
+#include <algorithm>
+
 namespace gpk {
 
 // ---------------------------------------------------------------------------------------
 // single-grid kernels (bodies in gp_device.h)
 // ---------------------------------------------------------------------------------------
-template <typename R, int M, int SW, bool CC, int NSTEP>
+#ifndef GP_XCD_REMAP
+#define GP_XCD_REMAP 1
+#endif
+
+template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE>
 __global__ void __launch_bounds__(1024)
 k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, int64_t psi_bytes, typename VecOf<R>::T ca,
               typename VecOf<R>::T cb, typename VecOf<R>::T cbl, typename VecOf<R>::T cP,
@@ -49,8 +55,9 @@ k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, int64_t psi_bytes, typenam
     scale = (R)st->s;
     g = (R)st->g;
   }
-  lines_body<R, M, SW, CC, NSTEP>(psi, psi_bytes, ca, cb, cbl, cP, omega, nwi, n, nseg, nlines, inner, px, vy, vz,
-                                  nz, tau, scale, g, blockIdx.x, smem_raw);
+  const int64_t b = GP_XCD_REMAP ? xcd_bundle(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  lines_body<R, M, SW, CC, NSTEP, WIDE>(psi, psi_bytes, ca, cb, cbl, cP, omega, nwi, n, nseg, nlines, inner, px, vy,
+                                        vz, nz, tau, scale, g, b, smem_raw);
 }
 
 template <typename R, int MZ, bool CC, bool NORM, int EPI>
@@ -165,6 +172,55 @@ __global__ void __launch_bounds__(256) k_obs_final(const double* __restrict__ pa
   }
 }
 
+// raw sums -> the scaled values of gp_raw_sums: N, kinetic link sums x 1/(2 d^2), U, I and
+// the second moments, each times dV (the host formulas, same operations and order)
+__global__ void k_obs_scale(const double* __restrict__ sums, double* __restrict__ raw, double dV, double d2x,
+                            double d2y, double d2z) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double d2[3] = {d2x, d2y, d2z};
+  raw[0] = __dmul_rn(sums[0], dV);
+  for (int a = 0; a < 3; ++a) raw[1 + a] = __ddiv_rn(__dmul_rn(__dmul_rn(0.5, sums[1 + a]), dV), d2[a]);
+  for (int q = 4; q < 9; ++q) raw[q] = __dmul_rn(sums[q], dV);
+}
+
+// the real-time phase factor's sin and cos on given arguments (error-bound checks)
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_eval_sincos(const R* __restrict__ x, int64_t n, R* __restrict__ sn, R* __restrict__ cs) {
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
+    R s, c;
+    dsincos(x[q], &s, &c);
+    sn[q] = s;
+    cs[q] = c;
+  }
+}
+
+// Streaming copy of 16-byte units with raw buffer loads and stores, the access width of
+// the sweeps' row loads: a block moves kCopyU x 256 consecutive units per iteration (all
+// loads issued before the stores), walking the array with a grid stride.  The resource
+// of each chunk starts at the chunk, so 32-bit offsets cover any array size.
+constexpr int kCopyU = 4;
+__global__ void __launch_bounds__(256)
+k_stream_copy(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int64_t nunits) {
+  constexpr int64_t chunk = 256 * kCopyU;
+  for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < nunits; c0 += (int64_t)gridDim.x * chunk) {
+    const int64_t left = min(nunits - c0, chunk);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src + c0 * 16, (uint32_t)(left * 16));
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst + c0 * 16, (uint32_t)(left * 16));
+    u32x4 v[kCopyU];
+#pragma unroll
+    for (int u = 0; u < kCopyU; ++u) {
+      const int i = (int)threadIdx.x + u * 256;
+      if (i < left) v[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, i * 16, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyU; ++u) {
+      const int i = (int)threadIdx.x + u * 256;
+      if (i < left) __builtin_amdgcn_raw_buffer_store_b128(v[u], rd, i * 16, 0, 0);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
@@ -175,7 +231,7 @@ template <typename R> static typename VecOf<R>::T cval(const double* c) {
   return v;
 }
 
-template <typename R, int M, int SW, bool CC, int NSTEP>
+template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE>
 static hipError_t go_lines(const SweepLaunch& a, hipStream_t s) {
   typedef typename VecOf<R>::T V;
   constexpr int LW = 64 / SW;
@@ -183,7 +239,7 @@ static hipError_t go_lines(const SweepLaunch& a, hipStream_t s) {
   const size_t lds = (size_t)3 * waves * SW * LW * sizeof(V);
   const int64_t blocks = (a.nlines + LW - 1) / LW;
   const int nwi = (a.nw <= M) ? a.nw : 0;
-  hipLaunchKernelGGL((k_sweep_lines<R, M, SW, CC, NSTEP>), dim3((unsigned)blocks), dim3(waves * 64), lds, s,
+  hipLaunchKernelGGL((k_sweep_lines<R, M, SW, CC, NSTEP, WIDE>), dim3((unsigned)blocks), dim3(waves * 64), lds, s,
                      (V*)a.psi, a.psi_bytes, cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4),
                      cval<R>(a.coef + 6), (const V*)a.omega, nwi, a.n, a.nseg, a.nlines, a.inner,
                      Pot1D<R>{(R)a.ph, (R)a.pc, (R)a.pd}, (const R*)a.vy, (const R*)a.vz, a.nz, (R)a.tau, a.st);
@@ -195,10 +251,10 @@ static hipError_t go_lines(const SweepLaunch& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename R, int M, int SW>
+template <typename R, int M, int SW, bool WIDE = false>
 static hipError_t go_lines_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
-  if (!cc) return a.nstep ? go_lines<R, M, SW, false, 1>(a, s) : go_lines<R, M, SW, false, 0>(a, s);
-  return a.nstep ? go_lines<R, M, SW, true, 2>(a, s) : go_lines<R, M, SW, true, 0>(a, s);
+  if (!cc) return a.nstep ? go_lines<R, M, SW, false, 1, WIDE>(a, s) : go_lines<R, M, SW, false, 0, WIDE>(a, s);
+  return a.nstep ? go_lines<R, M, SW, true, 2, WIDE>(a, s) : go_lines<R, M, SW, true, 0, WIDE>(a, s);
 }
 
 // Instances: complex64 M in {8, 10, 12, 16, 32}, complex128 M in {8, 16} (32 complex
@@ -206,7 +262,7 @@ static hipError_t go_lines_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
 // {1, 2, 4}, and SW = 8 with complex64 M = 16, SW = 4 with complex64 M = 30.  M = 10 and 12 keep the real-time x sweep (with the phase factor) at <= 64
 // VGPRs, i.e. 8 waves per SIMD, where M = 16 needs 80 (6 waves).
 bool sweep_lines_supported(int precision, int m, int sw) {
-  if (sw == 8) return precision == 0 && m == 16;  // lines of up to 2048 points without M = 32's spills
+  if (sw == 8) return m == 16;  // lines of up to 2048 points (complex64 without M = 32's spills)
   if (m == 30) return precision == 0 && sw == 4;  // 1920-point lines in 16 wavefronts, 128-byte line chunks
   if (sw != 1 && sw != 2 && sw != 4) return false;
   if (precision == 0) return m == 8 || m == 10 || m == 12 || m == 16 || m == 32;
@@ -220,7 +276,28 @@ bool sweep_lines_supported(int precision, int m, int sw) {
     if (a.sw == 4) return go_lines_mode<R, M, 4>(cc, a, s);                 \
   } while (0)
 
+// 64-bit addressed instances: the mappings that cover lines of 513-2048 points (and
+// complex128 lines of up to 1024 with 8 points per thread) on grids whose planes are so
+// large that a wavefront's rows span 2 GiB or more
+bool sweep_lines_wide_supported(int precision, int m, int sw) {
+  if (precision == 0) return (m == 16 && (sw == 4 || sw == 8)) || ((m == 30 || m == 32) && sw == 4);
+  return (m == 16 && (sw == 4 || sw == 8)) || (m == 8 && sw == 4);
+}
+
 hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipStream_t s) {
+  if (a.wide) {
+    if (precision == 0) {
+      if (a.m == 16 && a.sw == 4) return go_lines_mode<float, 16, 4, true>(cc, a, s);
+      if (a.m == 16 && a.sw == 8) return go_lines_mode<float, 16, 8, true>(cc, a, s);
+      if (a.m == 30 && a.sw == 4) return go_lines_mode<float, 30, 4, true>(cc, a, s);
+      if (a.m == 32 && a.sw == 4) return go_lines_mode<float, 32, 4, true>(cc, a, s);
+    } else {
+      if (a.m == 16 && a.sw == 4) return go_lines_mode<double, 16, 4, true>(cc, a, s);
+      if (a.m == 16 && a.sw == 8) return go_lines_mode<double, 16, 8, true>(cc, a, s);
+      if (a.m == 8 && a.sw == 4) return go_lines_mode<double, 8, 4, true>(cc, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (precision == 0) {
     if (a.m == 8) GP_LINES_SW(float, 8);
     if (a.m == 16 && a.sw == 8) return go_lines_mode<float, 16, 8>(cc, a, s);
@@ -230,6 +307,7 @@ hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipS
     if (a.m == 10) GP_LINES_SW(float, 10);
     if (a.m == 32) GP_LINES_SW(float, 32);
   } else {
+    if (a.m == 16 && a.sw == 8) return go_lines_mode<double, 16, 8>(cc, a, s);
     if (a.m == 8) GP_LINES_SW(double, 8);
     if (a.m == 16) GP_LINES_SW(double, 16);
   }
@@ -242,6 +320,15 @@ static hipError_t go_z(const SweepLaunch& a, hipStream_t s) {
   typedef typename VecOf<R>::T V;
   const int zpad = (MZ % 2 == 0) ? a.zpad : 0;
   const size_t lds = z_lds(a.nz, a.nseg, MZ, zpad, sizeof(V));
+  if (lds > 65536 - 512) {  // more than the default 64 KiB per block: opt in (up to 160 KiB)
+    static size_t granted = 0;
+    if (lds > granted) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_sweep_z<R, MZ, CC, NORM, EPI>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      granted = lds;
+    }
+  }
   hipLaunchKernelGGL((k_sweep_z<R, MZ, CC, NORM, EPI>), dim3(a.grid), dim3(256), lds, s, (V*)a.psi,
                      cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4), cval<R>(a.coef + 6),
                      (const V*)a.omega, a.nw, a.nz, a.nseg, a.nlines, a.partials, (const R*)a.vx, (const R*)a.vy,
@@ -257,13 +344,14 @@ static hipError_t go_z_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
   return a.nstep ? go_z<R, MZ, true, false, 2>(a, s) : go_z<R, MZ, true, false, 0>(a, s);
 }
 
-// z instances: points per thread MZ in {2, 4, 6, 7, 8, 12, 14, 16}; complex64 also
-// {20, 24, 32} for lines longer than 1024 points (64 segments; the block's 4 lines of a
-// complex128 line that long would not fit 64 KiB of LDS) and 15 (960 = 64 x 15 with
-// packed, conflict-free LDS rows and 5 blocks per CU)
+// z instances: points per thread MZ in {2, 4, 6, 7, 8, 12, 14, 16}, {20, 24, 32} for
+// lines longer than 1024 points (64 segments; complex128 blocks of such lines hold more
+// than 64 KiB of LDS and opt in to up to 160 KiB) and 15 (960 = 64 x 15 with packed,
+// conflict-free LDS rows and 5 complex64 blocks per CU)
 bool sweep_z_supported(int precision, int mz) {
-  if (precision == 0 && (mz == 15 || mz == 20 || mz == 24 || mz == 32)) return true;
-  return mz == 2 || mz == 4 || mz == 6 || mz == 7 || mz == 8 || mz == 12 || mz == 14 || mz == 16;
+  (void)precision;
+  return mz == 2 || mz == 4 || mz == 6 || mz == 7 || mz == 8 || mz == 12 || mz == 14 || mz == 15 || mz == 16 ||
+         mz == 20 || mz == 24 || mz == 32;
 }
 
 #define GP_Z_M(R)                                              \
@@ -289,6 +377,10 @@ hipError_t launch_sweep_z(int precision, bool cc, const SweepLaunch& a, hipStrea
     if (a.m == 32) return go_z_mode<float, 32>(cc, a, s);
     GP_Z_M(float);
   }
+  if (a.m == 15) return go_z_mode<double, 15>(cc, a, s);
+  if (a.m == 20) return go_z_mode<double, 20>(cc, a, s);
+  if (a.m == 24) return go_z_mode<double, 24>(cc, a, s);
+  if (a.m == 32) return go_z_mode<double, 32>(cc, a, s);
   GP_Z_M(double);
 }
 #undef GP_Z_M
@@ -309,6 +401,36 @@ hipError_t launch_scale(int precision, void* psi, int64_t n, DevState* st, hipSt
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reset_scale, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_scale(const double* sums, double* raw, double dV, const double d2[3], hipStream_t s) {
+  hipLaunchKernelGGL(k_obs_scale, dim3(1), dim3(64), 0, s, sums, raw, dV, d2[0], d2[1], d2[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_sincos(int precision, const void* x, int64_t n, void* sn, void* cs, hipStream_t s) {
+  const int64_t want = (n + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+  if (precision == 0)
+    hipLaunchKernelGGL(k_eval_sincos<float>, dim3(blocks), dim3(256), 0, s, (const float*)x, n, (float*)sn,
+                       (float*)cs);
+  else
+    hipLaunchKernelGGL(k_eval_sincos<double>, dim3(blocks), dim3(256), 0, s, (const double*)x, n, (double*)sn,
+                       (double*)cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+  const int64_t units = bytes / 16;
+  const int64_t chunks = (units + 256 * kCopyU - 1) / (256 * kCopyU);
+  int cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)cus * 16));
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)grid), dim3(256), 0, s, (const unsigned char*)src,
+                     (unsigned char*)dst, units);
   return hipGetLastError();
 }
 

@@ -24,6 +24,8 @@
 #include <string>
 #include <vector>
 
+#include "gp_internal.h"
+
 namespace nn {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -935,14 +937,17 @@ k_head_fwd(const uint16_t* __restrict__ aL, int64_t P, int N, int C, const float
   }
   f += log_prior(prm, s, i, j, k, N, dx);
   const float psi = __expf(fminf(f, kFMax));
-  if (cplx) reinterpret_cast<float2*>(out)[p] = make_float2(psi, 0.0f);
+  if (cplx == 2) reinterpret_cast<double2*>(out)[p] = make_double2((double)psi, 0.0);
+  else if (cplx) reinterpret_cast<float2*>(out)[p] = make_float2(psi, 0.0f);
   else reinterpret_cast<float*>(out)[p] = psi;
 }
 
 // loss and the head's backward: df = dL/dpsi * psi (zero where clamped);
 // dh[p][c] = df wh[c] silu'(pre[p][c]); per-block partials of sum (psi - t)^2, of
 // df a[p][c] and of df (wave shuffles, then the 4 waves in fixed order).
-template <int C>
+// LOSS: dL/dpsi = 2 (psi - t) scale from the target (t = tgt); otherwise dL/dpsi is
+// given per point (tgt holds it) and the loss partials are zero.
+template <int C, bool LOSS>
 __global__ void __launch_bounds__(256)
 k_head_bwd(const float* __restrict__ psi, const float* __restrict__ tgt, const uint16_t* __restrict__ aL,
            const uint16_t* __restrict__ preL, int64_t P, const float* __restrict__ whb, float scale,
@@ -956,9 +961,14 @@ k_head_bwd(const float* __restrict__ psi, const float* __restrict__ tgt, const u
   float ga[C];
   const bool pv = p < P;
   if (pv) {
-    const float ps = psi[p], d = ps - tgt[p];
-    d2 = (double)d * (double)d;
-    df = ps < __expf(kFMax) ? 2.0f * d * scale * ps : 0.0f;
+    const float ps = psi[p];
+    if (LOSS) {
+      const float d = ps - tgt[p];
+      d2 = (double)d * (double)d;
+      df = ps < __expf(kFMax) ? 2.0f * d * scale * ps : 0.0f;
+    } else {
+      df = ps < __expf(kFMax) ? tgt[p] * ps : 0.0f;
+    }
   }
 #pragma unroll
   for (int c8 = 0; c8 < C; c8 += 8) {
@@ -1293,7 +1303,7 @@ int hip_chk(gpnn* m, hipError_t e, const char* what) {
 
 template <typename T> int alloc(gpnn* m, T** p, int64_t count) {
   void* q = nullptr;
-  if (hipMalloc(&q, (size_t)count * sizeof(T)) != hipSuccess) {
+  if (gpk::dev_alloc(&q, (size_t)count * sizeof(T)) != hipSuccess) {
     (void)hipGetLastError();
     return set_err(m, GPNN_ERR_OOM, "device allocation failed");
   }
@@ -1444,6 +1454,7 @@ int gpnn_get_grads(gpnn* m, float* host, int64_t n) { return m ? get_vec(m, m->g
 
 int gpnn_forward(gpnn* m, const float* prm, int32_t n, void* out, int32_t out_complex64) {
   if (!m || !prm || !out || n < 1 || n > m->a.max_batch) return set_err(m, GPNN_ERR_INVALID, "bad forward arguments");
+  if (out_complex64 < 0 || out_complex64 > 2) return set_err(m, GPNN_ERR_INVALID, "bad output kind");
   const gpnn_arch& a = m->a;
   hipStream_t st = m->st;
   hipLaunchKernelGGL(k_features, dim3(nblk((int64_t)n * 32)), dim3(256), 0, st, prm, n, m->ms, m->z0);
@@ -1470,20 +1481,24 @@ int gpnn_forward(gpnn* m, const float* prm, int32_t n, void* out, int32_t out_co
   if (e == hipSuccess) {
     const int64_t P = (int64_t)n * vol(m->N);
     hipLaunchKernelGGL(k_head_fwd, dim3(nblk(P)), dim3(256), 0, st, prev, P, m->N, a.ch[m->S], m->w + m->owh, prm,
-                       (float)a.dx, out, out_complex64 ? 1 : 0);
+                       (float)a.dx, out, out_complex64);
     e = hipGetLastError();
   }
   if (e != hipSuccess) return hip_chk(m, e, "forward");
   m->n = n;
   m->prm = prm;
   m->out = out;
-  m->out_cplx = out_complex64 ? 1 : 0;
+  m->out_cplx = out_complex64;
   return GPNN_OK;
 }
 
-int gpnn_loss_backward(gpnn* m, const float* tgt, double* loss) {
-  if (!m || !tgt) return set_err(m, GPNN_ERR_INVALID, "bad backward arguments");
-  if (m->n < 1 || m->out_cplx) return set_err(m, GPNN_ERR_STATE, "no FP32 forward pass to differentiate");
+}  // extern "C"
+
+namespace {
+
+// Backward pass from the head: LOSS takes dL/dpsi from the L2 loss against `src` (the
+// target), otherwise `src` is dL/dpsi itself.  Overwrites every parameter gradient.
+template <bool LOSS> int backward_from(gpnn* m, const float* src, double* loss) {
   const gpnn_arch& a = m->a;
   hipStream_t st = m->st;
   const int n = m->n, S = m->S;
@@ -1492,14 +1507,14 @@ int gpnn_loss_backward(gpnn* m, const float* tgt, double* loss) {
   const float scale = (float)(a.dx * a.dx * a.dx / n);
   const float* psi = (const float*)m->out;
   if (a.ch[S] == 16)
-    hipLaunchKernelGGL((k_head_bwd<16>), dim3(hb), dim3(256), 0, st, psi, tgt, m->act[S], m->h[S], P, m->w + m->owh,
-                       scale, m->dA, m->gpart, m->lpart);
+    hipLaunchKernelGGL((k_head_bwd<16, LOSS>), dim3(hb), dim3(256), 0, st, psi, src, m->act[S], m->h[S], P,
+                       m->w + m->owh, scale, m->dA, m->gpart, m->lpart);
   else if (a.ch[S] == 32)
-    hipLaunchKernelGGL((k_head_bwd<32>), dim3(hb), dim3(256), 0, st, psi, tgt, m->act[S], m->h[S], P, m->w + m->owh,
-                       scale, m->dA, m->gpart, m->lpart);
+    hipLaunchKernelGGL((k_head_bwd<32, LOSS>), dim3(hb), dim3(256), 0, st, psi, src, m->act[S], m->h[S], P,
+                       m->w + m->owh, scale, m->dA, m->gpart, m->lpart);
   else
-    hipLaunchKernelGGL((k_head_bwd<64>), dim3(hb), dim3(256), 0, st, psi, tgt, m->act[S], m->h[S], P, m->w + m->owh,
-                       scale, m->dA, m->gpart, m->lpart);
+    hipLaunchKernelGGL((k_head_bwd<64, LOSS>), dim3(hb), dim3(256), 0, st, psi, src, m->act[S], m->h[S], P,
+                       m->w + m->owh, scale, m->dA, m->gpart, m->lpart);
   {  // head partials: groups of 128 blocks first (into the bias-partials buffer, free here)
     const int per = a.ch[S] + 1, n2 = (int)((hb + 127) / 128);
     hipLaunchKernelGGL(k_reduce_chunks_pre, dim3(nblk(per), (unsigned)n2), dim3(256), 0, st, m->gpart, (int)hb,
@@ -1543,6 +1558,24 @@ int gpnn_loss_backward(gpnn* m, const float* tgt, double* loss) {
     *loss *= a.dx * a.dx * a.dx / n;
   }
   return GPNN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gpnn_loss_backward(gpnn* m, const float* tgt, double* loss) {
+  if (!m || !tgt) return set_err(m, GPNN_ERR_INVALID, "bad backward arguments");
+  if (m->n < 1 || m->out_cplx) return set_err(m, GPNN_ERR_STATE, "no FP32 forward pass to differentiate");
+  return backward_from<true>(m, tgt, loss);
+}
+
+int gpnn_backward(gpnn* m, const void* grad_psi_dev) {
+  if (!m || !grad_psi_dev) return set_err(m, GPNN_ERR_INVALID, "bad backward arguments");
+  if (m->n < 1 || m->out_cplx) return set_err(m, GPNN_ERR_STATE, "no FP32 forward pass to differentiate");
+  if (reinterpret_cast<uintptr_t>(grad_psi_dev) % sizeof(float) != 0)
+    return set_err(m, GPNN_ERR_INVALID, "grad_psi is not aligned to float");
+  return backward_from<false>(m, static_cast<const float*>(grad_psi_dev), nullptr);
 }
 
 int gpnn_adam_step(gpnn* m, float lr, float b1, float b2, float eps, int64_t t) {

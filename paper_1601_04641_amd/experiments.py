@@ -2,6 +2,7 @@
 
     python -m paper_1601_04641_amd.experiments quench    [--prec c64|c128] [--out F]
     python -m paper_1601_04641_amd.experiments precision [--seeds 0,1,2,3,4] [--out F]
+    python -m paper_1601_04641_amd.experiments strang    [--out F]
 
 quench: the real-time quench workload (512x480x448, dx = 0.05, nu = (1, 1.4142, 1.7321)):
 imaginary time (dt = 0.1 dx^2) from the trap's Gaussian until mu changes by at most
@@ -148,9 +149,66 @@ def precision(seeds=(0, 1, 2, 3, 4), steps=20000, n=384, dx=0.08, chunk=2000):
     return dict(workload="precision_384cube_dx0.08", runs=out)
 
 
+def strang(dts=(0.008, 0.004, 0.002, 0.001), t_real=0.4, tol=1e-13):
+    """Lie against Strang splitting on the 48x40x32 workload, complex128.
+
+    Imaginary time: for each dt, both splittings from the trap's Gaussian to the fixed
+    point (stopping rule at `tol`, then 20% more steps); mu, E, rms, the estimate mu_est
+    and the fixed point's distance between the two splittings.  Real time: from a seeded
+    perturbed state to t_real, the state's change under dt halving (its error at fixed t
+    shrinks like dt^p: p = 1 Lie, 2 Strang)."""
+    import torch
+    gp.load()
+    w0 = dict(inputs.WORKLOADS["imag_48x40x32"])
+    nx, ny, nz = w0["nx"], w0["ny"], w0["nz"]
+    g0 = inputs.gaussian_psi(nx, ny, nz, w0["dx"], w0["dy"], w0["dz"], w0["nux"], w0["nuy"], w0["nuz"])
+    imag = []
+    for dt in dts:
+        row = dict(dt=dt)
+        states = {}
+        for split, name in ((gp.GP_SPLIT_LIE, "lie"), (gp.GP_SPLIT_STRANG, "strang")):
+            psi = torch.from_numpy(g0).to("cuda")
+            with gp.Solver.from_workload(psi, dict(w0, dt=dt), split=split) as s:
+                steps, mu, conv = s.converge_imag(tol=tol, check_every=max(1, round(0.05 / dt)), max_steps=10 ** 6)
+                s.step_imag(max(1, steps // 5))
+                e, mu = s.energy_mu()
+                row[name] = dict(steps=int(steps), converged=bool(conv), mu=mu, energy=e, rms=s.rms().tolist(),
+                                 mu_est=s.status()[1])
+                torch.cuda.synchronize()
+                states[name] = psi.cpu().numpy()
+            log(f"[strang imag dt {dt}] {name}: mu {row[name]['mu']:.12f} E {row[name]['energy']:.12f}")
+        a, b = states["lie"], states["strang"]
+        row["max_dpsi_lie_strang"] = float(np.max(np.abs(a - b)) / np.max(np.abs(a)))
+        imag.append(row)
+    # dt -> 0 differences: first-order (Lie mu) and second-order (E) behaviour
+    for key in ("lie", "strang"):
+        for q in ("mu", "energy"):
+            v = [r[key][q] for r in imag]
+            d = [v[k] - v[k + 1] for k in range(len(v) - 1)]
+            imag_order = [math.log2(d[k] / d[k + 1]) if d[k + 1] != 0 and d[k] / d[k + 1] > 0 else None
+                          for k in range(len(d) - 1)]
+            for r, o in zip(imag[2:], imag_order):
+                r.setdefault("observed_order", {})[f"{key}_{q}"] = o
+    psi0 = inputs.perturbed_psi(nx, ny, nz, w0["dx"], w0["dy"], w0["dz"], 1.3, 1.6, 2.0, seed=21, amp=0.15)
+    real = {}
+    for split, name in ((gp.GP_SPLIT_LIE, "lie"), (gp.GP_SPLIT_STRANG, "strang")):
+        res = []
+        for dt in dts:
+            psi = torch.from_numpy(psi0).to("cuda")
+            with gp.Solver.from_workload(psi, dict(w0, dt=dt), split=split) as s:
+                s.step_real(int(round(t_real / dt)))
+                torch.cuda.synchronize()
+                res.append(psi.cpu().numpy())
+        diffs = [float(np.max(np.abs(res[k] - res[k + 1]))) for k in range(len(res) - 1)]
+        real[name] = dict(dt=list(dts), successive_max_diff=diffs,
+                          observed_order=[math.log2(diffs[k] / diffs[k + 1]) for k in range(len(diffs) - 1)])
+        log(f"[strang real] {name}: {real[name]}")
+    return dict(workload="imag_48x40x32", precision="complex128", imag=imag, real=dict(t=t_real, **real))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=("quench", "precision"))
+    ap.add_argument("what", choices=("quench", "precision", "strang"))
     ap.add_argument("--prec", choices=("c64", "c128"), default="c64")
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--seeds", default="0,1,2,3,4")
@@ -159,6 +217,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.what == "quench":
         r = quench(gp.GP_C64 if a.prec == "c64" else gp.GP_C128, tol=a.tol)
+    elif a.what == "strang":
+        r = strang()
     else:
         r = precision(tuple(int(v) for v in a.seeds.split(",")), steps=a.steps)
     txt = json.dumps(r, indent=1)

@@ -30,7 +30,8 @@ EXPORTS = ("gp_init", "gp_destroy", "gp_step_imag", "gp_step_real", "gp_norm", "
            "gp_batch_norm", "gp_batch_energy_mu", "gp_batch_rms", "gp_batch_raw_sums",
            "gp_batch_status", "gp_batch_residual", "gp_batch_converge_imag", "gp_batch_get_mapping",
            "gp_batch_set_mapping", "gp_batch_autotune", "gp_batch_set_yz_fusion", "gp_batch_get_yz_fusion", "gp_batch_set_timing",
-           "gp_batch_get_timing", "gp_batch_last_error")
+           "gp_batch_get_timing", "gp_batch_last_error",
+           "gp_set_alloc_cap", "gp_eval_sincos", "gp_stream_copy")
 
 
 class GPError(RuntimeError):
@@ -94,7 +95,10 @@ def load(path: str = LIB_PATH):
         "gp_batch_converge_imag": [vp, d, i32, i64, P(i64), P(d), P(i32)],
         "gp_batch_get_mapping": [vp, P(i32)],
         "gp_batch_set_mapping": [vp, P(i32)],
-        "gp_batch_autotune": [vp, i32, i32, P(i32)],
+        "gp_batch_autotune": [vp, i32, i32, ctypes.c_char_p, P(i32)],
+        "gp_set_alloc_cap": [i64],
+        "gp_eval_sincos": [i32, vp, i64, vp, vp, vp],
+        "gp_stream_copy": [vp, vp, i64, vp],
         "gp_batch_set_yz_fusion": [vp, i32],
         "gp_batch_get_yz_fusion": [vp, P(i32), P(i32)],
         "gp_batch_set_timing": [vp, i32],
@@ -134,6 +138,52 @@ def gp_init(params: gp_params, psi_ptr: int, stream_ptr: int):
     rc = load().gp_init(ctypes.byref(params), ctypes.c_void_p(psi_ptr), ctypes.c_void_p(stream_ptr),
                         ctypes.byref(h))
     return rc, h
+
+
+def set_alloc_cap(nbytes: int | None):
+    """Make every later library allocation above nbytes fail with GP_ERR_OOM (None: no cap)."""
+    load().gp_set_alloc_cap(-1 if nbytes is None else int(nbytes))
+
+
+def _stream_ptr(t, stream):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(t.device)
+    return st.cuda_stream
+
+
+def eval_sincos(x, stream=None):
+    """(sin x, cos x) of the device phase-factor routine for a float32 or float64 device tensor."""
+    import torch
+    if not x.is_cuda or not x.is_contiguous() or x.dtype not in (torch.float32, torch.float64):
+        raise ValueError("x must be a contiguous float32/float64 device tensor")
+    sn, cs = torch.empty_like(x), torch.empty_like(x)
+    prec = GP_C64 if x.dtype == torch.float32 else GP_C128
+    rc = load().gp_eval_sincos(prec, ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(sn.data_ptr()),
+                               ctypes.c_void_p(cs.data_ptr()), ctypes.c_void_p(_stream_ptr(x, stream)))
+    if rc != GP_OK:
+        raise GPError(rc, "gp_eval_sincos")
+    return sn, cs
+
+
+def stream_copy(src, dst, stream=None):
+    """dst <- src (device tensors of equal byte size, a multiple of 16) by the library's copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()) or \
+            dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst must be contiguous device tensors of the same byte size")
+    rc = load().gp_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                               ctypes.c_void_p(_stream_ptr(src, stream)))
+    if rc != GP_OK:
+        raise GPError(rc, "gp_stream_copy")
+
+
+def _check_like(psi, shape, dtype, device):
+    """psi must match the context's shape, dtype and device and be contiguous device memory."""
+    if tuple(psi.shape) != tuple(shape) or psi.dtype != dtype or psi.device != device:
+        raise ValueError(f"psi must be {tuple(shape)} {dtype} on {device}, got {tuple(psi.shape)} "
+                         f"{psi.dtype} on {psi.device}")
+    if not psi.is_cuda or not psi.is_contiguous():
+        raise ValueError("psi must be a contiguous device tensor")
 
 
 class Solver:
@@ -199,6 +249,8 @@ class Solver:
         self._chk(self._L.gp_set_g(self._h, float(g)), "gp_set_g")
 
     def set_psi(self, psi):
+        """Continue on another buffer of the same shape, dtype and device (resume/checkpoint)."""
+        _check_like(psi, self.psi.shape, self.psi.dtype, self.psi.device)
         self._chk(self._L.gp_set_psi(self._h, ctypes.c_void_p(psi.data_ptr())), "gp_set_psi")
         self.psi = psi
 
@@ -265,12 +317,23 @@ class Batch:
 
     def __init__(self, psi, params, offsets, split=GP_SPLIT_LIE, stream=None):
         import torch
-        if not psi.is_cuda or not psi.is_contiguous() or psi.dim() != 1:
+        if not psi.is_contiguous() or psi.dim() != 1:
             raise ValueError("psi must be a contiguous 1D device tensor")
         prec = GP_C128 if psi.dtype == torch.complex128 else GP_C64 if psi.dtype == torch.complex64 else None
         if prec is None:
             raise ValueError("psi must be complex64 or complex128")
         self.n = len(params)
+        offsets = np.asarray(offsets, dtype=np.int64).reshape(-1)
+        if self.n < 1 or len(offsets) != self.n:
+            raise ValueError(f"{self.n} parameter sets but {len(offsets)} offsets")
+        sizes = np.array([int(w["nx"]) * int(w["ny"]) * int(w["nz"]) for w in params], dtype=np.int64)
+        if np.any(offsets < 0) or np.any(offsets + sizes > psi.numel()):
+            raise ValueError("every instance [offset, offset + nx*ny*nz) must lie inside psi")
+        order = np.argsort(offsets, kind="stable")
+        if np.any(offsets[order][1:] < (offsets + sizes)[order][:-1]):
+            raise ValueError("instance regions overlap")
+        if not psi.is_cuda:
+            raise ValueError("psi must be a contiguous 1D device tensor")
         arr = (gp_params * self.n)()
         for i, w in enumerate(params):
             arr[i] = make_params(w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"],
@@ -321,10 +384,15 @@ class Batch:
         self._chk(self._L.gp_batch_rms(self._h, _dp(out)), "gp_batch_rms")
         return out.reshape(self.n, 4)
 
-    def residual(self):
-        """(res, mu) per instance: || H[phi] phi - mu phi || and mu of phi = psi / sqrt(N)."""
+    def residual(self, allow_nonfinite=False):
+        """(res, mu) per instance: || H[phi] phi - mu phi || and mu of phi = psi / sqrt(N).
+        allow_nonfinite: return NaN/Inf entries (or a zero-norm instance's values) instead
+        of raising, for callers that judge each instance themselves."""
         r, m = np.zeros(self.n), np.zeros(self.n)
-        self._chk(self._L.gp_batch_residual(self._h, _dp(r), _dp(m)), "gp_batch_residual")
+        rc = self._L.gp_batch_residual(self._h, _dp(r), _dp(m))
+        if allow_nonfinite and rc in (GP_ERR_NONFINITE, GP_ERR_ZERO_NORM):
+            rc = GP_OK
+        self._chk(rc, "gp_batch_residual")
         return r, m
 
     def raw_sums(self):
@@ -359,9 +427,10 @@ class Batch:
         arr = (ctypes.c_int32 * 5)(int(mx), int(swx), int(my), int(swy), int(mz))
         self._chk(self._L.gp_batch_set_mapping(self._h, arr), "gp_batch_set_mapping")
 
-    def autotune(self, mode="imag", steps=4):
+    def autotune(self, mode="imag", steps=4, cache_path=None):
         out = (ctypes.c_int32 * 5)()
-        self._chk(self._L.gp_batch_autotune(self._h, 0 if mode == "imag" else 1, int(steps), out),
+        cp = cache_path.encode() if cache_path else None
+        self._chk(self._L.gp_batch_autotune(self._h, 0 if mode == "imag" else 1, int(steps), cp, out),
                   "gp_batch_autotune")
         return list(out)
 

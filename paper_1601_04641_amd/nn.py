@@ -16,7 +16,7 @@ from . import gp
 GPNN_OK, GPNN_ERR_INVALID, GPNN_ERR_HIP, GPNN_ERR_OOM, GPNN_ERR_STATE = 0, -1, -2, -3, -4
 
 EXPORTS = ("gpnn_create", "gpnn_destroy", "gpnn_param_count", "gpnn_set_params", "gpnn_get_params",
-           "gpnn_get_grads", "gpnn_forward", "gpnn_loss_backward", "gpnn_adam_step", "gpnn_conv",
+           "gpnn_get_grads", "gpnn_forward", "gpnn_loss_backward", "gpnn_backward", "gpnn_adam_step", "gpnn_conv",
            "gpnn_conv_wgrad", "gpnn_last_error")
 
 # standardisation of (nu_x, nu_y, nu_z, ln g) for nu ~ U[0.5, 4], ln g ~ U[0, ln 1000]
@@ -55,6 +55,7 @@ def load():
         "gpnn_get_grads": [vp, vp, i64],
         "gpnn_forward": [vp, vp, i32, vp, i32],
         "gpnn_loss_backward": [vp, vp, P(d)],
+        "gpnn_backward": [vp, vp],
         "gpnn_adam_step": [vp, f32, f32, f32, f32, i64],
         "gpnn_conv": [i32, i32, i32, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp],
         "gpnn_conv_wgrad": [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp],
@@ -143,16 +144,37 @@ class Net:
         return v
 
     def forward(self, prm, out, complex_out=False):
-        """prm: float32 [n, 4] device tensor; out: [n, N, N, N] float32 (or complex64)."""
+        """prm: float32 [n, 4] device tensor; out: [n, N, N, N] float32, or complex64 /
+        complex128 (complex_out=True; the kind follows out's dtype)."""
+        import torch
         n = prm.shape[0]
-        self._chk(self._L.gpnn_forward(self._h, prm.data_ptr(), n, out.data_ptr(), 1 if complex_out else 0),
-                  "gpnn_forward")
+        kind = 0
+        if complex_out:
+            kind = 2 if out.dtype == torch.complex128 else 1
+        if out.numel() < n * self.N ** 3 or not out.is_contiguous():
+            raise ValueError(f"out must hold {n} x {self.N}^3 contiguous values")
+        self._chk(self._L.gpnn_forward(self._h, prm.data_ptr(), n, out.data_ptr(), kind), "gpnn_forward")
+        self._last_points = n * self.N ** 3
 
     def loss_backward(self, target, want_loss=True):
+        lp = getattr(self, "_last_points", None)
+        if (lp is not None and target.numel() != lp) or not target.is_contiguous():
+            raise ValueError("target must have one value per point of the last forward pass's output")
         v = ctypes.c_double()
         self._chk(self._L.gpnn_loss_backward(self._h, target.data_ptr(), ctypes.byref(v) if want_loss else None),
                   "gpnn_loss_backward")
         return v.value if want_loss else None
+
+    def backward(self, grad_psi):
+        """Parameter gradients of the last FP32 forward pass for an upstream dL/dpsi
+        (FP32 device tensor shaped like that pass's output); overwrites the gradients."""
+        import torch
+        if not grad_psi.is_cuda or not grad_psi.is_contiguous() or grad_psi.dtype != torch.float32:
+            raise ValueError("grad_psi must be a contiguous float32 device tensor")
+        lp = getattr(self, "_last_points", None)
+        if lp is not None and grad_psi.numel() != lp:   # (no forward pass yet: the library's state error)
+            raise ValueError("grad_psi must have one value per point of the last forward pass's output")
+        self._chk(self._L.gpnn_backward(self._h, grad_psi.data_ptr()), "gpnn_backward")
 
     def adam_step(self, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
         self._chk(self._L.gpnn_adam_step(self._h, lr, beta1, beta2, eps, int(t)), "gpnn_adam_step")

@@ -14,8 +14,9 @@ calls):
   4. Residual gate: per problem, the network's start is kept only if its
      stationary-equation residual ||H[phi] phi - mu phi|| (gp_batch_residual) is below
      the Gaussian's and below `gate` * mu; otherwise the Gaussian is used.
-  5. Time to ground state at mu tolerance `tol` (|mu_n - mu_{n-K}| <= tol |mu_n|, K steps
-     between checks): (a) Gaussian starts, one single-grid solver after another;
+  5. Time to ground state at mu tolerance `tol` (the solver's stopping rule: mu checked
+     every K steps, its change and Aitken-extrapolated distance to the limit within
+     tol |mu|), in complex128: (a) Gaussian starts, one single-grid solver after another;
      (b) Gaussian starts, batched; (c) gated network starts (inference and gate
      included in the time), batched.
 The propagation is the paper's imaginary-time method (program summary (i)); the network
@@ -118,10 +119,11 @@ def train(torch, net, prm, tgt, epochs, batch, lr0, seed=0, lr_min=1e-5, log_eve
     return hist, time.perf_counter() - t0
 
 
-def infer(torch, net, prm_d, out_c64, batch):
-    """Network starts for every problem, written as complex64 into out_c64 ([M * n^3])."""
+def infer(torch, net, prm_d, out_c, batch):
+    """Network starts for every problem, written into the complex64 or complex128 solver
+    buffer out_c ([M * n^3])."""
     M = prm_d.shape[0]
-    view = out_c64.view(M, N_GRID, N_GRID, N_GRID)
+    view = out_c.view(M, N_GRID, N_GRID, N_GRID)
     for c0 in range(0, M, batch):
         c1 = min(M, c0 + batch)
         net.forward(prm_d[c0:c1], view[c0:c1], complex_out=True)
@@ -144,14 +146,38 @@ def eval_l2(torch, net, prm, tgt, batch):
     return errs
 
 
-def time_to_ground_state(torch, net, prm, tol, gate, batch, mu_ref, serial=True):
+def gated_starts(torch, net, prm_d, probs, offs, psi, gauss, gate, batch):
+    """Network starts for every problem written into psi (complex64, back to back at
+    offs), then the residual gate: a problem keeps the network's start only if its
+    stationary-equation residual is finite, below the Gaussian start's (gauss) and below
+    gate * |mu|; otherwise its slice of psi is replaced by the Gaussian start (the
+    fallback, also taken when corrupted weights give a non-finite or wrong state).
+    Returns (use_net, r_net, r_gauss, mu_net, mu_gauss)."""
+    M = len(probs)
+    with gp.Batch(gauss, probs, offs) as bg:
+        r_gauss, mu_gauss = bg.residual()
+    infer(torch, net, prm_d, psi, batch)
+    with gp.Batch(psi, probs, offs) as b:
+        r_net, mu_net = b.residual(allow_nonfinite=True)
+    ok = np.isfinite(r_net) & np.isfinite(mu_net)
+    use_net = ok & (np.where(ok, r_net, np.inf) < r_gauss) & (np.where(ok, r_net, np.inf) < gate * np.abs(mu_net))
+    pv, gv = psi.view(M, -1), gauss.view(M, -1)
+    for i in np.nonzero(~use_net)[0]:
+        pv[i].copy_(gv[i])
+    return use_net, r_net, r_gauss, mu_net, mu_gauss
+
+
+def time_to_ground_state(torch, net, prm, tol, gate, batch, mu_ref, serial=True, complex128=False):
+    """Time to the ground state at tolerance tol from three starts (see the module text);
+    complex128: every propagation in FP64 (the network's start is written in complex128),
+    so the stopped states can meet tol against an FP64 reference mu_ref."""
     M = len(prm)
     probs = [problem(r) for r in prm]
     offs = _offsets(M)
-    res = {}
+    res = {"precision": "complex128" if complex128 else "complex64"}
     # (a) Gaussian starts, one single-grid solver after another
     if serial:
-        psi = gaussian_starts(torch, prm)
+        psi = gaussian_starts(torch, prm, complex128=complex128)
         views = psi.view(M, N_GRID, N_GRID, N_GRID)
         solvers = [gp.Solver.from_workload(views[i], p) for i, p in enumerate(probs)]
         torch.cuda.synchronize()
@@ -168,7 +194,7 @@ def time_to_ground_state(torch, net, prm, tol, gate, batch, mu_ref, serial=True)
         del psi, views
         log(f"[ttgs] gaussian serial: {res['gaussian_serial']}")
     # (b) Gaussian starts, batched
-    psi = gaussian_starts(torch, prm)
+    psi = gaussian_starts(torch, prm, complex128=complex128)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with gp.Batch(psi, probs, offs) as b:
@@ -179,21 +205,15 @@ def time_to_ground_state(torch, net, prm, tol, gate, batch, mu_ref, serial=True)
                                    mu_rel_err_max=float(np.max(np.abs(mu - mu_ref) / mu_ref)))
     log(f"[ttgs] gaussian batched: {res['gaussian_batched']}")
     # (c) network starts (inference + gate included), batched
-    gauss = gaussian_starts(torch, prm)  # fallback states, built on the host like (a) and (b)
+    gauss = gaussian_starts(torch, prm, complex128=complex128)  # fallback states, built on the host like (a), (b)
     prm_d = torch.from_numpy(np.asarray(prm, dtype=np.float32)).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    with gp.Batch(gauss, probs, offs) as bg:
-        r_gauss, mu_gauss = bg.residual()
-    infer(torch, net, prm_d, psi, batch)
+    use_net, r_net, r_gauss, mu_net, mu_gauss = gated_starts(torch, net, prm_d, probs, offs, psi, gauss, gate,
+                                                             batch)
+    bad = np.nonzero(~use_net)[0]
+    t_gate = time.perf_counter() - t0
     with gp.Batch(psi, probs, offs) as b:
-        r_net, mu_net = b.residual()
-        use_net = (r_net < r_gauss) & (r_net < gate * np.abs(mu_net))
-        bad = np.nonzero(~use_net)[0]
-        pv, gv = psi.view(M, -1), gauss.view(M, -1)
-        for i in bad:
-            pv[i].copy_(gv[i])
-        t_gate = time.perf_counter() - t0
         st, mu, conv = b.converge_imag(tol=tol, check_every=0)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -258,7 +278,7 @@ def run(n_train=4096, n_test=512, epochs=40, batch=16, lr0=1e-3, data_tol=1e-8, 
         log(f"[eval] relative L2: test median {np.median(e_te):.2e}, p90 {np.percentile(e_te, 90):.2e}")
         torch.cuda.empty_cache()
         out["time_to_ground_state"] = time_to_ground_state(torch, net, prm_test, tol, gate, batch, mu_ref,
-                                                            serial=serial)
+                                                            serial=serial, complex128=True)
     return out
 
 

@@ -53,20 +53,22 @@ def test_init_rejects_bad_params_without_device(lib, field, value):
 
 
 def test_init_rejects_oversized_grids_without_device(lib):
-    # more than 2048 points on an axis; complex128 lines over 1024 points (no instance);
-    # complex64 2048^3, where every x mapping's wavefront would span over 2 GiB of rows
-    for n, prec in [((2049, 8, 8), gp.GP_C64), ((8, 8, 4096), gp.GP_C64), ((8, 8, 2040), gp.GP_C64),
-                    ((1100, 8, 8), gp.GP_C128),
-                    ((8, 8, 1020), gp.GP_C128), ((2048, 2048, 2048), gp.GP_C64)]:
+    # more than 2048 points on an axis
+    for n, prec in [((2049, 8, 8), gp.GP_C64), ((8, 8, 4096), gp.GP_C64), ((8, 2049, 8), gp.GP_C128),
+                    ((8, 8, 2049), gp.GP_C128)]:
         p = gp.make_params(*n, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001, prec)
         rc, _ = gp.gp_init(p, 0x1000, 0)
         assert rc == gp.GP_ERR_UNSUPPORTED, n
-    # the paper's large grids in complex64 have a mapping: init goes on to the device
-    # (and fails there only for want of one)
-    for n in [(1920, 1600, 1280), (1600, 1280, 960), (2048, 3, 5), (4, 3, 2032)]:
-        p = gp.make_params(*n, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001, gp.GP_C64)
-        rc, _ = gp.gp_init(p, 0x1000, 0)
-        assert rc != gp.GP_ERR_UNSUPPORTED, n
+    # every grid up to 2048 points per axis has a mapping, in both precisions (the paper's
+    # large grids, lines of 1025-2048 points, z blocks beyond 64 KiB of LDS, wavefronts
+    # whose rows span 2 GiB or more): init goes on to the device (and fails there only for
+    # want of one)
+    for n in [(1920, 1600, 1280), (1600, 1280, 960), (2048, 3, 5), (4, 3, 2032), (1100, 8, 8), (8, 8, 1020),
+              (8, 8, 2040), (8, 8, 2048), (2048, 2048, 2048)]:
+        for prec in (gp.GP_C64, gp.GP_C128):
+            p = gp.make_params(*n, 0.1, 0.1, 0.1, 1.0, 1.0, 1.0, 1.0, 0.001, prec)
+            rc, _ = gp.gp_init(p, 0x1000, 0)
+            assert rc != gp.GP_ERR_UNSUPPORTED, (n, prec)
 
 
 def test_null_arguments(lib):
@@ -127,3 +129,28 @@ def test_gpnn_conv_rejects_bad_shapes_without_device(lib, args):
     assert lib.gpnn_conv(ks, n, d, cin, cout, 0x1000, 0x1000, None, 0, None, 0x1000, None, None) == \
         nn.GPNN_ERR_INVALID
     assert lib.gpnn_conv_wgrad(ks, n, d, cin, cout, 0x1000, 0x1000, 0x1000, None, None) == nn.GPNN_ERR_INVALID
+
+
+def test_batch_rejects_bad_offsets_before_the_device():
+    """Offsets are checked against psi's length on the host: the C-ABI has no buffer
+    length, so a short or overlapping layout would otherwise reach the kernels."""
+    import torch
+    ws = [dict(nx=4, ny=5, nz=6, dx=0.2, dy=0.2, dz=0.2, nux=1, nuy=1, nuz=1, g=1, dt=0.004),
+          dict(nx=3, ny=3, nz=3, dx=0.2, dy=0.2, dz=0.2, nux=1, nuy=1, nuz=1, g=1, dt=0.004)]
+    psi = torch.zeros(120 + 27, dtype=torch.complex64)
+    for offs in ([0], [0, 120, 5], [0, 121], [-1, 120], [0, 100], [27, 0]):
+        with pytest.raises(ValueError):
+            gp.Batch(psi, ws, offs)
+    with pytest.raises(ValueError, match="device"):   # a valid layout reaches the device check
+        gp.Batch(psi, ws, [27, 0])
+
+
+def test_set_psi_checks_shape_dtype_and_device():
+    import torch
+    a = torch.zeros((4, 5, 6), dtype=torch.complex128)
+    for bad in (torch.zeros((4, 5, 7), dtype=torch.complex128), torch.zeros((4, 5, 6), dtype=torch.complex64),
+                torch.zeros(120, dtype=torch.complex128)):
+        with pytest.raises(ValueError):
+            gp._check_like(bad, a.shape, a.dtype, a.device)
+    with pytest.raises(ValueError):   # right shape and dtype, but host memory
+        gp._check_like(a.clone(), a.shape, a.dtype, a.device)

@@ -300,3 +300,49 @@ def test_strang_batch_matches_oracle(imag):
         o = oracle.Oracle.from_params(w, s0, split=1)
         (o.step_imag if imag else o.step_real)(9)
         assert float(np.max(np.abs(out - o.psi)) / np.max(np.abs(o.psi))) <= 1e-12
+
+
+@pytest.mark.parametrize("fuse", [False, True])
+@pytest.mark.parametrize("imag", [True, False])
+def test_batch_odd_sized_complex64_instance_first(fuse, imag):
+    """An odd-sized complex64 instance first puts the next instance at an odd element
+    offset (8- but not 16-byte aligned): the 16-byte plane and line copies must fall back
+    to 8-byte ones there."""
+    ws = instances()
+    ws = [dict(ws[4], nx=17, ny=33, nz=21), dict(ws[0], nx=24, ny=20, nz=30), dict(ws[2], nx=14, ny=11, nz=9),
+          dict(ws[1], nx=32, ny=24, nz=40)]
+    states, offs, total = pack(ws, gp.GP_C64, seed=50)
+    assert offs[1] % 2 == 1 and offs[3] % 2 == 1
+    psi = to_dev(states, total, gp.GP_C64)
+    say(f"case: odd offsets {offs.tolist()} fuse {fuse} imag {imag}")
+    with gp.Batch(psi, ws, offs) as b:
+        b.set_yz_fusion(fuse)
+        (b.step_imag if imag else b.step_real)(5)
+        torch.cuda.synchronize()
+        outs = unpack(psi, ws, offs)
+    for i, (w, s0, out) in enumerate(zip(ws, states, outs)):
+        o = oracle.Oracle.from_params(w, s0)
+        (o.step_imag if imag else o.step_real)(5)
+        err = float(np.max(np.abs(out - o.psi)) / np.max(np.abs(o.psi)))
+        tol = c64_tolerance(w, s0, o.psi, imag, steps=5)
+        say(f"  instance {i} offset {offs[i]}: rel err {err:.2e} (tol {tol:.1e})")
+        assert err <= tol
+
+
+def test_batch_autotune_cache(tmp_path):
+    ws = instances()
+    states, offs, total = pack(ws, gp.GP_C64, seed=40)
+    psi = to_dev(states, total, gp.GP_C64)
+    cache = str(tmp_path / "btune.txt")
+    with gp.Batch(psi, ws, offs) as b:
+        m1 = b.autotune("imag", steps=1, cache_path=cache)
+        f1 = b.get_yz_fusion()
+        b.set_mapping(8, 1, 8, 1, 4)
+        b.set_yz_fusion(not f1[0])
+        m2 = b.autotune("imag", steps=1, cache_path=cache)   # a hit: no timing, stored choice
+        assert m1 == m2 == b.get_mapping() and b.get_yz_fusion() == f1
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("gfx950-batch ")
+    with gp.Batch(psi, ws[:-1], offs[:-1]) as b:   # another batch: a miss, a second line
+        b.autotune("imag", steps=1, cache_path=cache)
+    assert len(open(cache).read().strip().splitlines()) == 2

@@ -348,3 +348,50 @@ def test_state_and_argument_errors():
             net.forward(prm, out)  # n > max_batch
         with pytest.raises(nn.NNError):
             net.set_params(np.zeros(3, dtype=np.float32))
+
+
+def test_backward_from_upstream_gradient():
+    """gpnn_backward with dL/dpsi given: (a) with dL/dpsi = 2 (psi - t) dx^3 / n, formed
+    in FP32 as the loss kernel forms it, the gradients are bitwise those of
+    gpnn_loss_backward; (b) with a smooth seeded upstream gradient G, against the
+    BF16-storage emulation of the reference chain rule (whose head gradient is G psi;
+    G enters it through the target t = psi - G n / (2 dx^3), for which the L2 loss has
+    dL/dpsi = G)."""
+    cfg = tiny_cfg()
+    w = trained_like_weights(cfg, 7)
+    p = inputs.draw_nn_params(8, 3)
+    a = ref_arch(cfg)
+    wr = bf16_round_weights(w)
+    p32 = p.astype(np.float32).astype(np.float64)
+    psi_ref, cache = R.forward(wr, p32, a)
+    x = R.grid_axis(a.n_out, a.dx)
+    tgt = (psi_ref * (1 + 0.2 * np.sin(x)[None, :, None, None])).astype(np.float32)
+    rng = np.random.default_rng(17)
+    # no symmetry of the grid (an odd G would cancel the low layers' gradients)
+    G = ((0.4 + np.cos(0.9 * x)[None, :, None, None] * (1 + 0.5 * np.sin(0.6 * x + 0.3))[None, None, None, :]
+          * (1 + 0.3 * np.cos(0.4 * x))[None, None, :, None]) * rng.uniform(0.5, 1.5, (3, 1, 1, 1))).astype(np.float32)
+    assert G.shape == tgt.shape
+    with nn.Net(**cfg) as net:
+        net.set_params(w)
+        prm = torch.from_numpy(p.astype(np.float32)).cuda()
+        out = torch.empty((3, net.N, net.N, net.N), dtype=torch.float32, device="cuda")
+        net.forward(prm, out)
+        t_d = torch.from_numpy(tgt).cuda()
+        net.loss_backward(t_d, want_loss=False)
+        g_loss = net.get_grads()
+        scale = np.float32(cfg["dx"] ** 3 / 3)
+        up = ((out - t_d) * 2.0) * float(scale)
+        net.backward(up.contiguous())
+        g_up = net.get_grads()
+        say(f"case: upstream-gradient backward; bitwise equal to the loss backward: {np.array_equal(g_loss, g_up)}")
+        assert np.array_equal(g_loss, g_up)
+        net.backward(torch.from_numpy(G).cuda())
+        g = nn.unflatten(net.get_grads(), net.shapes)
+        psi_gpu = out.cpu().numpy().astype(np.float64)
+    t_equiv = psi_gpu - G.astype(np.float64) * 3 / (2 * cfg["dx"] ** 3)
+    gemu = backward_bf16_storage(w, p32, t_equiv, a)
+    for k, _ in net.shapes:
+        gk = np.asarray(g[k], dtype=np.float64)
+        eem = float(np.linalg.norm(gk - gemu[k]) / np.linalg.norm(gemu[k]))
+        say(f"  {k}: rel err vs BF16-storage emulation {eem:.2e}")
+        assert eem <= 1.5e-2, k

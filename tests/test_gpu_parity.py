@@ -244,8 +244,9 @@ def test_full_size_sine_modes_closed_form(prec):
 
 @pytest.mark.parametrize("prec,imag", [(gp.GP_C64, False), (gp.GP_C128, False), (gp.GP_C128, True)])
 def test_full_size_step_matches_oracle(prec, imag):
-    """Quench workload grid in the benchmark's launch configuration, 2 steps from a seeded
-    state, compared with the oracle at every point."""
+    """Quench workload grid in the default line mapping, 2 steps from a seeded state,
+    compared with the oracle at every point (the benchmark's autotuned mapping is covered
+    by test_gpu_mappings.test_quench_grid_in_benchmark_mapping)."""
     w = inputs.WORKLOADS["quench_512x480x448"]
     prm = dict(w)
     if imag:

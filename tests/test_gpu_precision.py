@@ -1,7 +1,8 @@
 """Precision form on the 384^3 workload (dx = 0.08, trap and g drawn by seed 0):
 complex64 storage and FP32 sweeps with FP64 reductions, and the complex128 path, both
-compared with the FP64 CPU oracle over steps from a shared partly converged state (the
-oracle cannot afford the full 20000-step run at 5.7e7 points inside a test)."""
+compared with the FP64 CPU oracle over 200 steps from a shared partly converged state (the
+oracle cannot afford the full 20000-step run at 5.7e7 points inside a test: 200 steps take
+it about a minute on 16 host threads)."""
 import sys
 import time
 
@@ -15,6 +16,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 N, DX = 384, 0.08
+STEPS = 200
 
 
 def say(*a):
@@ -36,10 +38,10 @@ def shared_state():
     host = psi.cpu().numpy()
     del psi
     torch.cuda.empty_cache()
-    say("  oracle: 10 imaginary steps")
+    say(f"  oracle: {STEPS} imaginary steps")
     t0 = time.time()
     o = oracle.Oracle.from_params(w, host)
-    o.step_imag(10)
+    o.step_imag(STEPS)
     e, mu = o.energy_mu()
     say(f"  oracle done ({time.time() - t0:.1f} s), mu {mu:.12f}")
     yield w, host, o.psi.copy(), e, mu
@@ -52,7 +54,7 @@ def test_precision_form_384_against_oracle(shared_state, prec):
     dt = torch.complex64 if prec == gp.GP_C64 else torch.complex128
     psi = torch.from_numpy(host).to("cuda", dtype=dt)
     with gp.Solver.from_workload(psi, w) as s:
-        s.step_imag(10)
+        s.step_imag(STEPS)
         e, mu = s.energy_mu()
         out = psi.cpu().numpy().astype(np.complex128)
     del psi
