@@ -223,6 +223,22 @@ int gp_eval_sincos(int32_t precision, const void* x_dev, int64_t n, void* sin_de
  * practical HBM ceiling the sweep bandwidths are compared with.  Stream-ordered. */
 int gp_stream_copy(const void* src_dev, void* dst_dev, int64_t bytes, void* hip_stream);
 
+/* ---------------------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gp_raw_sums without a context.
+ * raw_dev (caller-owned device memory, 9 doubles) receives gp_raw_sums' raw[9] for the
+ * grid p describes (nx, ny, nz, dx, dy, dz, nux, nuy, nuz, precision; g, dt and split are
+ * not used) and psi_dev; the values are bitwise those of gp_raw_sums on a context of the
+ * same grid.  Stream-ordered: no synchronisation, no host copy, no allocation, no
+ * hipMemset; NaN/Inf/zero norms are returned as values, not as error codes.  The
+ * reduction scratch is one file-scope device array per GPU (147,584 bytes: 2048 blocks x
+ * 9 partial sums + the final sums), held until the process ends; its address is looked up
+ * on the first call on each device.  Grids up to 2048 points per axis (larger:
+ * GP_ERR_UNSUPPORTED).  All calls on one GPU share that array: calls that overlap in time
+ * on one GPU (different streams, or host threads) race and may return each other's sums;
+ * serialise them. */
+int gp_raw_sums_noalloc(const gp_params* p, const void* psi_dev, double* raw_dev, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

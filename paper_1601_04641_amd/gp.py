@@ -31,7 +31,7 @@ EXPORTS = ("gp_init", "gp_destroy", "gp_step_imag", "gp_step_real", "gp_norm", "
            "gp_batch_status", "gp_batch_residual", "gp_batch_converge_imag", "gp_batch_get_mapping",
            "gp_batch_set_mapping", "gp_batch_autotune", "gp_batch_set_yz_fusion", "gp_batch_get_yz_fusion", "gp_batch_set_timing",
            "gp_batch_get_timing", "gp_batch_last_error",
-           "gp_set_alloc_cap", "gp_eval_sincos", "gp_stream_copy")
+           "gp_set_alloc_cap", "gp_eval_sincos", "gp_stream_copy", "gp_raw_sums_noalloc")
 
 
 class GPError(RuntimeError):
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
         "gp_set_alloc_cap": [i64],
         "gp_eval_sincos": [i32, vp, i64, vp, vp, vp],
         "gp_stream_copy": [vp, vp, i64, vp],
+        "gp_raw_sums_noalloc": [P(gp_params), vp, vp, vp],
         "gp_batch_set_yz_fusion": [vp, i32],
         "gp_batch_get_yz_fusion": [vp, P(i32), P(i32)],
         "gp_batch_set_timing": [vp, i32],
