@@ -107,10 +107,11 @@ int gp_status(gp_ctx* c, int64_t* steps_done, double* mu_est, int32_t* flags);
 /* Imaginary-time propagation to the ground state at relative tolerance tol, checking every
  * check_every = K steps (K <= 0 selects ceil(0.25/dt)), at most max_steps steps.
  * Stopping rule, on the sequence of checked values m_n with d_n = m_n - m_{n-1}: while
- * m approaches its limit geometrically (d_n / d_{n-1} = r in (0, 1)), stop when |d_n| and
- * the extrapolated distance to the limit |d_n| r / (1 - r) (Aitken) are both <= tol |m_n|;
- * otherwise (m(t) turning, as from an already close start, or at its rounding floor) when
- * |d_n| <= tol |m_n| at two successive checks.  complex64: m = mu (the observables pass) at
+ * m approaches its limit geometrically (d_n / d_{n-1} = r in (0, 1)), stop when
+ * |d_n| <= tol |m_n|, the extrapolated distance to the limit |d_n| r / (1 - r) (Aitken)
+ * is <= tol |m_n| / 2 and the extrapolated limit agrees within tol |m_n| / 2 with the
+ * previous check's; otherwise (m(t) turning, as from an already close start, or at its
+ * rounding floor) when |d| <= tol |m| / 10 at three successive checks.  complex64: m = mu (the observables pass) at
  * every check.  complex128: m = mu_est = -ln(N_pre)/(2 dt) from the renormalisation (no
  * extra pass); when it stops, mu is evaluated and must change by at most tol |mu| (with the
  * same predicted tail) over one more interval, else monitoring resumes.
@@ -133,6 +134,19 @@ int gp_get_timing(gp_ctx* c, double ms_mean[5], int64_t launches[5]);
  * return GP_ERR_INVALID and leave the mapping unchanged.  Synchronises. */
 int gp_get_mapping(gp_ctx* c, int32_t map[6]);
 int gp_set_mapping(gp_ctx* c, const int32_t map[6]);
+
+/* Halo-truncated Crank-Nicolson inverse (an opt-in variant of the sweeps).  The solution
+ * of a line is u_i = sum_m a^m d_{i+m} (the back-substitution of the constant-pivot
+ * elimination, |a| = |c gamma| < 1); mode 1 keeps only the first H + 1 terms, with H the
+ * smallest length whose dropped tail |a|^(H+1)/(1-|a|) max|d| is below 1/100 of the storage
+ * precision's unit roundoff, so results agree with the exact sweeps to rounding.  Then each
+ * thread streams one whole x or y line (forward elimination exact from the line start,
+ * u_{j-H} emitted at step j): one coalesced read and write of psi per sweep, no LDS, no
+ * barriers.  The z sweep stays exact.  mode 0: exact sweeps (default).  Returns
+ * GP_ERR_UNSUPPORTED when H exceeds 15 (dt/dx^2 large; the exact sweeps stay in use).
+ * gp_get_truncation: the mode and H per [imaginary, real][x, y, z].  Synchronises. */
+int gp_set_truncation(gp_ctx* c, int32_t mode);
+int gp_get_truncation(gp_ctx* c, int32_t* mode, int32_t hlen[6]);
 
 /* Project autotuner: times every line mapping the kernels cover on this context's grid
  * (each axis independently, `steps` steps of kind mode = 0 imaginary / 1 real, HIP-event

@@ -61,6 +61,18 @@ void cn_axis_constants(int n, double d, double dt, int mode, int m, bool f32, Ax
     out->coef[2 * q2 + 1] = vals[q2].imag();
   }
   out->nw = nw;
+  // truncated back-substitution u_i = sum_{m<=H} a^m d_{i+m}: the dropped tail is at most
+  // |a|^(H+1) / (1 - |a|) max|d|; H is the smallest length that puts it below thr
+  {
+    const double aa = std::abs(a);
+    int h = 0;
+    double t = aa / (1.0 - aa);
+    while (t > thr && h < 64) {
+      t *= aa;
+      ++h;
+    }
+    out->hlen = (aa < 1.0) ? h : 64;
+  }
   out->omega.resize(nw);
   for (int i = 0; i < nw; ++i) out->omega[i] = beta * w[i];
 }
@@ -127,10 +139,16 @@ struct gp_ctx {
   DevState* st = nullptr;      // device
   void* tab[2][3] = {{nullptr}};  // [imag, real][axis]: omega, storage precision, n complex
   int nw[2][3] = {{0}};
+  int hlen[2][3] = {{0}};          // truncated back-substitution lengths [imag, real][axis]
+  int trunc = 0;                   // 0 exact sweeps; 1 streaming x/y sweeps, truncated back-substitution;
+                                   // 2 streaming x sweep + fused y+z pass
+  int yz_chunk = 0, yz_nchunks = 0;  // mode 2: rows per block and blocks per plane
+  double yzcoef[2][8] = {{0}};       // mode 2: z constants with P = a^mz of the fused kernel
   double coef[2][3][8] = {{{0}}};  // a, b, b_lo, P = a^m as (re, im)
   void* vtab[3] = {nullptr};      // storage-precision 1/2 nu^2 a^2
   double* zpart = nullptr;
   int zgrid = 0;
+  int zpart_cap = 0;  // doubles allocated at zpart (z sweep or fused y+z partials)
   double* opart = nullptr;
   int ogrid = 0;
   double* oout = nullptr;
@@ -295,6 +313,7 @@ int build_axis_table(gp_ctx* c, int mode, int axis) {
   gpk::cn_axis_constants(n, d, c->p.dt, mode, m, f32, &ac);
   for (int q = 0; q < 8; ++q) c->coef[mode][axis][q] = ac.coef[q];
   c->nw[mode][axis] = ac.nw;
+  c->hlen[mode][axis] = ac.hlen;
   if (ac.nw == 0) return GP_OK;
   std::vector<unsigned char> bytes;
   gpk::pack_complex(ac.omega, f32, bytes);
@@ -334,6 +353,7 @@ gpk::SweepLaunch lines_args(gp_ctx* c, int axis, int mode) {
   a.nlines = axis == 0 ? (int64_t)p.ny * p.nz : (int64_t)p.nx * p.nz;
   a.inner = axis == 0 ? (int64_t)p.ny * p.nz : (int64_t)p.nz;
   a.wide = needs_wide(axis_lines(p, axis), a.m, a.sw);
+  a.hlen = c->hlen[mode][axis];
   a.nstep = 0;
   if (axis == 0) {
     a.nstep = mode == 0 ? 1 : 2;
@@ -428,14 +448,60 @@ int timed(gp_ctx* c, hipStream_t s, int kind, F fn) {
   return GP_OK;
 }
 
+gpk::YZLaunch yz_args(gp_ctx* c, int mode) {
+  gpk::YZLaunch a{};
+  const gp_params& p = c->p;
+  a.psi = c->psi;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.nz = p.nz;
+  a.chunk = c->yz_chunk;
+  a.nchunks = c->yz_nchunks;
+  for (int q = 0; q < 6; ++q) a.ycoef[q] = c->coef[mode][1][q];
+  a.yomega = c->tab[mode][1];
+  a.ynw = c->nw[mode][1];
+  for (int q = 0; q < 8; ++q) a.zcoef[q] = c->yzcoef[mode][q];
+  a.zomega = c->tab[mode][2];
+  a.znw = c->nw[mode][2];
+  a.mz = gpk::yz_mz(p.nz);
+  a.hlen = c->hlen[mode][1];
+  a.epi = p.split == GP_SPLIT_STRANG ? (mode == 0 ? 1 : 2) : 0;
+  a.ph = 0.5 * p.nuz * p.nuz;
+  a.pc = 0.5 * (p.nz - 1);
+  a.pd = p.dz;
+  a.tau = 0.5 * p.dt;
+  a.vx = c->vtab[0];
+  a.vy = c->vtab[1];
+  a.st = c->st;
+  a.partials = mode == 0 ? c->zpart : nullptr;
+  return a;
+}
+
 // One full step on stream s. mode 0 imaginary (renormalising), 1 real.
 int enqueue_step(gp_ctx* c, int mode, hipStream_t s) {
   const int prec = c->p.precision;
   const bool cc = mode == 1;
+  if (c->trunc == 2) {  // streaming x sweep, then the fused y+z pass
+    gpk::SweepLaunch ax = lines_args(c, 0, mode);
+    gpk::YZLaunch ayz = yz_args(c, mode);
+    int rc = timed(c, s, 0, [&](hipStream_t t) { return gpk::launch_stream_lines(prec, cc, ax, t); });
+    if (rc) return rc;
+    rc = timed(c, s, 2, [&](hipStream_t t) { return gpk::launch_stream_yz(prec, cc, ayz, t); });
+    if (rc) return rc;
+    if (mode == 0) {
+      const double dV = c->p.dx * c->p.dy * c->p.dz;
+      const int nb = c->p.nx * c->yz_nchunks;
+      rc = timed(c, s, 3, [&](hipStream_t t) {
+        return gpk::launch_finalize_norm(c->zpart, nb, dV, c->p.dt, c->st, t);
+      });
+    }
+    return rc;
+  }
   gpk::SweepLaunch ax = lines_args(c, 0, mode), ay = lines_args(c, 1, mode), az = z_args(c, mode);
-  int rc = timed(c, s, 0, [&](hipStream_t t) { return gpk::launch_sweep_lines(prec, cc, ax, t); });
+  auto lines = c->trunc ? gpk::launch_stream_lines : gpk::launch_sweep_lines;
+  int rc = timed(c, s, 0, [&](hipStream_t t) { return lines(prec, cc, ax, t); });
   if (rc) return rc;
-  rc = timed(c, s, 1, [&](hipStream_t t) { return gpk::launch_sweep_lines(prec, cc, ay, t); });
+  rc = timed(c, s, 1, [&](hipStream_t t) { return lines(prec, cc, ay, t); });
   if (rc) return rc;
   rc = timed(c, s, 2, [&](hipStream_t t) { return gpk::launch_sweep_z(prec, cc, az, t); });
   if (rc) return rc;
@@ -625,6 +691,7 @@ int init_body(gp_ctx* c) {
   const int64_t oblocks = (c->npts + 255) / 256;
   c->ogrid = (int)std::min<int64_t>(oblocks, 2048);
   if ((rc = dalloc(c, &c->zpart, (size_t)c->zgrid * sizeof(double)))) return rc;
+  c->zpart_cap = c->zgrid;
   if ((rc = dalloc(c, &c->opart, (size_t)c->ogrid * 9 * sizeof(double)))) return rc;
   if ((rc = dalloc(c, &c->oout, 16 * sizeof(double)))) return rc;
   HIPCHK(c, hipHostMalloc((void**)&c->host, 16 * sizeof(double), hipHostMallocDefault));
@@ -814,7 +881,7 @@ int gp_converge_imag(gp_ctx* c, double tol, int32_t check_every, int64_t max_ste
     if ((rc = advance(&done))) return rc;
     if ((rc = gp_energy_mu(c, &e, &cur))) return rc;
     const double d = cur - m0, lim = tol * std::fabs(cur);
-    if (std::fabs(d) <= lim && rule.tail(d) <= lim) {
+    if (std::fabs(d) <= lim && rule.tail(d) <= 0.5 * lim) {
       conv = 1;
       break;
     }
@@ -905,7 +972,7 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
   const int64_t zlines = (int64_t)c->p.nx * c->p.ny;
   const int64_t zgroups = (zlines + 4 * (64 / nm.segz) - 1) / (4 * (64 / nm.segz));
   const int zgrid = z_grid(c, nm.segz, nm.mz, zgroups);
-  if (zgrid > c->zgrid) {
+  if (zgrid > c->zpart_cap) {
     double* np = nullptr;
     int rc = dalloc(c, &np, (size_t)zgrid * sizeof(double));
     if (rc) {
@@ -914,6 +981,7 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
     }
     (void)hipFree(c->zpart);
     c->zpart = np;
+    c->zpart_cap = zgrid;
   }
   const int old_zgrid = c->zgrid;
   c->zgrid = zgrid;
@@ -1067,6 +1135,72 @@ extern "C" int gp_autotune(gp_ctx* c, int32_t mode, int32_t steps, const char* c
   cache_store(cache_path, key, best);
   if (map_out)
     for (int q = 0; q < 6; ++q) map_out[q] = best[q];
+  return GP_OK;
+}
+
+int gp_set_truncation(gp_ctx* c, int32_t mode) {
+  if (!c || mode < 0 || mode > 2) return GP_ERR_INVALID;
+  const gp_params& p = c->p;
+  for (int m = 0; m < 2 && mode >= 1; ++m)
+    for (int a = 0; a < (mode == 1 ? 2 : 1); ++a)
+      if (gpk::stream_h(c->hlen[m][a]) < 0) {
+        snprintf(c->err, sizeof(c->err), "truncation length %d exceeds the streaming kernels' 15", c->hlen[m][a]);
+        return GP_ERR_UNSUPPORTED;
+      }
+  int chunk = 0, nchunks = 0;
+  if (mode == 2) {
+    if (gpk::yz_mz(p.nz) < 0) {
+      snprintf(c->err, sizeof(c->err), "the fused y+z pass holds z lines of at most 1024 points");
+      return GP_ERR_UNSUPPORTED;
+    }
+    int nwy = 0;
+    for (int m = 0; m < 2; ++m) {
+      if (gpk::yz_h(c->hlen[m][1]) < 0) {
+        snprintf(c->err, sizeof(c->err), "y truncation length %d exceeds the fused kernels' 11", c->hlen[m][1]);
+        return GP_ERR_UNSUPPORTED;
+      }
+      nwy = std::max(nwy, c->nw[m][1]);
+    }
+    // enough blocks to fill the device (about 2048), chunks of at least 32 rows, and the
+    // y head correction inside the first chunk (the only block that holds u_0)
+    nchunks = std::max(1, std::min(ceil_div(2048, p.nx), p.ny / 32));
+    chunk = ceil_div(p.ny, nchunks);
+    if (chunk < nwy) {
+      nchunks = 1;
+      chunk = p.ny;
+    }
+    nchunks = ceil_div(p.ny, chunk);
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (mode == 2) {
+    const int nb = p.nx * nchunks;
+    if (nb > c->zpart_cap) {  // room for the fused pass's norm partials
+      double* np = nullptr;
+      int rc = dalloc(c, &np, (size_t)nb * sizeof(double));
+      if (rc) return rc;
+      (void)hipFree(c->zpart);
+      c->zpart = np;
+      c->zpart_cap = nb;
+    }
+    for (int m = 0; m < 2; ++m) {
+      gpk::AxisConst ac;
+      gpk::cn_axis_constants(p.nz, p.dz, p.dt, m, gpk::yz_mz(p.nz), p.precision == GP_C64, &ac);
+      for (int q = 0; q < 8; ++q) c->yzcoef[m][q] = ac.coef[q];
+    }
+    c->yz_chunk = chunk;
+    c->yz_nchunks = nchunks;
+  }
+  c->trunc = mode;
+  destroy_graphs(c);
+  return GP_OK;
+}
+
+int gp_get_truncation(gp_ctx* c, int32_t* mode, int32_t hlen[6]) {
+  if (!c) return GP_ERR_INVALID;
+  if (mode) *mode = c->trunc;
+  if (hlen)
+    for (int m = 0; m < 2; ++m)
+      for (int a = 0; a < 3; ++a) hlen[3 * m + a] = c->hlen[m][a];
   return GP_OK;
 }
 

@@ -366,6 +366,73 @@ __device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ ps
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Streaming line solve with the back-substitution truncated after H terms (halo-truncated
+// Crank-Nicolson inverse).  One thread per line; the thread walks its line once, reading
+// p_{j+1} and writing u_{j-H} at step j:
+//   forward   d_j = a (p_{j-1} + p_{j+1} + d_{j-1}) + b p_j   (exact, from the line start)
+//   backward  u_j = sum_{m=0}^{H} a^m d_{j+m}                  (the exact sum runs to the
+//             line end; the dropped terms are below |a|^{H+1} / (1 - |a|) max|d|, and the
+//             host picks H so that this is 1/100 of the storage precision's unit roundoff)
+// followed by the head correction u_j += omega_j u_0 (j < nw, u_0 kept in a register).
+// Near the line end the sum stops at the last point, so it is exact there.  The loop is
+// unrolled by L = H + 1: the ring of the last L values of d and the queue of the next L
+// rows in flight are indexed by compile-time positions.  psi is read once and written
+// once, in 64-lane rows of consecutive lines (one coalesced access per row), with no LDS
+// and no barriers.  NSTEP: the potential step applied to each value as it is consumed.
+// ---------------------------------------------------------------------------------------
+template <typename R, int H, bool CC, int NSTEP>
+__device__ __forceinline__ void stream_line(typename VecOf<R>::T* __restrict__ lp, int n, int64_t inner,
+                                            const Coef<typename VecOf<R>::T>& cf,
+                                            const typename VecOf<R>::T* __restrict__ omega, int nw, Pot1D<R> px,
+                                            R vperp, R tau, R scale, R g) {
+  typedef typename VecOf<R>::T V;
+  constexpr int L = H + 1;
+  const V ca = cf.a;
+  auto load = [&](int j) { return lp[(int64_t)j * inner]; };
+  auto prep = [&](V v, int j) {
+    if (NSTEP != 0) v = nstep<NSTEP, R, V>(v, scale, px.at(j) + vperp, g, tau);
+    return v;
+  };
+  V q[L];     // rows j+1 .. j+L in flight (slot (j+1) % L holds p_{j+1})
+  V ring[L];  // d_{j-H} .. d_j (slot j % L holds d_j)
+#pragma unroll
+  for (int t = 0; t < L; ++t) {
+    ring[t] = vzero<V>();
+    q[(1 + t) % L] = (1 + t < n) ? load(1 + t) : vzero<V>();
+  }
+  V pm = vzero<V>(), pc = prep(load(0), 0), dprev = vzero<V>(), u0 = vzero<V>();
+  const int total = n + H;  // the last H steps only emit (d past the line end is zero)
+  for (int jb = 0; jb < total; jb += L) {
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const int j = jb + t;
+      if (j < total) {
+        V d = vzero<V>();
+        if (j < n) {
+          const int s1 = (t + 1) % L;
+          const V pn = (j + 1 < n) ? prep(q[s1], j + 1) : vzero<V>();
+          if (j + 1 + L < n) q[s1] = load(j + 1 + L);
+          d = fwd_point<CC, R, V>(cf, pm, pn, dprev, pc);
+          pm = pc;
+          pc = pn;
+          dprev = d;
+        }
+        ring[t] = d;
+        const int r = j - H;
+        if (r >= 0) {
+          V u = ring[t];
+#pragma unroll
+          for (int m = H - 1; m >= 0; --m) u = cfma<CC>(ca, u, ring[(t + 1 + m) % L]);
+          if (r == 0) u0 = u;
+          if (r < nw) u = cfma<CC>(omega[r], u0, u);
+          lp[(int64_t)r * inner] = u;
+        }
+      }
+    }
+  }
+}
+
 // Line bundle of block b when blocks are dealt to the XCDs round-robin (block b runs on
 // XCD b mod 8): XCD x takes one contiguous stretch of bundles, so the blocks resident on
 // one XCD (sharing its L2 and address-translation caches) read adjacent row chunks
@@ -388,6 +455,108 @@ k_head_correction(typename VecOf<R>::T* __restrict__ psi, const typename VecOf<R
     const V u0 = psi[base];
     for (int i = nw - 1; i >= 0; --i) psi[base + i * inner] = cfma<CC>(omega[i], u0, psi[base + i * inner]);
   }
+}
+
+// Solve of one z line held in LDS (row: its values, point q at q + zp (q / MZ)) by the
+// nseg lanes of line group l: lane p holds points s .. s + len - 1 (s = p MZ, LDS position
+// ss) in registers, runs both recurrences over them, and composes the segments' affine maps
+// across lanes by Hillis-Steele scans of shuffles; then the Sherman-Morrison head
+// correction.  The solution is left in v (registers); act = false lanes hold zeros.
+template <typename R, int MZ, bool CC>
+__device__ __forceinline__ void z_line_solve(typename VecOf<R>::T (&v)[MZ], const typename VecOf<R>::T* row, bool act,
+                                             int s, int ss, int zp, int len, int nz, int nseg, int l, int p,
+                                             const Coef<typename VecOf<R>::T>& cf, typename VecOf<R>::T cP,
+                                             const typename VecOf<R>::T* __restrict__ omega, int nwi) {
+  typedef typename VecOf<R>::T V;
+  const V ca = cf.a;
+#pragma unroll
+  for (int t = 0; t < MZ; ++t) {
+    v[t] = vzero<V>();
+    if (act && t < len) v[t] = row[ss + t];
+  }
+  // neighbours: the previous segment's last point and (for a full segment) the next
+  // segment's first point
+  const V left = (act && s > 0) ? row[ss - 1 - zp] : vzero<V>();
+  const V right = (act && s + len < nz) ? row[ss + len + zp] : vzero<V>();
+
+  V d = vzero<V>();
+  {
+    V prev = left;
+#pragma unroll
+    for (int t = 0; t < MZ; ++t) {
+      V nxt = right;
+      if (t + 1 < MZ) nxt = v[t + 1];
+      const V dn = fwd_point<CC, R, V>(cf, prev, nxt, d, v[t]);
+      prev = v[t];
+      v[t] = dn;
+      d = dn;
+    }
+  }
+  // inclusive scan of the segment maps x -> P x + B along the line.  Every segment
+  // before an active lane is full, so a span of `off` segments multiplies by P^off:
+  // the products are powers of P and only B travels between lanes.
+  V B = act ? d : vzero<V>();
+  {
+    V Apow = cP;
+    for (int off = 1; off < nseg; off <<= 1) {
+      const V Bp = shfl_up_v(B, off, nseg);
+      if (p >= off) B = cfma<CC>(Apow, Bp, B);
+      Apow = cmul<CC>(Apow, Apow);
+    }
+  }
+  V D = shfl_up_v(B, 1, nseg);
+  if (p == 0) D = vzero<V>();
+  {
+    V r = D;
+#pragma unroll
+    for (int t = 0; t < MZ; ++t) {
+      r = cmul<CC>(ca, r);
+      v[t] = vadd(v[t], r);
+    }
+  }
+  V u = vzero<V>();
+#pragma unroll
+  for (int t = MZ - 1; t >= 0; --t) {
+    u = cfma<CC>(ca, u, v[t]);
+    if (t >= len) u = vzero<V>();
+    v[t] = u;
+  }
+  // backward scan likewise; a span reaching into the empty lanes past the line's last
+  // segment gets P^off instead of the true product, but it only ever multiplies the
+  // zero contribution of those lanes
+  V Bu = act ? u : vzero<V>();
+  {
+    V Apow = cP;
+    for (int off = 1; off < nseg; off <<= 1) {
+      const V Bp = shfl_down_v(Bu, off, nseg);
+      if (p + off < nseg) Bu = cfma<CC>(Apow, Bp, Bu);
+      Apow = cmul<CC>(Apow, Apow);
+    }
+  }
+  V U = shfl_down_v(Bu, 1, nseg);
+  if (p == nseg - 1) U = vzero<V>();
+  {
+    V r = U;
+#pragma unroll
+    for (int t = MZ - 1; t >= 0; --t) {
+      r = cmul<CC>(ca, r);
+      v[t] = vadd(v[t], r);
+    }
+  }
+  // Sherman-Morrison head correction: u_i += omega_i u_0 for i < nwi
+  if (nwi > 0) {
+    const V u0 = vmake<V>(__shfl(v[0].x, l * nseg, 64), __shfl(v[0].y, l * nseg, 64));
+#pragma unroll
+    for (int t = 0; t < MZ; ++t) {
+      if (t < nwi) {  // uniform: segment-0 lanes need it whenever t < nwi
+        const int pos = s + t;
+        const V om = omega[min(pos, nwi - 1)];
+        const V c = cfma<CC>(om, u0, v[t]);
+        if (pos < nwi) v[t] = c;
+      }
+    }
+  }
+
 }
 
 // ---------------------------------------------------------------------------------------
@@ -482,93 +651,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
     const bool act = (ll < nl) && (len > 0);
     V* row = sdata + (act ? ll * pitch : 0);
     V v[MZ];
-#pragma unroll
-    for (int t = 0; t < MZ; ++t) {
-      v[t] = vzero<V>();
-      if (act && t < len) v[t] = row[ss + t];
-    }
-    // neighbours: the previous segment's last point and (for a full segment) the next
-    // segment's first point
-    const V left = (act && s > 0) ? row[ss - 1 - zp] : vzero<V>();
-    const V right = (act && s + len < nz) ? row[ss + len + zp] : vzero<V>();
-
-    V d = vzero<V>();
-    {
-      V prev = left;
-#pragma unroll
-      for (int t = 0; t < MZ; ++t) {
-        V nxt = right;
-        if (t + 1 < MZ) nxt = v[t + 1];
-        const V dn = fwd_point<CC, R, V>(cf, prev, nxt, d, v[t]);
-        prev = v[t];
-        v[t] = dn;
-        d = dn;
-      }
-    }
-    // inclusive scan of the segment maps x -> P x + B along the line.  Every segment
-    // before an active lane is full, so a span of `off` segments multiplies by P^off:
-    // the products are powers of P and only B travels between lanes.
-    V B = act ? d : vzero<V>();
-    {
-      V Apow = cP;
-      for (int off = 1; off < nseg; off <<= 1) {
-        const V Bp = shfl_up_v(B, off, nseg);
-        if (p >= off) B = cfma<CC>(Apow, Bp, B);
-        Apow = cmul<CC>(Apow, Apow);
-      }
-    }
-    V D = shfl_up_v(B, 1, nseg);
-    if (p == 0) D = vzero<V>();
-    {
-      V r = D;
-#pragma unroll
-      for (int t = 0; t < MZ; ++t) {
-        r = cmul<CC>(ca, r);
-        v[t] = vadd(v[t], r);
-      }
-    }
-    V u = vzero<V>();
-#pragma unroll
-    for (int t = MZ - 1; t >= 0; --t) {
-      u = cfma<CC>(ca, u, v[t]);
-      if (t >= len) u = vzero<V>();
-      v[t] = u;
-    }
-    // backward scan likewise; a span reaching into the empty lanes past the line's last
-    // segment gets P^off instead of the true product, but it only ever multiplies the
-    // zero contribution of those lanes
-    V Bu = act ? u : vzero<V>();
-    {
-      V Apow = cP;
-      for (int off = 1; off < nseg; off <<= 1) {
-        const V Bp = shfl_down_v(Bu, off, nseg);
-        if (p + off < nseg) Bu = cfma<CC>(Apow, Bp, Bu);
-        Apow = cmul<CC>(Apow, Apow);
-      }
-    }
-    V U = shfl_down_v(Bu, 1, nseg);
-    if (p == nseg - 1) U = vzero<V>();
-    {
-      V r = U;
-#pragma unroll
-      for (int t = MZ - 1; t >= 0; --t) {
-        r = cmul<CC>(ca, r);
-        v[t] = vadd(v[t], r);
-      }
-    }
-    // Sherman-Morrison head correction: u_i += omega_i u_0 for i < nwi
-    if (nwi > 0) {
-      const V u0 = vmake<V>(__shfl(v[0].x, l * nseg, 64), __shfl(v[0].y, l * nseg, 64));
-#pragma unroll
-      for (int t = 0; t < MZ; ++t) {
-        if (t < nwi) {  // uniform: segment-0 lanes need it whenever t < nwi
-          const int pos = s + t;
-          const V om = omega[min(pos, nwi - 1)];
-          const V c = cfma<CC>(om, u0, v[t]);
-          if (pos < nwi) v[t] = c;
-        }
-      }
-    }
+    z_line_solve<R, MZ, CC>(v, row, act, s, ss, zp, len, nz, nseg, l, p, cf, cP, omega, nwi);
 
     if (act) {
       R vxy = 0;

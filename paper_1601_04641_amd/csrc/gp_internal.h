@@ -62,6 +62,7 @@ struct SweepLaunch {
   int64_t inner;    // x sweep: ny*nz; y sweep: nz (line l -> base (l/inner)*n*inner + l%inner)
   int sw;           // segments per wavefront (x/y kernels)
   bool wide;        // x/y kernels: 64-bit addressing (a wavefront's rows span >= 2 GiB)
+  int hlen;         // streaming kernels: terms kept of the back-substitution (H)
   // potential step fused into the load (x sweep) or store (z sweep, Strang)
   double ph, pc, pd;  // potential of the swept axis: V(i) = ph ((i - pc) pd)^2
   int nstep;        // 0 none, 1 imaginary, 2 real
@@ -79,6 +80,33 @@ struct SweepLaunch {
 // precision: 0 complex64, 1 complex128; cc: complex coefficients (real time)
 hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipStream_t s);
 hipError_t launch_sweep_z(int precision, bool cc, const SweepLaunch& a, hipStream_t s);
+// Streaming x/y sweep with the back-substitution truncated after a.hlen terms
+hipError_t launch_stream_lines(int precision, bool cc, const SweepLaunch& a, hipStream_t s);
+int stream_h(int h);  // instance size for a required truncation length (-1: none)
+
+// Fused y + z sweep with the truncated y back-substitution (gp_stream.hip)
+struct YZLaunch {
+  void* psi;
+  int nx, ny, nz;
+  int chunk, nchunks;     // rows per block, blocks per plane
+  double ycoef[6];        // y: a, b, b_lo as (re, im)
+  const void* yomega;
+  int ynw;
+  double zcoef[8];        // z: a, b, b_lo, P = a^mz as (re, im)
+  const void* zomega;
+  int znw;
+  int mz;                 // z points per lane (yz_mz(nz))
+  int hlen;               // y truncation length
+  int epi;                // Strang: trailing half potential step (1 imaginary, 2 real)
+  double ph, pc, pd, tau; // z potential V(k) = ph ((k - pc) pd)^2; half step tau
+  const void* vx;
+  const void* vy;
+  const DevState* st;
+  double* partials;       // imaginary time: one FP64 sum per block
+};
+hipError_t launch_stream_yz(int precision, bool cc, const YZLaunch& a, hipStream_t s);
+int yz_h(int h);    // instance size for a y truncation length (-1: none)
+int yz_mz(int nz);  // z points per lane of the fused kernel (-1: nz > 1024)
 
 hipError_t launch_finalize_norm(const double* partials, int nb, double dV, double dt, DevState* st,
                                 hipStream_t s);
@@ -106,6 +134,7 @@ hipError_t launch_observables(int precision, const ObsLaunch& a, hipStream_t s);
 struct AxisConst {
   double coef[8];                             // a, b, b_lo, P = a^m as (re, im), rounded
   int nw;                                     // Sherman-Morrison correction length
+  int hlen;                                   // terms of a truncated back-substitution
   std::vector<std::complex<double>> omega;    // FP64 correction coefficients
 };
 void cn_axis_constants(int n, double d, double dt, int mode, int m, bool f32, AxisConst* out);
@@ -128,14 +157,20 @@ hipError_t launch_obs_scale(const double* sums, double* raw, double dV, const do
 // delta_n = mu_n - mu_{n-1}.  While two successive deltas have the same sign and shrink
 // (r = delta_n / delta_{n-1} in (0, 1): mu approaches its limit geometrically), the
 // distance of mu_n to that limit is estimated as |delta_n| r / (1 - r) (Aitken's
-// extrapolation) and must be at most tol |mu_n|, as must |delta_n|.  Otherwise (mu turning,
-// or at its rounding floor) |delta_n| <= tol |mu_n| must hold at two successive checks.
+// extrapolation) and must be at most tol |mu_n| / 2 (a margin for the neglected slower
+// modes), with |delta_n| <= tol |mu_n|, and the extrapolated limit mu_n + that tail must
+// agree within tol |mu_n| / 2 with the previous check's (two modes of opposite sign can
+// fake a geometric ratio for one check).  Otherwise (mu turning, as from a start already
+// close to the ground state, or at its rounding floor) |delta| <= tol |mu_n| / 10 must hold
+// at three successive checks: near a turning point of mu(t) two small changes can straddle
+// the extremum while mu is still far from its limit.
 struct StopRule {
   double prev = NAN, prev2 = NAN;
-  double r = -1.0;  // last contraction ratio (-1: none, or not in (0, 1))
+  double r = -1.0;      // last contraction ratio (-1: none, or not in (0, 1))
+  double lim_prev = NAN;  // extrapolated limit at the previous check (NaN: not geometric)
   int hits = 0;
   void reset() {
-    prev = prev2 = NAN;
+    prev = prev2 = lim_prev = NAN;
     r = -1.0;
     hits = 0;
   }
@@ -145,22 +180,26 @@ struct StopRule {
     bool done = false;
     if (std::isfinite(prev) && std::isfinite(cur)) {
       const double d1 = cur - prev, lim = tol * std::fabs(cur);
-      const bool small = std::fabs(d1) <= lim;
-      hits = small ? hits + 1 : 0;
+      hits = std::fabs(d1) <= 0.1 * lim ? hits + 1 : 0;
       r = -1.0;
+      double extrap = NAN;
       if (std::isfinite(prev2)) {
         const double d0 = prev - prev2;
         const double q = d0 != 0.0 ? d1 / d0 : -1.0;
         if (q > 0.0 && q < 1.0) {
           r = q;
-          done = small && tail(d1) <= lim;
-        } else {
-          done = hits >= 2;
+          extrap = cur + d1 * q / (1.0 - q);
+          // geometric at two successive checks, with the same extrapolated limit
+          done = std::fabs(d1) <= lim && tail(d1) <= 0.5 * lim && std::isfinite(lim_prev) &&
+                 std::fabs(extrap - lim_prev) <= 0.5 * lim;
         }
       }
+      lim_prev = extrap;
+      done = done || hits >= 3;
     } else {
       hits = 0;
       r = -1.0;
+      lim_prev = NAN;
     }
     prev2 = prev;
     prev = cur;

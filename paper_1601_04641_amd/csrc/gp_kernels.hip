@@ -42,8 +42,12 @@ namespace gpk {
 #define GP_XCD_REMAP 1
 #endif
 
-template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE>
-__global__ void __launch_bounds__(1024)
+// MAXW: the most wavefronts a block of this instance may have.  1024-thread blocks cap a
+// thread at 128 VGPRs; complex128 with 16 points per thread needs more in the x sweep (the
+// potential step's phase factor), and spilling there cost 30% extra HBM traffic (scratch
+// reads and writes), so blocks of at most 8 wavefronts run an instance bounded at 512.
+template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE, int MAXW>
+__global__ void __launch_bounds__(64 * MAXW)
 k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, int64_t psi_bytes, typename VecOf<R>::T ca,
               typename VecOf<R>::T cb, typename VecOf<R>::T cbl, typename VecOf<R>::T cP,
               const typename VecOf<R>::T* __restrict__ omega, int nwi, int n, int nseg, int64_t nlines,
@@ -58,6 +62,31 @@ k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, int64_t psi_bytes, typenam
   const int64_t b = GP_XCD_REMAP ? xcd_bundle(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   lines_body<R, M, SW, CC, NSTEP, WIDE>(psi, psi_bytes, ca, cb, cbl, cP, omega, nwi, n, nseg, nlines, inner, px, vy,
                                         vz, nz, tau, scale, g, b, smem_raw);
+}
+
+// Streaming x or y sweep with the truncated back-substitution (stream_line): thread =
+// line; lines l = j*nz + k (x sweep, inner = ny*nz) or i*nz + k (y sweep, inner = nz).
+template <typename R, int H, bool CC, int NSTEP>
+__global__ void __launch_bounds__(256)
+k_stream_lines(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typename VecOf<R>::T cb,
+               typename VecOf<R>::T cbl, const typename VecOf<R>::T* __restrict__ omega, int nw, int n,
+               int64_t nlines, int64_t inner, Pot1D<R> px, const R* __restrict__ vy, const R* __restrict__ vz,
+               int nz, R tau, const DevState* __restrict__ st) {
+  const int64_t b = GP_XCD_REMAP ? xcd_bundle(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t line = b * 256 + threadIdx.x;
+  if (line >= nlines) return;
+  R scale = 1, g = 0, vperp = 0;
+  if (NSTEP != 0) {
+    scale = (R)st->s;
+    g = (R)st->g;
+    vperp = vy[line / nz] + vz[line % nz];  // x-sweep line index = j*nz + k
+  }
+  const int64_t base = (line / inner) * (inner * n) + (line % inner);
+  Coef<typename VecOf<R>::T> cf;
+  cf.a = ca;
+  cf.b = cb;
+  cf.bl = cbl;
+  stream_line<R, H, CC, NSTEP>(psi + base, n, inner, cf, omega, nw, px, vperp, tau, scale, g);
 }
 
 template <typename R, int MZ, bool CC, bool NORM, int EPI>
@@ -239,7 +268,10 @@ static hipError_t go_lines(const SweepLaunch& a, hipStream_t s) {
   const size_t lds = (size_t)3 * waves * SW * LW * sizeof(V);
   const int64_t blocks = (a.nlines + LW - 1) / LW;
   const int nwi = (a.nw <= M) ? a.nw : 0;
-  hipLaunchKernelGGL((k_sweep_lines<R, M, SW, CC, NSTEP, WIDE>), dim3((unsigned)blocks), dim3(waves * 64), lds, s,
+  auto kern = k_sweep_lines<R, M, SW, CC, NSTEP, WIDE, 16>;
+  if constexpr (sizeof(R) == 8 && M == 16 && NSTEP != 0)
+    if (waves <= 8) kern = k_sweep_lines<R, M, SW, CC, NSTEP, WIDE, 8>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(waves * 64), lds, s,
                      (V*)a.psi, a.psi_bytes, cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4),
                      cval<R>(a.coef + 6), (const V*)a.omega, nwi, a.n, a.nseg, a.nlines, a.inner,
                      Pot1D<R>{(R)a.ph, (R)a.pc, (R)a.pd}, (const R*)a.vy, (const R*)a.vz, a.nz, (R)a.tau, a.st);
@@ -314,6 +346,52 @@ hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipS
   return hipErrorInvalidValue;
 }
 #undef GP_LINES_SW
+
+template <typename R, int H, bool CC, int NSTEP>
+static hipError_t go_stream(const SweepLaunch& a, hipStream_t s) {
+  typedef typename VecOf<R>::T V;
+  const int64_t blocks = (a.nlines + 255) / 256;
+  hipLaunchKernelGGL((k_stream_lines<R, H, CC, NSTEP>), dim3((unsigned)blocks), dim3(256), 0, s, (V*)a.psi,
+                     cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4), (const V*)a.omega, a.nw, a.n,
+                     a.nlines, a.inner, Pot1D<R>{(R)a.ph, (R)a.pc, (R)a.pd}, (const R*)a.vy, (const R*)a.vz, a.nz,
+                     (R)a.tau, a.st);
+  return hipGetLastError();
+}
+
+template <typename R, int H>
+static hipError_t go_stream_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
+  if (!cc) return a.nstep ? go_stream<R, H, false, 1>(a, s) : go_stream<R, H, false, 0>(a, s);
+  return a.nstep ? go_stream<R, H, true, 2>(a, s) : go_stream<R, H, true, 0>(a, s);
+}
+
+// truncation lengths with kernel instances: the smallest one >= the required H is used
+int stream_h(int h) {
+  for (int v : {3, 5, 7, 11, 15})
+    if (h <= v) return v;
+  return -1;
+}
+
+hipError_t launch_stream_lines(int precision, bool cc, const SweepLaunch& a, hipStream_t s) {
+  const int h = stream_h(a.hlen);
+  if (precision == 0) {
+    switch (h) {
+      case 3: return go_stream_mode<float, 3>(cc, a, s);
+      case 5: return go_stream_mode<float, 5>(cc, a, s);
+      case 7: return go_stream_mode<float, 7>(cc, a, s);
+      case 11: return go_stream_mode<float, 11>(cc, a, s);
+      case 15: return go_stream_mode<float, 15>(cc, a, s);
+    }
+  } else {
+    switch (h) {
+      case 3: return go_stream_mode<double, 3>(cc, a, s);
+      case 5: return go_stream_mode<double, 5>(cc, a, s);
+      case 7: return go_stream_mode<double, 7>(cc, a, s);
+      case 11: return go_stream_mode<double, 11>(cc, a, s);
+      case 15: return go_stream_mode<double, 15>(cc, a, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
 
 template <typename R, int MZ, bool CC, bool NORM, int EPI>
 static hipError_t go_z(const SweepLaunch& a, hipStream_t s) {

@@ -31,7 +31,8 @@ EXPORTS = ("gp_init", "gp_destroy", "gp_step_imag", "gp_step_real", "gp_norm", "
            "gp_batch_status", "gp_batch_residual", "gp_batch_converge_imag", "gp_batch_get_mapping",
            "gp_batch_set_mapping", "gp_batch_autotune", "gp_batch_set_yz_fusion", "gp_batch_get_yz_fusion", "gp_batch_set_timing",
            "gp_batch_get_timing", "gp_batch_last_error",
-           "gp_set_alloc_cap", "gp_eval_sincos", "gp_stream_copy", "gp_raw_sums_noalloc")
+           "gp_set_alloc_cap", "gp_eval_sincos", "gp_stream_copy", "gp_raw_sums_noalloc",
+           "gp_set_truncation", "gp_get_truncation")
 
 
 class GPError(RuntimeError):
@@ -100,6 +101,8 @@ def load(path: str = LIB_PATH):
         "gp_eval_sincos": [i32, vp, i64, vp, vp, vp],
         "gp_stream_copy": [vp, vp, i64, vp],
         "gp_raw_sums_noalloc": [P(gp_params), vp, vp, vp],
+        "gp_set_truncation": [vp, i32],
+        "gp_get_truncation": [vp, P(i32), P(i32)],
         "gp_batch_set_yz_fusion": [vp, i32],
         "gp_batch_get_yz_fusion": [vp, P(i32), P(i32)],
         "gp_batch_set_timing": [vp, i32],
@@ -286,6 +289,17 @@ class Solver:
     def set_mapping(self, mx=0, swx=0, my=0, swy=0, segz=0, mz=0):
         arr = (ctypes.c_int32 * 6)(int(mx), int(swx), int(my), int(swy), int(segz), int(mz))
         self._chk(self._L.gp_set_mapping(self._h, arr), "gp_set_mapping")
+
+    def set_truncation(self, mode: int):
+        """0: exact sweeps; 1: streaming x/y sweeps with the halo-truncated inverse."""
+        self._chk(self._L.gp_set_truncation(self._h, int(mode)), "gp_set_truncation")
+
+    def get_truncation(self):
+        """(mode, H as [[x, y, z] imaginary, [x, y, z] real])"""
+        m = ctypes.c_int32()
+        h = (ctypes.c_int32 * 6)()
+        self._chk(self._L.gp_get_truncation(self._h, ctypes.byref(m), h), "gp_get_truncation")
+        return m.value, [list(h[0:3]), list(h[3:6])]
 
     def autotune(self, mode="real", steps=5, cache_path=None):
         """Time every line mapping on this grid and keep the fastest (see gp_autotune)."""
