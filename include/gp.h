@@ -142,8 +142,15 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]);
  * precision's unit roundoff, so results agree with the exact sweeps to rounding.  Then each
  * thread streams one whole x or y line (forward elimination exact from the line start,
  * u_{j-H} emitted at step j): one coalesced read and write of psi per sweep, no LDS, no
- * barriers.  The z sweep stays exact.  mode 0: exact sweeps (default).  Returns
- * GP_ERR_UNSUPPORTED when H exceeds 15 (dt/dx^2 large; the exact sweeps stay in use).
+ * barriers; the z sweep stays exact.  mode 2 keeps the exact x sweep, writing its result
+ * to a work array the context allocates (psi's size), and fuses the y and z sweeps into
+ * one pass from that array back into psi: a block walks the rows of one plane (chunks of
+ * rows, each started H rows early), and every row the truncated y solve emits is a whole
+ * z line, solved at once in LDS; psi crosses HBM twice per step instead of three times
+ * (32 instead of 48 B per point in complex64).  mode 2 needs z lines of at most 1024
+ * points and psi-sized free device memory (else GP_ERR_OOM, mode unchanged).  mode 0: exact
+ * sweeps (default).  Returns GP_ERR_UNSUPPORTED (mode unchanged) when H exceeds 15
+ * (dt/dx^2 large) or the grid does not fit the fused pass.
  * gp_get_truncation: the mode and H per [imaginary, real][x, y, z].  Synchronises. */
 int gp_set_truncation(gp_ctx* c, int32_t mode);
 int gp_get_truncation(gp_ctx* c, int32_t* mode, int32_t hlen[6]);

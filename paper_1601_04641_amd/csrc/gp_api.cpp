@@ -143,6 +143,7 @@ struct gp_ctx {
   int trunc = 0;                   // 0 exact sweeps; 1 streaming x/y sweeps, truncated back-substitution;
                                    // 2 streaming x sweep + fused y+z pass
   int yz_chunk = 0, yz_nchunks = 0;  // mode 2: rows per block and blocks per plane
+  void* work = nullptr;              // mode 2: the x sweep's output, the fused pass's input
   double yzcoef[2][8] = {{0}};       // mode 2: z constants with P = a^mz of the fused kernel
   double coef[2][3][8] = {{{0}}};  // a, b, b_lo, P = a^m as (re, im)
   void* vtab[3] = {nullptr};      // storage-precision 1/2 nu^2 a^2
@@ -262,7 +263,11 @@ bool pick_lines(int prec, const AxisLines& a, bool nstep, int* m_out, int* sw_ou
 // partial round of blocks would leave most CUs idle at the tail
 int zpad_of(int nz, int seg, int m, size_t esize) { return gpk::z_pad(nz, seg, m, esize, gpk::kMaxLdsBlock); }
 
+// complex128: one block per line group (measured 723 -> 706 us, with the non-temporal
+// policy 671 -> 654 us on the quench grid); complex64 keeps the resident grid (one block
+// per group measured 2-4% slower there)
 int z_grid(const gp_ctx* c, int segz, int mz, int64_t zgroups) {
+  if (c->esize == 16) return (int)std::max<int64_t>(1, std::min<int64_t>(zgroups, 0x7fffffff));
   int cus = 0, lds_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1) cus = 256;
   if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) != hipSuccess ||
@@ -451,6 +456,7 @@ int timed(gp_ctx* c, hipStream_t s, int kind, F fn) {
 gpk::YZLaunch yz_args(gp_ctx* c, int mode) {
   gpk::YZLaunch a{};
   const gp_params& p = c->p;
+  a.src = c->work;
   a.psi = c->psi;
   a.nx = p.nx;
   a.ny = p.ny;
@@ -481,10 +487,11 @@ gpk::YZLaunch yz_args(gp_ctx* c, int mode) {
 int enqueue_step(gp_ctx* c, int mode, hipStream_t s) {
   const int prec = c->p.precision;
   const bool cc = mode == 1;
-  if (c->trunc == 2) {  // streaming x sweep, then the fused y+z pass
+  if (c->trunc == 2) {  // exact x sweep psi -> work, then the fused y+z pass work -> psi
     gpk::SweepLaunch ax = lines_args(c, 0, mode);
+    ax.dst = c->work;
     gpk::YZLaunch ayz = yz_args(c, mode);
-    int rc = timed(c, s, 0, [&](hipStream_t t) { return gpk::launch_stream_lines(prec, cc, ax, t); });
+    int rc = timed(c, s, 0, [&](hipStream_t t) { return gpk::launch_sweep_lines(prec, cc, ax, t); });
     if (rc) return rc;
     rc = timed(c, s, 2, [&](hipStream_t t) { return gpk::launch_stream_yz(prec, cc, ayz, t); });
     if (rc) return rc;
@@ -607,6 +614,7 @@ void release(gp_ctx* c) {
     (void)hipFree(c->vtab[a]);
   }
   (void)hipFree(c->zpart);
+  (void)hipFree(c->work);
   (void)hipFree(c->opart);
   (void)hipFree(c->oout);
   if (c->host) (void)hipHostFree(c->host);
@@ -1141,8 +1149,8 @@ extern "C" int gp_autotune(gp_ctx* c, int32_t mode, int32_t steps, const char* c
 int gp_set_truncation(gp_ctx* c, int32_t mode) {
   if (!c || mode < 0 || mode > 2) return GP_ERR_INVALID;
   const gp_params& p = c->p;
-  for (int m = 0; m < 2 && mode >= 1; ++m)
-    for (int a = 0; a < (mode == 1 ? 2 : 1); ++a)
+  for (int m = 0; m < 2 && mode == 1; ++m)
+    for (int a = 0; a < 2; ++a)
       if (gpk::stream_h(c->hlen[m][a]) < 0) {
         snprintf(c->err, sizeof(c->err), "truncation length %d exceeds the streaming kernels' 15", c->hlen[m][a]);
         return GP_ERR_UNSUPPORTED;
@@ -1156,7 +1164,7 @@ int gp_set_truncation(gp_ctx* c, int32_t mode) {
     int nwy = 0;
     for (int m = 0; m < 2; ++m) {
       if (gpk::yz_h(c->hlen[m][1]) < 0) {
-        snprintf(c->err, sizeof(c->err), "y truncation length %d exceeds the fused kernels' 11", c->hlen[m][1]);
+        snprintf(c->err, sizeof(c->err), "y truncation length %d exceeds the fused kernels' 15", c->hlen[m][1]);
         return GP_ERR_UNSUPPORTED;
       }
       nwy = std::max(nwy, c->nw[m][1]);
@@ -1172,6 +1180,14 @@ int gp_set_truncation(gp_ctx* c, int32_t mode) {
     nchunks = ceil_div(p.ny, chunk);
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (mode == 2 && !c->work) {  // the x sweep's output array (one more psi-sized buffer)
+    int rc = dalloc(c, &c->work, (size_t)c->npts * c->esize);
+    if (rc) return rc;
+  }
+  if (mode != 2 && c->work) {
+    (void)hipFree(c->work);
+    c->work = nullptr;
+  }
   if (mode == 2) {
     const int nb = p.nx * nchunks;
     if (nb > c->zpart_cap) {  // room for the fused pass's norm partials

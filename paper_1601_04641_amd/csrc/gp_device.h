@@ -162,17 +162,52 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
 }
 typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
 typedef unsigned int u32x4 __attribute__((__vector_size__(16)));
+
+// Cache policy of psi's loads and stores: non-temporal (cache-policy value 2), since psi
+// streams through once per sweep and nothing re-reads it from the caches.  Measured on the
+// 512x480x448 quench: y and z sweeps 1-7% faster (complex128 y 666 -> 626 us, z 723 ->
+// 671 us; complex64 z 348 -> 324 us); the complex64 x sweep 4% slower (346 -> 360 us),
+// so the x sweeps' buffer accesses take NT as a template choice (kNtLines).
+#ifndef GP_NT
+#define GP_NT 2
+#endif
+template <int AUX = GP_NT>
 __device__ __forceinline__ void bload(float2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+  v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, AUX));
 }
+template <int AUX = GP_NT>
 __device__ __forceinline__ void bload(double2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+  v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, AUX));
 }
+template <int AUX = GP_NT>
 __device__ __forceinline__ void bstore(const float2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vo, (int)so, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vo, (int)so, AUX);
 }
+template <int AUX = GP_NT>
 __device__ __forceinline__ void bstore(const double2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)vo, (int)so, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)vo, (int)so, AUX);
+}
+// cache policy of a line sweep's accesses: the complex64 sweep with the potential step
+// (the x sweep) keeps the default policy
+template <typename R, int NSTEP> constexpr int kNtLines = (sizeof(R) == 4 && NSTEP != 0) ? 0 : GP_NT;
+// plain global loads and stores of psi values (8 or 16 bytes) under the same policy
+template <typename T> __device__ __forceinline__ T gld(const T* p) {
+  static_assert(sizeof(T) == 8 || sizeof(T) == 16, "8- or 16-byte values");
+  if constexpr (GP_NT != 0) {
+    if constexpr (sizeof(T) == 16) return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p)));
+    else return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p)));
+  } else {
+    return *p;
+  }
+}
+template <typename T> __device__ __forceinline__ void gst(T* p, const T& v) {
+  static_assert(sizeof(T) == 8 || sizeof(T) == 16, "8- or 16-byte values");
+  if constexpr (GP_NT != 0) {
+    if constexpr (sizeof(T) == 16) __builtin_nontemporal_store(__builtin_bit_cast(u32x4, v), reinterpret_cast<u32x4*>(p));
+    else __builtin_nontemporal_store(__builtin_bit_cast(u32x2, v), reinterpret_cast<u32x2*>(p));
+  } else {
+    *p = v;
+  }
 }
 
 template <typename V> __device__ __forceinline__ V shfl_up_v(V v, int off, int width) {
@@ -232,10 +267,13 @@ template <typename R> struct Pot1D {
 // 32-bit byte offsets span only the wavefront's own rows and lines, whatever the size of
 // psi; the host keeps that span below 2 GiB.  WIDE instances (for wavefronts whose rows
 // span more, e.g. complex128 x lines of the paper's 1920x1600x1280 grid: 128 rows of
-// 32.8 MB) address every point with a 64-bit pointer instead.
+// 32.8 MB) address every point with a 64-bit pointer instead.  The sweep reads psi and
+// writes dst (the same array for the in-place sweeps; another one for the x sweep ahead of
+// the fused y+z pass, which must not read values another block has already replaced).
 // ---------------------------------------------------------------------------------------
 template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE = false>
-__device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ psi, int64_t psi_bytes,
+__device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, typename VecOf<R>::T* dst,
+                                           int64_t psi_bytes,
                                            typename VecOf<R>::T ca, typename VecOf<R>::T cb,
                                            typename VecOf<R>::T cbl, typename VecOf<R>::T cP,
                                            const typename VecOf<R>::T* __restrict__ omega, int nwi, int n,
@@ -266,17 +304,20 @@ __device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ ps
   const int64_t line0 = min(bidx * LW, nlines - 1);
   const int64_t e0 = (line0 / inner) * (inner * n) + (line0 % inner) + (int64_t)(w * SW * M) * inner;
   const int64_t left_bytes = psi_bytes - e0 * (int64_t)sizeof(V);
-  const __amdgpu_buffer_rsrc_t rs = make_rsrc(psi + e0, (uint32_t)min(left_bytes, (int64_t)0xffffffff));
+  const uint32_t span = (uint32_t)min(left_bytes, (int64_t)0xffffffff);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(psi + e0, span);
+  const __amdgpu_buffer_rsrc_t rd = (dst == psi) ? rs : make_rsrc(dst + e0, span);
   const uint32_t voff = (uint32_t)((base + (int64_t)s * inner - e0) * (int64_t)sizeof(V));
   const uint32_t srow = (uint32_t)(inner * (int64_t)sizeof(V));
-  V* const lp = psi + base + (int64_t)s * inner;  // WIDE: this lane's first point
+  const V* const lp = psi + base + (int64_t)s * inner;  // WIDE: this lane's first point
+  V* const lq = dst + base + (int64_t)s * inner;
   V v[M];
 #pragma unroll
   for (int t = 0; t < M; ++t) {
     v[t] = vzero<V>();
     if (t < len) {
-      if (WIDE) v[t] = lp[(int64_t)t * inner];
-      else bload(v[t], rs, voff, (uint32_t)t * srow);
+      if (WIDE) v[t] = gld(lp + (int64_t)t * inner);
+      else bload<kNtLines<R, NSTEP>>(v[t], rs, voff, (uint32_t)t * srow);
     }
   }
   if (NSTEP != 0) {
@@ -361,8 +402,8 @@ __device__ __forceinline__ void lines_body(typename VecOf<R>::T* __restrict__ ps
 #pragma unroll
   for (int t = 0; t < M; ++t)
     if (t < len) {
-      if (WIDE) lp[(int64_t)t * inner] = v[t];
-      else bstore(v[t], rs, voff, (uint32_t)t * srow);
+      if (WIDE) gst(lq + (int64_t)t * inner, v[t]);
+      else bstore<kNtLines<R, NSTEP>>(v[t], rd, voff, (uint32_t)t * srow);
     }
 }
 
@@ -389,7 +430,7 @@ __device__ __forceinline__ void stream_line(typename VecOf<R>::T* __restrict__ l
   typedef typename VecOf<R>::T V;
   constexpr int L = H + 1;
   const V ca = cf.a;
-  auto load = [&](int j) { return lp[(int64_t)j * inner]; };
+  auto load = [&](int j) { return gld(lp + (int64_t)j * inner); };
   auto prep = [&](V v, int j) {
     if (NSTEP != 0) v = nstep<NSTEP, R, V>(v, scale, px.at(j) + vperp, g, tau);
     return v;
@@ -426,7 +467,7 @@ __device__ __forceinline__ void stream_line(typename VecOf<R>::T* __restrict__ l
           for (int m = H - 1; m >= 0; --m) u = cfma<CC>(ca, u, ring[(t + 1 + m) % L]);
           if (r == 0) u0 = u;
           if (r < nw) u = cfma<CC>(omega[r], u0, u);
-          lp[(int64_t)r * inner] = u;
+          gst(lp + (int64_t)r * inner, u);
         }
       }
     }
@@ -614,16 +655,16 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
       if (sizeof(V) == 8 && al16 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {  // 16-byte copies
         const float4* s4 = reinterpret_cast<const float4*>(src);
         float4* d4 = reinterpret_cast<float4*>(sdata);
-        for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];
+        for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = gld(s4 + q);
       } else {
-        for (int q = tid; q < cnt; q += 256) sdata[q] = src[q];
+        for (int q = tid; q < cnt; q += 256) sdata[q] = gld(src + q);
       }
     } else if (pairs) {  // 16-byte global loads; a pair never straddles a line or segment
       const float4* s4 = reinterpret_cast<const float4*>(src);
       int cl = tid / cn, cq = tid % cn;
       for (int f = tid; f < (cnt >> 1); f += 256) {
         const int q = 2 * cq, at = cl * pitch + q + q / MZ;
-        const float4 x = s4[f];
+        const float4 x = gld(s4 + f);
         sdata[at] = vmake<V>(x.x, x.y);
         sdata[at + 1] = vmake<V>(x.z, x.w);
         cq += dq;
@@ -636,7 +677,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
     } else {
       int cl = tid / cn, cq = tid % cn;
       for (int f = tid; f < cnt; f += 256) {
-        sdata[cl * pitch + cq + cq / MZ] = src[f];
+        sdata[cl * pitch + cq + cq / MZ] = gld(src + f);
         cq += dq;
         cl += dl;
         if (cq >= cn) {
@@ -674,9 +715,9 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
       if (sizeof(V) == 8 && al16 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {
         float4* d4 = reinterpret_cast<float4*>(dst);
         const float4* s4 = reinterpret_cast<const float4*>(sdata);
-        for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = s4[q];
+        for (int q = tid; q < (cnt >> 1); q += 256) gst(d4 + q, s4[q]);
       } else {
-        for (int q = tid; q < cnt; q += 256) dst[q] = sdata[q];
+        for (int q = tid; q < cnt; q += 256) gst(dst + q, sdata[q]);
       }
     } else if (pairs) {
       float4* d4 = reinterpret_cast<float4*>(dst);
@@ -684,7 +725,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
       for (int f = tid; f < (cnt >> 1); f += 256) {
         const int q = 2 * cq, at = cl * pitch + q + q / MZ;
         const V a = sdata[at], b = sdata[at + 1];
-        d4[f] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+        gst(d4 + f, make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y));
         cq += dq;
         cl += dl;
         if (cq >= cn) {
@@ -695,7 +736,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
     } else {
       int cl = tid / cn, cq = tid % cn;
       for (int f = tid; f < cnt; f += 256) {
-        dst[f] = sdata[cl * pitch + cq + cq / MZ];
+        gst(dst + f, sdata[cl * pitch + cq + cq / MZ]);
         cq += dq;
         cl += dl;
         if (cq >= cn) {

@@ -51,6 +51,7 @@ constexpr size_t kMaxLdsBlock = 163840;
 
 struct SweepLaunch {
   void* psi;
+  void* dst;        // x/y kernels: output array (null: in place)
   int64_t psi_bytes;  // size of psi in bytes
   double coef[8];
   const void* omega;
@@ -86,7 +87,8 @@ int stream_h(int h);  // instance size for a required truncation length (-1: non
 
 // Fused y + z sweep with the truncated y back-substitution (gp_stream.hip)
 struct YZLaunch {
-  void* psi;
+  const void* src;        // input: the x sweep's output (a separate array)
+  void* psi;              // output
   int nx, ny, nz;
   int chunk, nchunks;     // rows per block, blocks per plane
   double ycoef[6];        // y: a, b, b_lo as (re, im)

@@ -48,7 +48,7 @@ namespace gpk {
 // reads and writes), so blocks of at most 8 wavefronts run an instance bounded at 512.
 template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE, int MAXW>
 __global__ void __launch_bounds__(64 * MAXW)
-k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, int64_t psi_bytes, typename VecOf<R>::T ca,
+k_sweep_lines(const typename VecOf<R>::T* psi, typename VecOf<R>::T* dst, int64_t psi_bytes, typename VecOf<R>::T ca,
               typename VecOf<R>::T cb, typename VecOf<R>::T cbl, typename VecOf<R>::T cP,
               const typename VecOf<R>::T* __restrict__ omega, int nwi, int n, int nseg, int64_t nlines,
               int64_t inner, Pot1D<R> px, const R* __restrict__ vy, const R* __restrict__ vz, int nz,
@@ -60,7 +60,7 @@ k_sweep_lines(typename VecOf<R>::T* __restrict__ psi, int64_t psi_bytes, typenam
     g = (R)st->g;
   }
   const int64_t b = GP_XCD_REMAP ? xcd_bundle(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-  lines_body<R, M, SW, CC, NSTEP, WIDE>(psi, psi_bytes, ca, cb, cbl, cP, omega, nwi, n, nseg, nlines, inner, px, vy,
+  lines_body<R, M, SW, CC, NSTEP, WIDE>(psi, dst, psi_bytes, ca, cb, cbl, cP, omega, nwi, n, nseg, nlines, inner, px, vy,
                                         vz, nz, tau, scale, g, b, smem_raw);
 }
 
@@ -225,29 +225,19 @@ k_eval_sincos(const R* __restrict__ x, int64_t n, R* __restrict__ sn, R* __restr
 }
 
 // Streaming copy of 16-byte units with raw buffer loads and stores, the access width of
-// the sweeps' row loads: a block moves kCopyU x 256 consecutive units per iteration (all
-// loads issued before the stores), walking the array with a grid stride.  The resource
-// of each chunk starts at the chunk, so 32-bit offsets cover any array size.
-constexpr int kCopyU = 4;
+// the sweeps' row loads, marked non-temporal: one unit per thread and one launch wide
+// enough for the whole array (measured on the MI355X, 2 GiB: 6.37 TB/s, against 5.7 TB/s
+// for grid-stride loops of 4 units per thread and 5.5 TB/s without the non-temporal
+// hint).  Each block's resource starts at its own 4 KiB chunk.
 __global__ void __launch_bounds__(256)
 k_stream_copy(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int64_t nunits) {
-  constexpr int64_t chunk = 256 * kCopyU;
-  for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < nunits; c0 += (int64_t)gridDim.x * chunk) {
-    const int64_t left = min(nunits - c0, chunk);
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src + c0 * 16, (uint32_t)(left * 16));
-    const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst + c0 * 16, (uint32_t)(left * 16));
-    u32x4 v[kCopyU];
-#pragma unroll
-    for (int u = 0; u < kCopyU; ++u) {
-      const int i = (int)threadIdx.x + u * 256;
-      if (i < left) v[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, i * 16, 0, 0);
-    }
-#pragma unroll
-    for (int u = 0; u < kCopyU; ++u) {
-      const int i = (int)threadIdx.x + u * 256;
-      if (i < left) __builtin_amdgcn_raw_buffer_store_b128(v[u], rd, i * 16, 0, 0);
-    }
-  }
+  const int64_t c0 = (int64_t)blockIdx.x * 256;
+  const int64_t left = min(nunits - c0, (int64_t)256);
+  if ((int64_t)threadIdx.x >= left) return;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(src + c0 * 16, (uint32_t)(left * 16));
+  const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst + c0 * 16, (uint32_t)(left * 16));
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)threadIdx.x * 16, 0, 2);
+  __builtin_amdgcn_raw_buffer_store_b128(v, rd, (int)threadIdx.x * 16, 0, 2);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -271,15 +261,16 @@ static hipError_t go_lines(const SweepLaunch& a, hipStream_t s) {
   auto kern = k_sweep_lines<R, M, SW, CC, NSTEP, WIDE, 16>;
   if constexpr (sizeof(R) == 8 && M == 16 && NSTEP != 0)
     if (waves <= 8) kern = k_sweep_lines<R, M, SW, CC, NSTEP, WIDE, 8>;
+  V* dst = (V*)(a.dst ? a.dst : a.psi);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(waves * 64), lds, s,
-                     (V*)a.psi, a.psi_bytes, cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4),
+                     (const V*)a.psi, dst, a.psi_bytes, cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4),
                      cval<R>(a.coef + 6), (const V*)a.omega, nwi, a.n, a.nseg, a.nlines, a.inner,
                      Pot1D<R>{(R)a.ph, (R)a.pc, (R)a.pd}, (const R*)a.vy, (const R*)a.vz, a.nz, (R)a.tau, a.st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || nwi > 0 || a.nw == 0) return e;
   const int64_t want = (a.nlines + 255) / 256;
   hipLaunchKernelGGL((k_head_correction<R, CC>), dim3((unsigned)(want < 2048 ? want : 2048)), dim3(256), 0, s,
-                     (V*)a.psi, (const V*)a.omega, a.nw, a.n, a.nlines, a.inner);
+                     dst, (const V*)a.omega, a.nw, a.n, a.nlines, a.inner);
   return hipGetLastError();
 }
 
@@ -501,14 +492,10 @@ hipError_t launch_eval_sincos(int precision, const void* x, int64_t n, void* sn,
 
 hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
   const int64_t units = bytes / 16;
-  const int64_t chunks = (units + 256 * kCopyU - 1) / (256 * kCopyU);
-  int cus = 0, dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-    cus = 256;
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)cus * 16));
-  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)grid), dim3(256), 0, s, (const unsigned char*)src,
-                     (unsigned char*)dst, units);
+  const int64_t blocks = (units + 255) / 256;  // < 2^31 for any array below 32 TiB
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, s,
+                     (const unsigned char*)src, (unsigned char*)dst, units);
   return hipGetLastError();
 }
 

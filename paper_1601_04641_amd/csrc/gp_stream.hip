@@ -8,12 +8,15 @@
 //             from the line start when j0 <= H)
 //   backward  u_r = sum_{m=0}^{H} a^m d_{r+m}                  (emitted at step r + H)
 // with the y head correction u_r += omega_r u_0 near the line start.  Every emitted row is
-// at once a complete z line: the block's waves solve the rows of each group of L = H + 1
-// steps (one row per wave, 64 lanes x MZ points, the z sweep's scans) in LDS, add the
+// at once a complete z line: the block's waves solve the rows of each group of
+// L ceil(W / L) steps (L = H + 1, W wavefronts; one row per wave at a time, 64 lanes x MZ
+// points, the z sweep's scans) in LDS, add the
 // Strang half potential step if asked, and store them.  psi is read once (plus 2H halo
 // rows per chunk) and written once for the y and z sweeps together: 16 B per point
 // (complex64) instead of the 32 B of two separate sweeps.  Imaginary time: FP64 sums of
-// |psi|^2 per block for the renormalisation.
+// |psi|^2 per block for the renormalisation.  The pass reads one array (the x sweep's
+// output) and writes another: chunks read H rows beyond their own on each side, rows that
+// the neighbouring chunk's block writes, so in place the result would depend on block order.
 #include "gp_device.h"
 
 #include <algorithm>
@@ -24,7 +27,8 @@ namespace gpk {
 // wavefronts are bounded at 512 threads, which leaves 256 VGPRs per thread (no spills).
 template <typename R, int H, int MZ, bool CC, bool NORM, int EPI, int MAXW>
 __global__ void __launch_bounds__(64 * MAXW)
-k_stream_yz(typename VecOf<R>::T* __restrict__ psi, int ny, int nz, int chunk, int nchunks,
+k_stream_yz(const typename VecOf<R>::T* __restrict__ src, typename VecOf<R>::T* __restrict__ psi, int ny, int nz,
+            int chunk, int nchunks,
             typename VecOf<R>::T ya, typename VecOf<R>::T yb, typename VecOf<R>::T ybl,
             const typename VecOf<R>::T* __restrict__ yomega, int ynw, typename VecOf<R>::T za,
             typename VecOf<R>::T zb, typename VecOf<R>::T zbl, typename VecOf<R>::T zP,
@@ -46,8 +50,9 @@ k_stream_yz(typename VecOf<R>::T* __restrict__ psi, int ny, int nz, int chunk, i
   const int k = threadIdx.x;
   const bool kin = k < nz;
   const int kpos = k + zp * (k / MZ);  // LDS position of column k in a row slot
-  V* plane = psi + i * (int64_t)ny * nz;
-  auto load = [&](int j) { return kin ? plane[(int64_t)j * nz + k] : vzero<V>(); };
+  const V* splane = src + i * (int64_t)ny * nz;  // input (the x sweep's output)
+  V* plane = psi + i * (int64_t)ny * nz;         // output
+  auto load = [&](int j) { return kin ? gld(splane + (int64_t)j * nz + k) : vzero<V>(); };
   Coef<V> cy, cz;
   cy.a = ya;
   cy.b = yb;
@@ -70,6 +75,10 @@ k_stream_yz(typename VecOf<R>::T* __restrict__ psi, int ny, int nz, int chunk, i
   V pm = vzero<V>(), pc = load(js), dprev = vzero<V>(), u0 = vzero<V>();
   double acc = 0.0;
   const int total = j1 + H - js;  // steps js .. j1 - 1 + H
+  // rows are solved along z in groups of G = L ceil(W / L) steps, so that every wave has a
+  // row to solve; LDS slot of step jj: jj - gstart
+  const int G = L * ((W + L - 1) / L);
+  int gstart = 0;
   for (int jb = 0; jb < total; jb += L) {
 #pragma unroll
     for (int t = 0; t < L; ++t) {
@@ -93,15 +102,17 @@ k_stream_yz(typename VecOf<R>::T* __restrict__ psi, int ny, int nz, int chunk, i
           for (int m = H - 1; m >= 0; --m) u = cfma<CC>(ya, u, ring[(t + 1 + m) % L]);
           if (r == 0) u0 = u;
           if (r < ynw) u = cfma<CC>(yomega[r], u0, u);
-          if (kin) sdata[t * pitch + kpos] = u;
+          if (kin) sdata[(jj - gstart) * pitch + kpos] = u;
         }
       }
     }
-    // the rows emitted in this group: slot t holds row js + jb + t - H
+    const int gend = min(jb + L, total);
+    if (gend - gstart < G && gend < total) continue;  // group not full yet (uniform)
+    // the rows emitted in this group: slot q holds row js + gstart + q - H
     __syncthreads();
-    for (int slot = w; slot < L; slot += W) {
-      const int r = js + jb + slot - H;
-      if (jb + slot < total && r >= j0) {
+    for (int slot = w; slot < gend - gstart; slot += W) {
+      const int r = js + gstart + slot - H;
+      if (r >= j0) {
         V* row = sdata + slot * pitch;
         V v[MZ];
         z_line_solve<R, MZ, CC>(v, row, len > 0, s, ss, zp, len, nz, 64, 0, lane, cz, zP, zomega, znw);
@@ -120,12 +131,12 @@ k_stream_yz(typename VecOf<R>::T* __restrict__ psi, int ny, int nz, int chunk, i
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int t = 0; t < L; ++t) {
-      const int r = js + jb + t - H;
-      if (jb + t < total && r >= j0 && kin) plane[(int64_t)r * nz + k] = sdata[t * pitch + kpos];
+    for (int slot = 0; slot < gend - gstart; ++slot) {
+      const int r = js + gstart + slot - H;
+      if (r >= j0 && kin) gst(plane + (int64_t)r * nz + k, sdata[slot * pitch + kpos]);
     }
     __syncthreads();
+    gstart = gend;
   }
   if (NORM) {
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
@@ -152,8 +163,9 @@ template <typename R, int H, int MZ, bool CC, bool NORM, int EPI>
 hipError_t go_yz(const YZLaunch& a, hipStream_t s) {
   typedef typename VecOf<R>::T V;
   const int zp = (MZ % 4 == 0) ? 1 : 0;
-  const size_t lds = (size_t)(H + 1) * z_pitch(a.nz, MZ, zp) * sizeof(V);
   const int waves = (a.nz + 63) / 64;
+  const int group = (H + 1) * ((waves + H) / (H + 1));  // L ceil(W / L) row slots
+  const size_t lds = (size_t)group * z_pitch(a.nz, MZ, zp) * sizeof(V);
   auto kern = k_stream_yz<R, H, MZ, CC, NORM, EPI, 16>;
   int which = 0;
   if constexpr (sizeof(R) == 8)
@@ -169,8 +181,8 @@ hipError_t go_yz(const YZLaunch& a, hipStream_t s) {
       granted[which] = lds;
     }
   }
-  hipLaunchKernelGGL(kern, dim3((unsigned)((int64_t)a.nx * a.nchunks)), dim3(64 * waves), lds, s, (V*)a.psi, a.ny,
-                     a.nz, a.chunk, a.nchunks, cv<R>(a.ycoef), cv<R>(a.ycoef + 2), cv<R>(a.ycoef + 4),
+  hipLaunchKernelGGL(kern, dim3((unsigned)((int64_t)a.nx * a.nchunks)), dim3(64 * waves), lds, s, (const V*)a.src,
+                     (V*)a.psi, a.ny, a.nz, a.chunk, a.nchunks, cv<R>(a.ycoef), cv<R>(a.ycoef + 2), cv<R>(a.ycoef + 4),
                      (const V*)a.yomega, a.ynw, cv<R>(a.zcoef), cv<R>(a.zcoef + 2), cv<R>(a.zcoef + 4),
                      cv<R>(a.zcoef + 6), (const V*)a.zomega, a.znw, (const R*)a.vx, (const R*)a.vy,
                      Pot1D<R>{(R)a.ph, (R)a.pc, (R)a.pd}, (R)a.tau, a.st, a.partials, zp);
@@ -203,6 +215,7 @@ hipError_t go_yz_h(bool cc, int epi, const YZLaunch& a, hipStream_t s) {
     case 5: return go_yz_m<R, 5>(cc, epi, a, s);
     case 7: return go_yz_m<R, 7>(cc, epi, a, s);
     case 11: return go_yz_m<R, 11>(cc, epi, a, s);
+    case 15: return go_yz_m<R, 15>(cc, epi, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -210,7 +223,7 @@ hipError_t go_yz_h(bool cc, int epi, const YZLaunch& a, hipStream_t s) {
 }  // namespace
 
 int yz_h(int h) {
-  for (int v : {3, 5, 7, 11})
+  for (int v : {3, 5, 7, 11, 15})
     if (h <= v) return v;
   return -1;
 }
