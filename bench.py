@@ -17,9 +17,11 @@ is the library's own streaming copy (16-byte buffer loads and stores, like the s
 Line mappings come from a private copy of the committed autotuner cache
 (results/autotune_gfx950.txt), which a run never modifies.  cpu_baseline times the CPU
 FP64 oracle on host cores on bounded samples: the quench grid, the 48x40x32 run in full and
-the 384^3 grid, with all host threads and with one.  Sub-objects: `batched` (256 uneven
-grids advanced by shared launches vs one solver after another) and `time_to_ground_state`
-(512 held-out problems: Gaussian starts serial and batched, learned warm starts batched).
+the 384^3 grid, with all host threads and with one.  Sub-objects: `halo_truncated` (the
+truncated-inverse step variants on the quench grid against the exact sweeps), `batched`
+(256 uneven grids advanced by shared launches vs one solver after another) and
+`time_to_ground_state` (512 held-out problems: Gaussian starts serial and batched, learned
+warm starts batched).
 """
 from __future__ import annotations
 
@@ -63,6 +65,8 @@ def parse():
                     help="run one 1 GiB copy with the library's copy kernel (HBM counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--no-trunc", action="store_true", help="skip the halo-truncated inverse measurement")
+    ap.add_argument("--trunc-steps", type=int, default=50)
     ap.add_argument("--batch-n", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--batch-serial-steps", type=int, default=400)
@@ -212,6 +216,64 @@ def run_batch(torch, gp, inputs, args):
             "algorithmic_frac_of_hbm_peak": rate_b * 3 * 2 * 8 / PEAK_HBM, "mapping": mapping,
             "yz_fusion": {"enabled": fusion[0], "fused_instances": fusion[1]},
             "kernels": kern, "mu_range": [float(np.min(mu)), float(np.max(mu))]}
+
+
+def run_truncated(torch, gp, inputs, w, args):
+    """The halo-truncated inverse (gp_set_truncation) on the quench grid, per precision and
+    step kind: the exact sweeps (mode 0), the streaming x and y sweeps (mode 1) and the exact
+    x sweep followed by one fused pass of the truncated y sweep and the z sweep (mode 2), each
+    `trunc_steps` steps from the same Gaussian start after 5 untimed ones; ms per step, the
+    algorithmic fraction of the HBM peak (6 psi transfers per step in modes 0 and 1, 4 in
+    mode 2) and the largest difference from mode 0's final state relative to max|psi|."""
+    nx, ny, nz = w["nx"], w["ny"], w["nz"]
+    npts = nx * ny * nz
+    K = args.trunc_steps
+    out = {"workload": "quench_512x480x448", "steps": K}
+    for prec in (gp.GP_C128, gp.GP_C64):
+        tag = "c64" if prec == gp.GP_C64 else "c128"
+        esz = 8 if prec == gp.GP_C64 else 16
+        ndt = np.complex64 if prec == gp.GP_C64 else np.complex128
+        psi0 = torch.from_numpy(inputs.gaussian_psi(nx, ny, nz, w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"],
+                                                    w["nuz"], dtype=ndt)).to("cuda")
+        psi = torch.empty_like(psi0)
+        for kind in ("imag", "real"):
+            prm = dict(w, dt=w["dt_imag"]) if kind == "imag" else dict(w)
+            ref = None
+            for mode in (0, 1, 2):
+                psi.copy_(psi0)
+                with gp.Solver.from_workload(psi, prm) as s:
+                    if not args.no_autotune:   # the exact sweeps' mapping (x in mode 2)
+                        s.autotune(kind, steps=args.autotune_steps, cache_path=args.tune_cache)
+                    s.set_truncation(mode)
+                    step = s.step_imag if kind == "imag" else s.step_real
+                    step(5)
+                    torch.cuda.synchronize()
+                    s.set_timing(True)
+                    t0 = time.perf_counter()
+                    step(K)
+                    torch.cuda.synchronize()
+                    wall = time.perf_counter() - t0
+                    ms, n = s.get_timing()
+                    s.set_timing(False)
+                    hlen = s.get_truncation()[1][0 if kind == "imag" else 1]
+                torch.cuda.synchronize()
+                if mode == 0:
+                    ref = psi.clone()
+                    diff = 0.0
+                else:
+                    diff = float((psi - ref).abs().max() / ref.abs().max())
+                moves = 4 if mode == 2 else 6
+                r = dict(ms_per_step=wall / K * 1e3, updates_per_s=npts * K / wall,
+                         algorithmic_frac_of_hbm_peak=npts * K / wall * moves * esz / PEAK_HBM,
+                         kernel_ms={KINDS[q]: float(ms[q]) for q in range(3) if n[q]},
+                         halo=hlen if mode else None, max_rel_diff_vs_exact=diff)
+                out[f"{tag}_{kind}_mode{mode}"] = r
+                log(f"[bench] truncation {tag} {kind} mode {mode}: {r['ms_per_step']:.3f} ms/step, "
+                    f"diff vs exact {diff:.2e}")
+            del ref
+        del psi, psi0
+        torch.cuda.empty_cache()
+    return out
 
 
 def stream_copy_gbps(torch, gp, nbytes=1 << 30, reps=5):
@@ -449,6 +511,8 @@ def main():
         sub["dtype"] = "f32" if other == gp.GP_C64 else "f64"
         sub["precision"] = ("complex64 storage+sweeps, FP64 reductions" if other == gp.GP_C64 else "complex128")
         out["precision_form" if other == gp.GP_C64 else "complex128"] = sub
+    if not args.no_trunc:
+        out["halo_truncated"] = run_truncated(torch, gp, inputs, w, args)
     if not args.no_batch:
         out["batched"] = run_batch(torch, gp, inputs, args)
     if not args.no_ttgs and os.path.exists(args.weights):

@@ -106,19 +106,28 @@ int gp_status(gp_ctx* c, int64_t* steps_done, double* mu_est, int32_t* flags);
 
 /* Imaginary-time propagation to the ground state at relative tolerance tol, checking every
  * check_every = K steps (K <= 0 selects ceil(0.25/dt)), at most max_steps steps.
- * Stopping rule, on the sequence of checked values m_n with d_n = m_n - m_{n-1}: while
- * m approaches its limit geometrically (d_n / d_{n-1} = r in (0, 1)), stop when
- * |d_n| <= tol |m_n|, the extrapolated distance to the limit |d_n| r / (1 - r) (Aitken)
- * is <= tol |m_n| / 2 and the extrapolated limit agrees within tol |m_n| / 2 with the
- * previous check's; otherwise (m(t) turning, as from an already close start, or at its
- * rounding floor) when |d| <= tol |m| / 10 at three successive checks.  complex64: m = mu (the observables pass) at
- * every check.  complex128: m = mu_est = -ln(N_pre)/(2 dt) from the renormalisation (no
- * extra pass); when it stops, mu is evaluated and must change by at most tol |mu| (with the
- * same predicted tail) over one more interval, else monitoring resumes.
+ * Stopping rule, on the sequence of checked values m_n with d_n = m_n - m_{n-1} and
+ * q_n = d_n / d_{n-1}: while m approaches its limit geometrically (q_n and q_{n-1} in
+ * (0, 1) and within q_n / 10 of each other), stop when |d_n| <= tol |m_n|, the
+ * extrapolated distance to the limit |d_n| r / (1 - r) with r = max(q_n, q_{n-1})
+ * (Aitken) is <= tol |m_n| / 2 and the extrapolated limit agrees within tol |m_n| / 2 with
+ * the previous check's; otherwise (m(t) turning, as from an already close start,
+ * alternating, or at its rounding floor) when |d| <= tol |m| / 10 at three successive
+ * checks (gp_stop_rule_eval replays the rule on a given sequence).  complex64: m = mu (the
+ * observables pass) at every check.  complex128: m = mu_est = -ln(N_pre)/(2 dt) from the
+ * renormalisation (no extra pass); when it stops, mu is evaluated and must change by at
+ * most tol |mu| (with the same predicted tail) over one more interval, else monitoring
+ * resumes.
  * Returns the steps taken and the final mu.  GP_OK also when max_steps is reached;
  * *converged tells which.  Synchronises at every check. */
 int gp_converge_imag(gp_ctx* c, double tol, int32_t check_every, int64_t max_steps,
                      int64_t* steps_taken, double* mu, int32_t* converged);
+/* The stopping rule of gp_converge_imag and gp_batch_converge_imag on a host sequence
+ * values[0..n) (one value per check, in order): *stop_index = the first index at which the
+ * rule is met, -1 if it never is.  Host only (no device, no context); n >= 0, values and
+ * stop_index non-null when n > 0, else GP_ERR_INVALID. */
+int gp_stop_rule_eval(const double* values, int32_t n, double tol, int32_t* stop_index);
+
 
 /* Per-kernel timing: while enabled, eager launches are bracketed by HIP events on the
  * context's stream (graphs are not used).  gp_get_timing returns the mean duration in ms

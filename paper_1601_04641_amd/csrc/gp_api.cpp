@@ -902,6 +902,18 @@ int gp_converge_imag(gp_ctx* c, double tol, int32_t check_every, int64_t max_ste
   return GP_OK;
 }
 
+int gp_stop_rule_eval(const double* values, int32_t n, double tol, int32_t* stop_index) {
+  if (n < 0 || (n > 0 && (!values || !stop_index))) return GP_ERR_INVALID;
+  if (stop_index) *stop_index = -1;
+  gpk::StopRule rule;
+  for (int32_t k = 0; k < n; ++k)
+    if (rule.update(values[k], tol)) {
+      *stop_index = k;
+      break;
+    }
+  return GP_OK;
+}
+
 int gp_set_timing(gp_ctx* c, int32_t enable) {
   if (!c) return GP_ERR_INVALID;
   int rc = harvest(c);

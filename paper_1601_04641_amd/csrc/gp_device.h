@@ -41,8 +41,9 @@ __device__ __forceinline__ double dexp(double v) { return exp(v); }
 // r^17 / r^18 in FP64; truncation below 1e-10 resp. 1e-20 on [-pi/4, pi/4]), and the
 // quadrant k mod 4.  FP32 arguments beyond 1e4 are reduced in FP64 with the FP64 parts
 // (the residual of pi/2 after three FP64 parts is ~1e-49, so k stays exact to |x| ~ 1e15);
-// FP64 arguments use the same reduction up to |x| ~ 2^52.  Worst error found on a dense
-// sample of |x| <= 1e4 against the C library: 1.4 ulp (FP32), 1.0 ulp (FP64).  There is no
+// FP64 arguments use the same reduction up to |x| ~ 2^52.  Worst error measured on dense
+// samples of |x| <= 1e4 against an 80-bit extended-precision reference, in ulps of the
+// correctly rounded value: 1.46 (sin) / 1.47 (cos) in FP32, 1.47 / 1.48 in FP64.  There is no
 // out-of-line fallback: a call inside the unrolled sweeps would force the calling
 // convention on every live register (94 instead of 77 VGPRs in the x sweep).  The phase
 // of one real-time step is usually far below 1/8; there the series is used directly.

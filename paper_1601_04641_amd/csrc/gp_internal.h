@@ -156,51 +156,57 @@ hipError_t launch_stream_copy(const void* src, void* dst, int64_t bytes, hipStre
 hipError_t launch_obs_scale(const double* sums, double* raw, double dV, const double d2[3], hipStream_t st);
 
 // Stopping rule of the imaginary-time convergence loops, fed one value (mu) per check.
-// delta_n = mu_n - mu_{n-1}.  While two successive deltas have the same sign and shrink
-// (r = delta_n / delta_{n-1} in (0, 1): mu approaches its limit geometrically), the
-// distance of mu_n to that limit is estimated as |delta_n| r / (1 - r) (Aitken's
-// extrapolation) and must be at most tol |mu_n| / 2 (a margin for the neglected slower
-// modes), with |delta_n| <= tol |mu_n|, and the extrapolated limit mu_n + that tail must
-// agree within tol |mu_n| / 2 with the previous check's (two modes of opposite sign can
-// fake a geometric ratio for one check).  Otherwise (mu turning, as from a start already
-// close to the ground state, or at its rounding floor) |delta| <= tol |mu_n| / 10 must hold
-// at three successive checks: near a turning point of mu(t) two small changes can straddle
-// the extremum while mu is still far from its limit.
+// delta_n = mu_n - mu_{n-1}, q_n = delta_n / delta_{n-1}.  mu approaches its limit
+// geometrically when one decaying mode dominates: then q_n lies in (0, 1) and stays put.
+// The rule asks for that at two successive checks, |q_n - q_{n-1}| <= q_n / 10, and prices
+// the distance to the limit with the larger ratio r = max(q_n, q_{n-1}) (Aitken's
+// extrapolation): |delta_n| r / (1 - r) <= tol |mu_n| / 2, |delta_n| <= tol |mu_n|, and the
+// extrapolated limit mu_n + delta_n r / (1 - r) within tol |mu_n| / 2 of the previous
+// check's.  The band on q rejects the two ways a mix of modes imitates a converged tail:
+// a slower mode of opposite sign emerging makes q fall (towards a turning point of mu(t),
+// where the changes are small while mu is still far from its limit), and a slower mode of
+// the same sign makes q rise (its tail is then underpriced by the current ratio).
+// Otherwise (mu turning, alternating, or at its rounding floor) |delta| <= tol |mu_n| / 10
+// must hold at three successive checks.
 struct StopRule {
   double prev = NAN, prev2 = NAN;
-  double r = -1.0;      // last contraction ratio (-1: none, or not in (0, 1))
+  double q = -1.0;        // last ratio delta_n / delta_{n-1} (-1: none, or not in (0, 1))
+  double r = -1.0;        // ratio the tail is priced with (-1: not geometric at this check)
   double lim_prev = NAN;  // extrapolated limit at the previous check (NaN: not geometric)
   int hits = 0;
   void reset() {
     prev = prev2 = lim_prev = NAN;
-    r = -1.0;
+    q = r = -1.0;
     hits = 0;
   }
-  // distance to the limit that the ratio r predicts for a change d (0 outside (0, 1))
+  // distance to the limit that the ratio r predicts for a change d (0 when not geometric)
   double tail(double d) const { return (r > 0.0 && r < 1.0) ? std::fabs(d) * r / (1.0 - r) : 0.0; }
   bool update(double cur, double tol) {
     bool done = false;
     if (std::isfinite(prev) && std::isfinite(cur)) {
       const double d1 = cur - prev, lim = tol * std::fabs(cur);
       hits = std::fabs(d1) <= 0.1 * lim ? hits + 1 : 0;
-      r = -1.0;
+      const double qp = q;
+      q = r = -1.0;
       double extrap = NAN;
       if (std::isfinite(prev2)) {
         const double d0 = prev - prev2;
-        const double q = d0 != 0.0 ? d1 / d0 : -1.0;
-        if (q > 0.0 && q < 1.0) {
-          r = q;
-          extrap = cur + d1 * q / (1.0 - q);
-          // geometric at two successive checks, with the same extrapolated limit
-          done = std::fabs(d1) <= lim && tail(d1) <= 0.5 * lim && std::isfinite(lim_prev) &&
-                 std::fabs(extrap - lim_prev) <= 0.5 * lim;
+        const double qn = d0 != 0.0 ? d1 / d0 : -1.0;
+        if (qn > 0.0 && qn < 1.0) {
+          q = qn;
+          if (qp > 0.0 && qp < 1.0 && std::fabs(qn - qp) <= 0.1 * qn) {
+            r = std::max(qn, qp);
+            extrap = cur + d1 * r / (1.0 - r);
+            done = std::fabs(d1) <= lim && tail(d1) <= 0.5 * lim && std::isfinite(lim_prev) &&
+                   std::fabs(extrap - lim_prev) <= 0.5 * lim;
+          }
         }
       }
       lim_prev = extrap;
       done = done || hits >= 3;
     } else {
       hits = 0;
-      r = -1.0;
+      q = r = -1.0;
       lim_prev = NAN;
     }
     prev2 = prev;

@@ -32,7 +32,7 @@ EXPORTS = ("gp_init", "gp_destroy", "gp_step_imag", "gp_step_real", "gp_norm", "
            "gp_batch_set_mapping", "gp_batch_autotune", "gp_batch_set_yz_fusion", "gp_batch_get_yz_fusion", "gp_batch_set_timing",
            "gp_batch_get_timing", "gp_batch_last_error",
            "gp_set_alloc_cap", "gp_eval_sincos", "gp_stream_copy", "gp_raw_sums_noalloc",
-           "gp_set_truncation", "gp_get_truncation")
+           "gp_set_truncation", "gp_get_truncation", "gp_stop_rule_eval")
 
 
 class GPError(RuntimeError):
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
         "gp_raw_sums_noalloc": [P(gp_params), vp, vp, vp],
         "gp_set_truncation": [vp, i32],
         "gp_get_truncation": [vp, P(i32), P(i32)],
+        "gp_stop_rule_eval": [P(d), i32, d, P(i32)],
         "gp_batch_set_yz_fusion": [vp, i32],
         "gp_batch_get_yz_fusion": [vp, P(i32), P(i32)],
         "gp_batch_set_timing": [vp, i32],
@@ -147,6 +148,18 @@ def gp_init(params: gp_params, psi_ptr: int, stream_ptr: int):
 def set_alloc_cap(nbytes: int | None):
     """Make every later library allocation above nbytes fail with GP_ERR_OOM (None: no cap)."""
     load().gp_set_alloc_cap(-1 if nbytes is None else int(nbytes))
+
+
+def stop_rule_eval(values, tol: float) -> int:
+    """Index of the first check at which the convergence loops' stopping rule is met on
+    the given sequence of checked values (-1: never).  Host only."""
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    out = ctypes.c_int32()
+    rc = load().gp_stop_rule_eval(v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(v.size), float(tol),
+                                  ctypes.byref(out))
+    if rc:
+        raise GPError(rc, "gp_stop_rule_eval")
+    return out.value
 
 
 def _stream_ptr(t, stream):
@@ -291,7 +304,9 @@ class Solver:
         self._chk(self._L.gp_set_mapping(self._h, arr), "gp_set_mapping")
 
     def set_truncation(self, mode: int):
-        """0: exact sweeps; 1: streaming x/y sweeps with the halo-truncated inverse."""
+        """0: exact sweeps; 1: streaming x and y sweeps with the halo-truncated inverse;
+        2: exact x sweep into a work array, then one fused pass of the truncated y sweep
+        and the z sweep (see gp_set_truncation)."""
         self._chk(self._L.gp_set_truncation(self._h, int(mode)), "gp_set_truncation")
 
     def get_truncation(self):
