@@ -148,7 +148,9 @@ struct gp_ctx {
   double coef[2][3][8] = {{{0}}};  // a, b, b_lo, P = a^m as (re, im)
   void* vtab[3] = {nullptr};      // storage-precision 1/2 nu^2 a^2
   double* zpart = nullptr;
-  int zgrid = 0;
+  int zgrid = 0;       // z sweep blocks in imaginary time (one FP64 norm partial each)
+  int zgrid_real = 0;  // z sweep blocks in real time
+  int zw = 4;          // z sweep wavefronts per block (gpk::z_waves)
   int zpart_cap = 0;  // doubles allocated at zpart (z sweep or fused y+z partials)
   double* opart = nullptr;
   int ogrid = 0;
@@ -263,20 +265,45 @@ bool pick_lines(int prec, const AxisLines& a, bool nstep, int* m_out, int* sw_ou
 // partial round of blocks would leave most CUs idle at the tail
 int zpad_of(int nz, int seg, int m, size_t esize) { return gpk::z_pad(nz, seg, m, esize, gpk::kMaxLdsBlock); }
 
-// complex128: one block per line group (measured 723 -> 706 us, with the non-temporal
-// policy 671 -> 654 us on the quench grid); complex64 keeps the resident grid (one block
-// per group measured 2-4% slower there)
-int z_grid(const gp_ctx* c, int segz, int mz, int64_t zgroups) {
-  if (c->esize == 16) return (int)std::max<int64_t>(1, std::min<int64_t>(zgroups, 0x7fffffff));
+// z sweep grids.  4-wavefront blocks: complex128 one block per line group (measured
+// 723 -> 706 us, with the non-temporal policy 671 -> 654 us on the quench grid); complex64
+// the blocks that fit on the device at once, each walking an equal share of the groups
+// (one block per group measured 2-4% slower there; a second, partial round of resident
+// blocks would leave most CUs idle at the tail).  1-wavefront blocks (long lines): one
+// block per group in real time; in imaginary time the resident grid (the occupancy of the
+// kernel instance), which keeps the norm partials few.
+struct ZPlan {
+  int zw = 4;
+  int64_t groups = 0;
+  int grid_imag = 0, grid_real = 0;
+};
+
+ZPlan z_plan(const gp_ctx* c, int segz, int mz) {
+  ZPlan z;
+  const int zpad = zpad_of(c->p.nz, segz, mz, c->esize);
+  z.zw = gpk::z_waves(c->p.nz, segz, mz, zpad, c->esize);
+  const int64_t per_grp = (int64_t)z.zw * (64 / segz);
+  z.groups = ((int64_t)c->p.nx * c->p.ny + per_grp - 1) / per_grp;
+  const int64_t one_shot = std::max<int64_t>(1, std::min<int64_t>(z.groups, 0x7fffffff));
   int cus = 0, lds_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1) cus = 256;
   if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) != hipSuccess ||
       lds_cu < 65536)
     lds_cu = 65536;
-  const int64_t lds = (int64_t)gpk::z_lds(c->p.nz, segz, mz, zpad_of(c->p.nz, segz, mz, c->esize), c->esize) + 512;
-  int64_t per_cu = lds_cu / std::max<int64_t>(lds, 1);
-  per_cu = std::max<int64_t>(1, std::min<int64_t>(per_cu, 8));
-  return (int)std::max<int64_t>(1, std::min<int64_t>(zgroups, per_cu * cus));
+  const size_t lds = gpk::z_lds(c->p.nz, segz, mz, zpad, c->esize, z.zw);
+  if (z.zw == 1) {
+    int64_t per_cu = gpk::z_resident_per_cu(c->esize == 16 ? 1 : 0, mz, 1, lds);
+    if (per_cu < 1) per_cu = std::max<int64_t>(1, std::min<int64_t>(lds_cu / (int64_t)(lds + 512), 16));
+    z.grid_imag = (int)std::max<int64_t>(1, std::min<int64_t>(z.groups, per_cu * cus));
+    z.grid_real = (int)one_shot;
+  } else if (c->esize == 16) {
+    z.grid_imag = z.grid_real = (int)one_shot;
+  } else {
+    int64_t per_cu = lds_cu / std::max<int64_t>((int64_t)lds + 512, 1);
+    per_cu = std::max<int64_t>(1, std::min<int64_t>(per_cu, 8));
+    z.grid_imag = z.grid_real = (int)std::max<int64_t>(1, std::min<int64_t>(z.groups, per_cu * cus));
+  }
+  return z;
 }
 
 bool valid_z(int nz, int seg, int m, size_t esize) {
@@ -400,8 +427,9 @@ gpk::SweepLaunch z_args(gp_ctx* c, int mode) {
   a.nz = p.nz;
   a.st = c->st;
   a.partials = mode == 0 ? c->zpart : nullptr;
-  a.grid = c->zgrid;
+  a.grid = mode == 0 ? c->zgrid : c->zgrid_real;
   a.zpad = zpad_of(p.nz, a.nseg, a.m, c->esize);
+  a.zw = c->zw;
   return a;
 }
 
@@ -693,9 +721,10 @@ int init_body(gp_ctx* c) {
       HIPCHK(c, hipMemcpy(c->vtab[a], vf.data(), n[a] * sizeof(float), hipMemcpyHostToDevice));
   }
   if ((rc = build_tables(c))) return rc;
-  const int64_t zlines = (int64_t)p.nx * p.ny;
-  const int64_t zgroups = (zlines + 4 * (64 / c->map.segz) - 1) / (4 * (64 / c->map.segz));
-  c->zgrid = z_grid(c, c->map.segz, c->map.mz, zgroups);
+  const ZPlan zp = z_plan(c, c->map.segz, c->map.mz);
+  c->zw = zp.zw;
+  c->zgrid = zp.grid_imag;
+  c->zgrid_real = zp.grid_real;
   const int64_t oblocks = (c->npts + 255) / 256;
   c->ogrid = (int)std::min<int64_t>(oblocks, 2048);
   if ((rc = dalloc(c, &c->zpart, (size_t)c->zgrid * sizeof(double)))) return rc;
@@ -989,9 +1018,8 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const Mapping old = c->map;
   c->map = nm;
-  const int64_t zlines = (int64_t)c->p.nx * c->p.ny;
-  const int64_t zgroups = (zlines + 4 * (64 / nm.segz) - 1) / (4 * (64 / nm.segz));
-  const int zgrid = z_grid(c, nm.segz, nm.mz, zgroups);
+  const ZPlan zp = z_plan(c, nm.segz, nm.mz);
+  const int zgrid = zp.grid_imag;
   if (zgrid > c->zpart_cap) {
     double* np = nullptr;
     int rc = dalloc(c, &np, (size_t)zgrid * sizeof(double));
@@ -1003,13 +1031,17 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]) {
     c->zpart = np;
     c->zpart_cap = zgrid;
   }
-  const int old_zgrid = c->zgrid;
+  const int old_zgrid = c->zgrid, old_zgrid_real = c->zgrid_real, old_zw = c->zw;
   c->zgrid = zgrid;
+  c->zgrid_real = zp.grid_real;
+  c->zw = zp.zw;
   destroy_graphs(c);
   int rc = build_tables(c);
   if (rc) {  // back to the previous mapping (its tables fit: they were built before)
     c->map = old;
     c->zgrid = old_zgrid;
+    c->zgrid_real = old_zgrid_real;
+    c->zw = old_zw;
     (void)build_tables(c);
   }
   return rc;

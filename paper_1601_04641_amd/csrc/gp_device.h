@@ -327,6 +327,10 @@ __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, type
     for (int t = 0; t < M; ++t) {
       const int pos = min(s + t, n - 1);
       v[t] = nstep<NSTEP, R, V>(v[t], scale, px.at(pos) + vyz, g, tau);  // padding stays 0
+      // complex128 with 30+ points per thread: one point's exp or sin/cos at a time, else
+      // the scheduler overlaps many of them and the live temporaries exceed even 256 VGPRs
+      // (spills; complex64 keeps the overlap, which measured 9% faster there)
+      if constexpr (M >= 30 && sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
     }
   }
 
@@ -602,14 +606,15 @@ __device__ __forceinline__ void z_line_solve(typename VecOf<R>::T (&v)[MZ], cons
 }
 
 // ---------------------------------------------------------------------------------------
-// z sweep.  Block = 4 wavefronts; a wavefront holds L = 64/nseg z lines, lane =
-// line-in-wave * nseg + segment, MZ points per thread.  Each iteration copies 4L
-// consecutive lines (contiguous in memory) into LDS, solves them, and copies them back.
+// z sweep.  Block = NW wavefronts (4, or 1 for long lines); a wavefront holds L = 64/nseg
+// z lines, lane = line-in-wave * nseg + segment, MZ points per thread.  Each iteration
+// copies NW L consecutive lines (contiguous in memory) into LDS, solves them, and copies
+// them back.
 // The omega correction runs here (any nw), u'_0 broadcast along the line by a shuffle.
 // Processes line groups grp_begin, grp_begin + grp_step, ...; returns this thread's FP64
 // sum of |psi|^2 over the stored points when NORM.
 // ---------------------------------------------------------------------------------------
-template <typename R, int MZ, bool CC, bool NORM, int EPI>
+template <typename R, int MZ, bool CC, bool NORM, int EPI, int NW = 4>
 __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca,
                                          typename VecOf<R>::T cb, typename VecOf<R>::T cbl,
                                          typename VecOf<R>::T cP, const typename VecOf<R>::T* __restrict__ omega,
@@ -627,7 +632,8 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int L = 64 / nseg;
   const int l = lane / nseg, p = lane % nseg;
-  const int lines_per_grp = 4 * L;
+  constexpr int NT = 64 * NW;  // threads per block
+  const int lines_per_grp = NW * L;
   const int64_t ngrp = (nlines + lines_per_grp - 1) / lines_per_grp;
   const int s = p * MZ;
   const int ss = s + zp * p;  // LDS position of the segment's first point
@@ -637,7 +643,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
   cf.b = cb;
   cf.bl = cbl;
   double acc = 0.0;
-  // this thread's copy positions advance by 256 points (or pairs) per iteration: their
+  // this thread's copy positions advance by NT points (or pairs) per iteration: their
   // (line, point) digits advance by the step's own digits with one carry
   const int half = nz >> 1;
   // 16-byte copies need a 16-byte aligned grid base (a batched instance may start at any
@@ -645,7 +651,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
   const bool al16 = (reinterpret_cast<uintptr_t>(psi) & 15) == 0;
   const bool pairs = sizeof(V) == 8 && (nz & 1) == 0 && al16;  // with zp = 1 (MZ even)
   const int cn = pairs ? half : nz;
-  const int dl = 256 / cn, dq = 256 % cn;
+  const int dl = NT / cn, dq = NT % cn;
 
   for (int64_t grp = grp_begin; grp < ngrp; grp += grp_step) {
     const int64_t line0 = grp * lines_per_grp;
@@ -656,14 +662,14 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
       if (sizeof(V) == 8 && al16 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {  // 16-byte copies
         const float4* s4 = reinterpret_cast<const float4*>(src);
         float4* d4 = reinterpret_cast<float4*>(sdata);
-        for (int q = tid; q < (cnt >> 1); q += 256) d4[q] = gld(s4 + q);
+        for (int q = tid; q < (cnt >> 1); q += NT) d4[q] = gld(s4 + q);
       } else {
-        for (int q = tid; q < cnt; q += 256) sdata[q] = gld(src + q);
+        for (int q = tid; q < cnt; q += NT) sdata[q] = gld(src + q);
       }
     } else if (pairs) {  // 16-byte global loads; a pair never straddles a line or segment
       const float4* s4 = reinterpret_cast<const float4*>(src);
       int cl = tid / cn, cq = tid % cn;
-      for (int f = tid; f < (cnt >> 1); f += 256) {
+      for (int f = tid; f < (cnt >> 1); f += NT) {
         const int q = 2 * cq, at = cl * pitch + q + q / MZ;
         const float4 x = gld(s4 + f);
         sdata[at] = vmake<V>(x.x, x.y);
@@ -677,7 +683,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
       }
     } else {
       int cl = tid / cn, cq = tid % cn;
-      for (int f = tid; f < cnt; f += 256) {
+      for (int f = tid; f < cnt; f += NT) {
         sdata[cl * pitch + cq + cq / MZ] = gld(src + f);
         cq += dq;
         cl += dl;
@@ -716,14 +722,14 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
       if (sizeof(V) == 8 && al16 && ((line0 * nz) & 1) == 0 && (cnt & 1) == 0) {
         float4* d4 = reinterpret_cast<float4*>(dst);
         const float4* s4 = reinterpret_cast<const float4*>(sdata);
-        for (int q = tid; q < (cnt >> 1); q += 256) gst(d4 + q, s4[q]);
+        for (int q = tid; q < (cnt >> 1); q += NT) gst(d4 + q, s4[q]);
       } else {
-        for (int q = tid; q < cnt; q += 256) gst(dst + q, sdata[q]);
+        for (int q = tid; q < cnt; q += NT) gst(dst + q, sdata[q]);
       }
     } else if (pairs) {
       float4* d4 = reinterpret_cast<float4*>(dst);
       int cl = tid / cn, cq = tid % cn;
-      for (int f = tid; f < (cnt >> 1); f += 256) {
+      for (int f = tid; f < (cnt >> 1); f += NT) {
         const int q = 2 * cq, at = cl * pitch + q + q / MZ;
         const V a = sdata[at], b = sdata[at + 1];
         gst(d4 + f, make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y));
@@ -736,7 +742,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
       }
     } else {
       int cl = tid / cn, cq = tid % cn;
-      for (int f = tid; f < cnt; f += 256) {
+      for (int f = tid; f < cnt; f += NT) {
         gst(dst + f, sdata[cl * pitch + cq + cq / MZ]);
         cq += dq;
         cl += dl;
@@ -788,6 +794,14 @@ __device__ __forceinline__ double block_sum_256(double v, double* red) {
   const double r = (red[0] + red[1]) + (red[2] + red[3]);
   __syncthreads();
   return r;
+}
+
+// sum over a block of NW = 1 or 4 wavefronts (red: 4 doubles of LDS), fixed order
+template <int NW> __device__ __forceinline__ double block_sum_w(double v, double* red) {
+  static_assert(NW == 1 || NW == 4, "z blocks are 1 or 4 wavefronts");
+  if constexpr (NW == 4) return block_sum_256(v, red);
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
 }
 
 }  // namespace gpk

@@ -35,8 +35,18 @@ struct DevState {
 // whenever the padded block still fits 64 KiB; other even mz conflict 2-way at most,
 // which measured no slower packed.
 __host__ __device__ inline int z_pitch(int nz, int mz, int zpad) { return nz + zpad * ((nz + mz - 1) / mz); }
-inline size_t z_lds(int nz, int seg, int mz, int zpad, size_t esize) {
-  return (size_t)4 * (64 / seg) * (size_t)z_pitch(nz, mz, zpad) * esize;
+inline size_t z_lds(int nz, int seg, int mz, int zpad, size_t esize, int nw = 4) {
+  return (size_t)nw * (64 / seg) * (size_t)z_pitch(nz, mz, zpad) * esize;
+}
+// Wavefronts per z block: 4, or 1 for long complex128 lines (mz >= 8) whose 4-wavefront
+// block would hold more than 32 KiB of LDS.  The LDS of a CU then holds fewer than five
+// 4-wavefront blocks, and a block's phases (copy in, solve, copy out) stop overlapping
+// with other blocks' memory traffic; one-wavefront blocks keep about the same lines per
+// CU in flight in independent units.  Measured (1000 steps): 1280-point lines 48.2 ->
+// 37.8 ms (imaginary time), 960-point lines 18.3 -> 15.4 ms (real time).  complex64
+// 1280-point lines ran slower that way (14.2 -> 20.3 ms) and keep 4 wavefronts.
+inline int z_waves(int nz, int seg, int mz, int zpad, size_t esize) {
+  return (esize == 16 && mz >= 8 && z_lds(nz, seg, mz, zpad, esize, 4) + 512 > 32768) ? 1 : 4;
 }
 // Blocks whose packed rows already need more than 64 KiB (complex128 lines beyond 1016
 // points, complex64 beyond 2032) take the padded layout whenever it fits max_lds.
@@ -76,11 +86,15 @@ struct SweepLaunch {
   double* partials; // z sweep: per-block FP64 sum |psi|^2 (imaginary time), else null
   int grid;         // z sweep: number of blocks
   int zpad;         // z sweep: one empty LDS slot after each segment (z_pad)
+  int zw;           // z sweep: wavefronts per block (z_waves)
 };
 
 // precision: 0 complex64, 1 complex128; cc: complex coefficients (real time)
 hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipStream_t s);
 hipError_t launch_sweep_z(int precision, bool cc, const SweepLaunch& a, hipStream_t s);
+// Resident blocks per CU of the imaginary-time z kernels (the fewer of the two instances,
+// with and without the Strang half step) for this mapping; 0 on failure
+int z_resident_per_cu(int precision, int mz, int zw, size_t lds);
 // Streaming x/y sweep with the back-substitution truncated after a.hlen terms
 hipError_t launch_stream_lines(int precision, bool cc, const SweepLaunch& a, hipStream_t s);
 int stream_h(int h);  // instance size for a required truncation length (-1: none)

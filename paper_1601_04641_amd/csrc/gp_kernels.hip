@@ -45,7 +45,8 @@ namespace gpk {
 // MAXW: the most wavefronts a block of this instance may have.  1024-thread blocks cap a
 // thread at 128 VGPRs; complex128 with 16 points per thread needs more in the x sweep (the
 // potential step's phase factor), and spilling there cost 30% extra HBM traffic (scratch
-// reads and writes), so blocks of at most 8 wavefronts run an instance bounded at 512.
+// reads and writes), so blocks of at most 8 wavefronts run an instance bounded at 512
+// (256 VGPRs).  The same holds for 30 and 32 points per thread in either precision.
 template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE, int MAXW>
 __global__ void __launch_bounds__(64 * MAXW)
 k_sweep_lines(const typename VecOf<R>::T* psi, typename VecOf<R>::T* dst, int64_t psi_bytes, typename VecOf<R>::T ca,
@@ -89,8 +90,8 @@ k_stream_lines(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, 
   stream_line<R, H, CC, NSTEP>(psi + base, n, inner, cf, omega, nw, px, vperp, tau, scale, g);
 }
 
-template <typename R, int MZ, bool CC, bool NORM, int EPI>
-__global__ void __launch_bounds__(256)
+template <typename R, int MZ, bool CC, bool NORM, int EPI, int NW>
+__global__ void __launch_bounds__(64 * NW)
 k_sweep_z(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typename VecOf<R>::T cb,
           typename VecOf<R>::T cbl, typename VecOf<R>::T cP, const typename VecOf<R>::T* __restrict__ omega, int nwi,
           int nz, int nseg, int64_t nlines, double* __restrict__ partials, const R* __restrict__ vx,
@@ -99,10 +100,10 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typen
   __shared__ double red[4];
   R g = 0;
   if (EPI != 0) g = (R)st->g;
-  const double acc = z_body<R, MZ, CC, NORM, EPI>(psi, ca, cb, cbl, cP, omega, nwi, nz, nseg, nlines, vx, vy, pz, ny,
-                                                  tau, g, blockIdx.x, gridDim.x, zpad, smem_raw);
+  const double acc = z_body<R, MZ, CC, NORM, EPI, NW>(psi, ca, cb, cbl, cP, omega, nwi, nz, nseg, nlines, vx, vy, pz,
+                                                      ny, tau, g, blockIdx.x, gridDim.x, zpad, smem_raw);
   if (NORM) {
-    const double t = block_sum_256(acc, red);
+    const double t = block_sum_w<NW>(acc, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
   }
 }
@@ -259,7 +260,7 @@ static hipError_t go_lines(const SweepLaunch& a, hipStream_t s) {
   const int64_t blocks = (a.nlines + LW - 1) / LW;
   const int nwi = (a.nw <= M) ? a.nw : 0;
   auto kern = k_sweep_lines<R, M, SW, CC, NSTEP, WIDE, 16>;
-  if constexpr (sizeof(R) == 8 && M == 16 && NSTEP != 0)
+  if constexpr ((sizeof(R) == 8 && M == 16 && NSTEP != 0) || M >= 30)
     if (waves <= 8) kern = k_sweep_lines<R, M, SW, CC, NSTEP, WIDE, 8>;
   V* dst = (V*)(a.dst ? a.dst : a.psi);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(waves * 64), lds, s,
@@ -280,13 +281,15 @@ static hipError_t go_lines_mode(bool cc, const SweepLaunch& a, hipStream_t s) {
   return a.nstep ? go_lines<R, M, SW, true, 2, WIDE>(a, s) : go_lines<R, M, SW, true, 0, WIDE>(a, s);
 }
 
-// Instances: complex64 M in {8, 10, 12, 16, 32}, complex128 M in {8, 16} (32 complex
-// doubles per thread would not fit the 128-VGPR budget of 1024-thread blocks); SW in
-// {1, 2, 4}, and SW = 8 with complex64 M = 16, SW = 4 with complex64 M = 30.  M = 10 and 12 keep the real-time x sweep (with the phase factor) at <= 64
-// VGPRs, i.e. 8 waves per SIMD, where M = 16 needs 80 (6 waves).
+// Instances: complex64 M in {8, 10, 12, 16, 32}, complex128 M in {8, 16}, SW in {1, 2, 4}
+// (32 complex doubles per thread would not fit the 128 VGPRs of 1024-thread blocks);
+// M = 10 and 12 keep the real-time x sweep (with the phase factor) at <= 64 VGPRs, i.e.
+// 8 waves per SIMD, where M = 16 needs 80 (6 waves).  For lines of up to 2048 points:
+// SW = 8 with M = 16, 30, 32 in both precisions (M = 30, 32: at most 8 wavefronts, so the
+// 512-thread bound and no spills), and complex64 M = 30 with SW = 4 (128-byte line chunks).
 bool sweep_lines_supported(int precision, int m, int sw) {
-  if (sw == 8) return m == 16;  // lines of up to 2048 points (complex64 without M = 32's spills)
-  if (m == 30) return precision == 0 && sw == 4;  // 1920-point lines in 16 wavefronts, 128-byte line chunks
+  if (sw == 8) return m == 16 || m == 30 || m == 32;
+  if (m == 30) return precision == 0 && sw == 4;
   if (sw != 1 && sw != 2 && sw != 4) return false;
   if (precision == 0) return m == 8 || m == 10 || m == 12 || m == 16 || m == 32;
   return m == 8 || m == 16;
@@ -303,6 +306,7 @@ bool sweep_lines_supported(int precision, int m, int sw) {
 // complex128 lines of up to 1024 with 8 points per thread) on grids whose planes are so
 // large that a wavefront's rows span 2 GiB or more
 bool sweep_lines_wide_supported(int precision, int m, int sw) {
+  if ((m == 30 || m == 32) && sw == 8) return true;
   if (precision == 0) return (m == 16 && (sw == 4 || sw == 8)) || ((m == 30 || m == 32) && sw == 4);
   return (m == 16 && (sw == 4 || sw == 8)) || (m == 8 && sw == 4);
 }
@@ -314,10 +318,14 @@ hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipS
       if (a.m == 16 && a.sw == 8) return go_lines_mode<float, 16, 8, true>(cc, a, s);
       if (a.m == 30 && a.sw == 4) return go_lines_mode<float, 30, 4, true>(cc, a, s);
       if (a.m == 32 && a.sw == 4) return go_lines_mode<float, 32, 4, true>(cc, a, s);
+      if (a.m == 30 && a.sw == 8) return go_lines_mode<float, 30, 8, true>(cc, a, s);
+      if (a.m == 32 && a.sw == 8) return go_lines_mode<float, 32, 8, true>(cc, a, s);
     } else {
       if (a.m == 16 && a.sw == 4) return go_lines_mode<double, 16, 4, true>(cc, a, s);
       if (a.m == 16 && a.sw == 8) return go_lines_mode<double, 16, 8, true>(cc, a, s);
       if (a.m == 8 && a.sw == 4) return go_lines_mode<double, 8, 4, true>(cc, a, s);
+      if (a.m == 30 && a.sw == 8) return go_lines_mode<double, 30, 8, true>(cc, a, s);
+      if (a.m == 32 && a.sw == 8) return go_lines_mode<double, 32, 8, true>(cc, a, s);
     }
     return hipErrorInvalidValue;
   }
@@ -325,12 +333,16 @@ hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipS
     if (a.m == 8) GP_LINES_SW(float, 8);
     if (a.m == 16 && a.sw == 8) return go_lines_mode<float, 16, 8>(cc, a, s);
     if (a.m == 30 && a.sw == 4) return go_lines_mode<float, 30, 4>(cc, a, s);
+    if (a.m == 30 && a.sw == 8) return go_lines_mode<float, 30, 8>(cc, a, s);
+    if (a.m == 32 && a.sw == 8) return go_lines_mode<float, 32, 8>(cc, a, s);
     if (a.m == 16) GP_LINES_SW(float, 16);
     if (a.m == 12) GP_LINES_SW(float, 12);
     if (a.m == 10) GP_LINES_SW(float, 10);
     if (a.m == 32) GP_LINES_SW(float, 32);
   } else {
     if (a.m == 16 && a.sw == 8) return go_lines_mode<double, 16, 8>(cc, a, s);
+    if (a.m == 30 && a.sw == 8) return go_lines_mode<double, 30, 8>(cc, a, s);
+    if (a.m == 32 && a.sw == 8) return go_lines_mode<double, 32, 8>(cc, a, s);
     if (a.m == 8) GP_LINES_SW(double, 8);
     if (a.m == 16) GP_LINES_SW(double, 16);
   }
@@ -384,25 +396,36 @@ hipError_t launch_stream_lines(int precision, bool cc, const SweepLaunch& a, hip
   return hipErrorInvalidValue;
 }
 
-template <typename R, int MZ, bool CC, bool NORM, int EPI>
-static hipError_t go_z(const SweepLaunch& a, hipStream_t s) {
+template <typename R, int MZ, bool CC, bool NORM, int EPI, int NW>
+static hipError_t go_z_w(const SweepLaunch& a, hipStream_t s) {
   typedef typename VecOf<R>::T V;
   const int zpad = (MZ % 2 == 0) ? a.zpad : 0;
-  const size_t lds = z_lds(a.nz, a.nseg, MZ, zpad, sizeof(V));
+  const size_t lds = z_lds(a.nz, a.nseg, MZ, zpad, sizeof(V), NW);
   if (lds > 65536 - 512) {  // more than the default 64 KiB per block: opt in (up to 160 KiB)
     static size_t granted = 0;
     if (lds > granted) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_sweep_z<R, MZ, CC, NORM, EPI>,
+      hipError_t e = hipFuncSetAttribute((const void*)k_sweep_z<R, MZ, CC, NORM, EPI, NW>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
       granted = lds;
     }
   }
-  hipLaunchKernelGGL((k_sweep_z<R, MZ, CC, NORM, EPI>), dim3(a.grid), dim3(256), lds, s, (V*)a.psi,
+  hipLaunchKernelGGL((k_sweep_z<R, MZ, CC, NORM, EPI, NW>), dim3(a.grid), dim3(64 * NW), lds, s, (V*)a.psi,
                      cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4), cval<R>(a.coef + 6),
                      (const V*)a.omega, a.nw, a.nz, a.nseg, a.nlines, a.partials, (const R*)a.vx, (const R*)a.vy,
                      Pot1D<R>{(R)a.ph, (R)a.pc, (R)a.pd}, a.ny, (R)a.tau, a.st, zpad);
   return hipGetLastError();
+}
+
+// one-wavefront blocks exist for the instances of long lines (z_waves picks them)
+template <int MZ> constexpr bool kZOneWave = MZ >= 8;
+
+template <typename R, int MZ, bool CC, bool NORM, int EPI>
+static hipError_t go_z(const SweepLaunch& a, hipStream_t s) {
+  if constexpr (kZOneWave<MZ>)
+    if (a.zw == 1) return go_z_w<R, MZ, CC, NORM, EPI, 1>(a, s);
+  if (a.zw != 4) return hipErrorInvalidValue;
+  return go_z_w<R, MZ, CC, NORM, EPI, 4>(a, s);
 }
 
 template <typename R, int MZ>
@@ -453,6 +476,47 @@ hipError_t launch_sweep_z(int precision, bool cc, const SweepLaunch& a, hipStrea
   GP_Z_M(double);
 }
 #undef GP_Z_M
+
+namespace {
+template <typename K> int occ_of(K kern, int threads, size_t lds) {
+  if (lds > 65536 - 512 && hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                (int)lds) != hipSuccess)
+    return 0;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, lds) != hipSuccess) return 0;
+  return n;
+}
+template <typename R, int MZ, int NW> int z_occ_w(size_t lds) {
+  return std::min(occ_of(k_sweep_z<R, MZ, false, true, 0, NW>, 64 * NW, lds),
+                  occ_of(k_sweep_z<R, MZ, false, true, 1, NW>, 64 * NW, lds));
+}
+template <typename R, int MZ> int z_occ(int zw, size_t lds) {
+  if constexpr (kZOneWave<MZ>)
+    if (zw == 1) return z_occ_w<R, MZ, 1>(lds);
+  return zw == 4 ? z_occ_w<R, MZ, 4>(lds) : 0;
+}
+template <typename R> int z_occ_m(int mz, int zw, size_t lds) {
+  switch (mz) {
+    case 2: return z_occ<R, 2>(zw, lds);
+    case 4: return z_occ<R, 4>(zw, lds);
+    case 6: return z_occ<R, 6>(zw, lds);
+    case 7: return z_occ<R, 7>(zw, lds);
+    case 8: return z_occ<R, 8>(zw, lds);
+    case 12: return z_occ<R, 12>(zw, lds);
+    case 14: return z_occ<R, 14>(zw, lds);
+    case 15: return z_occ<R, 15>(zw, lds);
+    case 16: return z_occ<R, 16>(zw, lds);
+    case 20: return z_occ<R, 20>(zw, lds);
+    case 24: return z_occ<R, 24>(zw, lds);
+    case 32: return z_occ<R, 32>(zw, lds);
+  }
+  return 0;
+}
+}  // namespace
+
+int z_resident_per_cu(int precision, int mz, int zw, size_t lds) {
+  return precision == 0 ? z_occ_m<float>(mz, zw, lds) : z_occ_m<double>(mz, zw, lds);
+}
 
 hipError_t launch_finalize_norm(const double* partials, int nb, double dV, double dt, DevState* st,
                                 hipStream_t s) {

@@ -180,7 +180,7 @@ def test_invalid_mapping_rejected():
     with gp.Solver.from_workload(psi, prm) as s:
         before = s.get_mapping()
         for bad in [(1, 1, 0, 0, 0, 0), (0, 3, 0, 0, 0, 0), (0, 0, 0, 0, 3, 0), (0, 0, 0, 0, 4, 3),
-                    (64, 0, 0, 0, 0, 0), (0, 0, 0, 0, 128, 0), (0, 0, 32, 8, 0, 0)]:
+                    (64, 0, 0, 0, 0, 0), (0, 0, 0, 0, 128, 0), (0, 0, 24, 8, 0, 0)]:
             with pytest.raises(gp.GPError):
                 s.set_mapping(*bad)
         assert s.get_mapping() == before
