@@ -8,6 +8,8 @@
   Writes the JSON that bench.py reports as ``roofline.traffic`` when the mapping matches.
 * ``stats``: a markdown table of a ``--kernel-trace --stats`` summary, with algorithmic
   GB/s for the sweep kernels of one grid (one read and one write of psi per launch).
+* ``counters``: the mean per dispatch of every counter of one or more ``--pmc`` runs, per
+  sweep kernel.
 
     python -m paper_1601_04641_amd.profiling traffic --fetch F.csv --write W.csv \\
         --bench B.json --out profiles/traffic.json
@@ -126,6 +128,28 @@ def traffic(fetch_csv: str, write_csv: str, bench_json: str, copy_bytes: int = 1
     return out
 
 
+def counter_table(csvs, kernels=None):
+    """Markdown table of the mean value per dispatch of every counter in the given
+    counter_collection CSVs, one row per sweep kernel (or per kernel whose name contains
+    one of `kernels`)."""
+    vals = defaultdict(lambda: defaultdict(list))
+    for path in csvs:
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                vals[row["Kernel_Name"]][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    names = sorted({c for d in vals.values() for c in d})
+    lines = ["| kernel | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    for k in sorted(vals):
+        keep = classify(k) is not None if kernels is None else any(s in k for s in kernels)
+        if not keep:
+            continue
+        d = vals[k]
+        n = max(len(v) for v in d.values())
+        cells = [f"{sum(d[c]) / len(d[c]):.4g}" if d.get(c) else "" for c in names]
+        lines.append(f"| `{k.split('(')[0].replace('void ', '')}` | {n} | " + " | ".join(cells) + " |")
+    return "\n".join(lines)
+
+
 def _col(row, *names):
     for n in names:
         if n in row:
@@ -165,6 +189,9 @@ def main(argv=None):
     t.add_argument("--calib-kernel", default="__amd_rocclr_copyBuffer",
                    help="name prefix of the copy kernel whose dispatches of --copy-bytes calibrate the counters")
     t.add_argument("--out", default=None)
+    c = sub.add_parser("counters")
+    c.add_argument("csv", nargs="+", help="counter_collection CSVs of one or more --pmc runs")
+    c.add_argument("--kernels", nargs="*", default=None, help="name fragments to keep (default: the sweeps)")
     s = sub.add_parser("stats")
     s.add_argument("--stats", required=True)
     s.add_argument("--points", type=int, default=0)
@@ -177,6 +204,8 @@ def main(argv=None):
             with open(a.out, "w") as f:
                 f.write(text + "\n")
         print(text)
+    elif a.cmd == "counters":
+        print(counter_table(a.csv, a.kernels))
     else:
         print(stats_table(a.stats, a.points, a.top))
 

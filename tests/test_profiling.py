@@ -82,3 +82,18 @@ def test_stats_table(tmp_path):
     lines = t.splitlines()
     assert lines[2].startswith("| `gpk::k_sweep_z<double, 7, true, false, 0>` | 10 | 700.0 | 60.0% | 5033 |")
     assert lines[3].endswith("| 40.0% |  |")
+
+
+def test_counter_table(tmp_path):
+    f = tmp_path / "c.csv"
+    with open(f, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(HEAD)
+        w.writerow([0, 0, "Agent 1", 1, 1, 1, 64, 1, X128, 64, 0, 0, 8, 0, 8, "TCP_UTCL1_REQUEST_sum", 10, 0, 1])
+        w.writerow([1, 1, "Agent 1", 1, 1, 1, 64, 1, X128, 64, 0, 0, 8, 0, 8, "TCP_UTCL1_REQUEST_sum", 30, 0, 1])
+        w.writerow([2, 2, "Agent 1", 1, 1, 1, 64, 1, COPY, 64, 0, 0, 8, 0, 8, "TCP_UTCL1_REQUEST_sum", 5, 0, 1])
+    t = profiling.counter_table([str(f)]).splitlines()
+    assert t[0] == "| kernel | dispatches | TCP_UTCL1_REQUEST_sum |"
+    assert t[2] == "| `gpk::k_sweep_lines<double, 16, 8, true, 2, false, 8>` | 2 | 20 |"
+    assert len(t) == 3   # the copy kernel is not a sweep
+    assert len(profiling.counter_table([str(f)], kernels=["rocclr"]).splitlines()) == 3
