@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--paper-precision", choices=("c64", "c128", "both"), default="both")
     ap.add_argument("--paper-iterations", type=int, default=1000,
                     help="timed iterations per grid in --paper-scale (the paper's runs: 1000)")
+    ap.add_argument("--paper-no-trunc", action="store_true",
+                    help="--paper-scale: skip the halo-truncated repeat of each run")
     return ap.parse_args()
 
 
@@ -356,11 +358,24 @@ def cpu_baseline(inputs):
                 legs=legs)
 
 
+def max_rel_diff(torch, a, b, chunk=1 << 26):
+    """max|a - b| / max|b| over flat views, in chunks (no psi-sized temporaries)."""
+    fa, fb = a.reshape(-1), b.reshape(-1)
+    num = den = 0.0
+    for o in range(0, fa.numel(), chunk):
+        num = max(num, float((fa[o:o + chunk] - fb[o:o + chunk]).abs().max()))
+        den = max(den, float(fb[o:o + chunk].abs().max()))
+    return num / den
+
+
 def run_paper_scale(torch, gp, inputs, args):
     """The paper's large runs on one device: 1000 imaginary-time iterations on 1920x1600x1280
     and 1000 real-time iterations on 1600x1280x960 from the trap's Gaussian, in complex128
     (the paper's precision; 63 and 31 GB) and complex64 storage and sweeps with FP64
-    reductions (31.5 and 15.7 GB), psi resident in HBM, autotuned line mapping."""
+    reductions (31.5 and 15.7 GB), psi resident in HBM, autotuned line mapping.  Each run
+    is repeated from the same start with the halo-truncated inverse's streaming x and y
+    sweeps (gp_set_truncation mode 1; `halo_truncated_mode1`, with the largest difference
+    of its final state from the exact run's) unless --paper-no-trunc."""
     out = {}
     precs = {"c64": [gp.GP_C64], "c128": [gp.GP_C128], "both": [gp.GP_C128, gp.GP_C64]}[args.paper_precision]
     for prec in precs:
@@ -374,46 +389,65 @@ def run_paper_scale(torch, gp, inputs, args):
             f = [torch.from_numpy(v.astype(ndt)).to("cuda")
                  for v in inputs.gaussian_factors(nx, ny, nz, w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"],
                                                   w["nuz"])]
-            psi = (f[0][:, None, None] * f[1][None, :, None]) * f[2][None, None, :]
-            del f
-            assert psi.dtype == cdt
-            s = gp.Solver.from_workload(psi, w)
-            step = s.step_imag if imag else s.step_real
-            log(f"[bench] {name} {tag}: {npts * esz / 1e9:.1f} GB, default mapping {s.get_mapping()}")
-            if args.mapping:
-                s.set_mapping(*(int(v) for v in args.mapping.split(",")))
-            elif not args.no_autotune:
-                s.autotune("imag" if imag else "real", steps=3, cache_path=args.tune_cache)
-            log(f"[bench] {name} {tag}: mapping {s.get_mapping()}; warmup")
-            step(args.warmup)
-            n0 = s.norm()
-            torch.cuda.synchronize()
-            s.set_timing(True)
-            log(f"[bench] {name} {tag}: timed {K} iterations")
-            t0 = time.perf_counter()
-            step(K)
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-            ms, n = s.get_timing()
-            s.set_timing(False)
-            e, mu = s.energy_mu()
-            n1 = s.norm()
-            r = dict(grid=[nx, ny, nz], precision=tag, mode="imaginary" if imag else "real", iterations=K,
-                     seconds=wall, ms_per_step=wall / K * 1e3, updates_per_s=npts * K / wall,
-                     algorithmic_frac_of_hbm_peak=npts * K / wall * 6 * esz / PEAK_HBM,
-                     kernels={KINDS[q]: dict(ms=float(ms[q]), GBps=2 * esz * npts / (ms[q] * 1e-3) / 1e9)
-                              for q in range(3) if n[q]},
-                     mapping=s.get_mapping(), mu=mu, energy=e,
-                     norm=n1 if imag else None, norm_drift=None if imag else abs(n1 - n0) / n0)
-            log(f"[bench] {name} {tag}: {wall:.1f} s for {K} iterations ({r['ms_per_step']:.2f} ms/step)")
-            s.close()
-            del psi
+            psi = torch.empty((nx, ny, nz), dtype=cdt, device="cuda")
+            ref = None
+            mapping = None
+            for trunc in ((0,) if args.paper_no_trunc else (0, 1)):
+                torch.mul(f[0][:, None, None] * f[1][None, :, None], f[2][None, None, :], out=psi)
+                s = gp.Solver.from_workload(psi, w)
+                step = s.step_imag if imag else s.step_real
+                if trunc == 0:
+                    log(f"[bench] {name} {tag}: {npts * esz / 1e9:.1f} GB, default mapping {s.get_mapping()}")
+                    if args.mapping:
+                        s.set_mapping(*(int(v) for v in args.mapping.split(",")))
+                    elif not args.no_autotune:
+                        s.autotune("imag" if imag else "real", steps=3, cache_path=args.tune_cache)
+                    mapping = s.get_mapping()
+                else:
+                    s.set_mapping(*mapping)
+                    s.set_truncation(1)
+                label = "exact" if trunc == 0 else "halo-truncated mode 1"
+                log(f"[bench] {name} {tag} {label}: mapping {s.get_mapping()}; warmup")
+                step(args.warmup)
+                n0 = s.norm()
+                torch.cuda.synchronize()
+                s.set_timing(True)
+                log(f"[bench] {name} {tag} {label}: timed {K} iterations")
+                t0 = time.perf_counter()
+                step(K)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                ms, n = s.get_timing()
+                s.set_timing(False)
+                e, mu = s.energy_mu()
+                n1 = s.norm()
+                r = dict(grid=[nx, ny, nz], precision=tag, mode="imaginary" if imag else "real", iterations=K,
+                         seconds=wall, ms_per_step=wall / K * 1e3, updates_per_s=npts * K / wall,
+                         algorithmic_frac_of_hbm_peak=npts * K / wall * 6 * esz / PEAK_HBM,
+                         kernels={KINDS[q]: dict(ms=float(ms[q]), GBps=2 * esz * npts / (ms[q] * 1e-3) / 1e9)
+                                  for q in range(3) if n[q]},
+                         mapping=s.get_mapping(), mu=mu, energy=e,
+                         norm=n1 if imag else None, norm_drift=None if imag else abs(n1 - n0) / n0)
+                if trunc:
+                    r["halo"] = s.get_truncation()[1][0 if imag else 1]
+                s.close()
+                log(f"[bench] {name} {tag} {label}: {wall:.1f} s for {K} iterations ({r['ms_per_step']:.2f} ms/step)")
+                torch.cuda.synchronize()
+                if trunc == 0:
+                    out[f"{name}_{tag}"] = r
+                    if not args.paper_no_trunc:
+                        ref = psi.clone()
+                else:
+                    r["max_rel_diff_vs_exact"] = max_rel_diff(torch, psi, ref)
+                    out[f"{name}_{tag}"]["halo_truncated_mode1"] = r
+                    log(f"[bench] {name} {tag}: final states differ by {r['max_rel_diff_vs_exact']:.2e}")
+            del f, psi, ref
             torch.cuda.empty_cache()
             # the practical ceiling at this footprint: a copy of psi's size
-            r.update(stream_copy_gbps(torch, gp, nbytes=npts * esz, reps=3))
+            out[f"{name}_{tag}"].update(stream_copy_gbps(torch, gp, nbytes=npts * esz, reps=3))
+            r = out[f"{name}_{tag}"]
             log(f"[bench] {name} {tag}: copies of {npts * esz / 1e9:.1f} GB: "
                 f"{r['library_copy_GBps']:.0f} (library), {r['torch_copy_GBps']:.0f} (torch) GB/s")
-            out[f"{name}_{tag}"] = r
     return out
 
 

@@ -157,9 +157,11 @@ int gp_set_mapping(gp_ctx* c, const int32_t map[6]);
  * rows, each started H rows early), and every row the truncated y solve emits is a whole
  * z line, solved at once in LDS; psi crosses HBM twice per step instead of three times
  * (32 instead of 48 B per point in complex64).  mode 2 needs z lines of at most 1024
- * points and psi-sized free device memory (else GP_ERR_OOM, mode unchanged).  mode 0: exact
- * sweeps (default).  Returns GP_ERR_UNSUPPORTED (mode unchanged) when H exceeds 15
- * (dt/dx^2 large) or the grid does not fit the fused pass.
+ * points, one group of rows of z lines ((H + 1) ceil(ceil(nz/64) / (H + 1)) rows) within
+ * 160 KiB of LDS (complex128 960-point lines with H = 6 need 261 KB: unsupported), and
+ * psi-sized free device memory (else GP_ERR_OOM, mode unchanged).  mode 0: exact sweeps
+ * (default).  Returns GP_ERR_UNSUPPORTED (mode unchanged) when H exceeds 15 (dt/dx^2
+ * large) or the grid does not fit the fused pass.
  * gp_get_truncation: the mode and H per [imaginary, real][x, y, z].  Synchronises. */
 int gp_set_truncation(gp_ctx* c, int32_t mode);
 int gp_get_truncation(gp_ctx* c, int32_t* mode, int32_t hlen[6]);

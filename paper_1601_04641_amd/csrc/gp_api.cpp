@@ -1212,6 +1212,12 @@ int gp_set_truncation(gp_ctx* c, int32_t mode) {
         return GP_ERR_UNSUPPORTED;
       }
       nwy = std::max(nwy, c->nw[m][1]);
+      const size_t lds = gpk::yz_lds(p.nz, c->hlen[m][1], c->esize);
+      if (lds > gpk::kMaxLdsBlock) {  // the rows of one group of z lines must fit one block's LDS
+        snprintf(c->err, sizeof(c->err), "the fused y+z pass would need %zu bytes of LDS per block (at most %zu)",
+                 lds, gpk::kMaxLdsBlock);
+        return GP_ERR_UNSUPPORTED;
+      }
     }
     // enough blocks to fill the device (about 2048), chunks of at least 32 rows, and the
     // y head correction inside the first chunk (the only block that holds u_0)

@@ -228,6 +228,15 @@ int yz_h(int h) {
   return -1;
 }
 
+size_t yz_lds(int nz, int h, size_t esize) {
+  const int H = yz_h(h), mz = yz_mz(nz);
+  if (H < 0 || mz < 0) return 0;
+  const int waves = (nz + 63) / 64;
+  const int group = (H + 1) * ((waves + H) / (H + 1));
+  const int zp = (mz % 4 == 0) ? 1 : 0;
+  return (size_t)group * z_pitch(nz, mz, zp) * esize;
+}
+
 int yz_mz(int nz) {
   for (int m : {4, 6, 7, 8, 12, 16})
     if (64 * m >= nz) return m;

@@ -69,8 +69,11 @@ def unpack(psi, ws, offs):
 
 def c64_tolerance(w, s0, ref, imag, steps=20):
     """complex64 tolerance from the problem's own conditioning: the oracle is rerun from
-    the initial state perturbed by FP32-sized relative noise (6e-8); the FP32 path commits
-    such an error at every step, so 40x the resulting deviation (floor 5e-6) bounds it.
+    the initial state perturbed by FP32-sized relative noise (u = 6e-8), which measures the
+    amplification A of an error committed at the start (sens = A u).  The FP32 path commits
+    an error of about 2u per step (the rounding of psi after each sweep, with the
+    coefficient tables rounded once), each amplified by at most A over the remaining steps:
+    20 steps x 2u x A = 40 sens bounds the total (floor 5e-6 for well-conditioned cases).
     Strongly nonlinear real-time cases (g ~ 10^3) amplify input noise ~70x in 20 steps."""
     rng = np.random.default_rng(12345)
     o = oracle.Oracle.from_params(w, s0 * (1 + 6e-8 * rng.standard_normal(s0.shape)))

@@ -134,3 +134,29 @@ def test_fused_pass_limits_and_norm():
             assert abs(s.norm() - 1.0) <= 1e-12
             ests.append(s.status()[1])
     assert abs(ests[0] - ests[1]) <= 1e-12 * abs(ests[0])
+
+
+@pytest.mark.parametrize("imag", [True, False])
+def test_fused_pass_large_lds(imag):
+    """960-point z lines: one group of rows needs 130-147 KB of LDS in complex64 (the
+    blocks opt in beyond 64 KiB) and matches the oracle; complex128 would need 261-392 KB
+    and is refused, the exact sweeps staying on.  dt = 0.1 dx^2 (imaginary) and
+    0.01 dx^2 (real), as the workloads use (H = 5 / 3 in complex64, 11 / 6 in complex128)."""
+    nx, ny, nz = 3, 40, 960
+    dx = 0.03
+    prm = dict(nx=nx, ny=ny, nz=nz, dx=dx, dy=dx, dz=dx, nux=1.3, nuy=1.1, nuz=0.9, g=30.0,
+               dt=(0.1 if imag else 0.01) * dx * dx)
+    psi0 = inputs.perturbed_psi(nx, ny, nz, dx, dx, dx, 0.03, 0.04, 0.05, seed=960, amp=0.2)
+    psi = torch.from_numpy(psi0).to("cuda")
+    with gp.Solver.from_workload(psi, prm) as s:
+        with pytest.raises(gp.GPError) as ei:
+            s.set_truncation(2)
+        assert ei.value.code == gp.GP_ERR_UNSUPPORTED
+        assert s.get_truncation()[0] == 0
+    psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    out, h = run(prm, psi0, gp.GP_C64, imag, 3, mode=2)
+    o = oracle.Oracle.from_params(prm, psi0)
+    (o.step_imag if imag else o.step_real)(3)
+    err = rel_err(out, o.psi)
+    say(f"case: fused pass 960-point z lines imag {imag} H {h}: rel err {err:.2e}")
+    assert err <= 2e-6
