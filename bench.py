@@ -220,13 +220,17 @@ def run_batch(torch, gp, inputs, args):
             "kernels": kern, "mu_range": [float(np.min(mu)), float(np.max(mu))]}
 
 
-def run_truncated(torch, gp, inputs, w, args):
-    """The halo-truncated inverse (gp_set_truncation) on the quench grid, per precision and
-    step kind: the exact sweeps (mode 0), the streaming x and y sweeps (mode 1) and the exact
-    x sweep followed by one fused pass of the truncated y sweep and the z sweep (mode 2), each
-    `trunc_steps` steps from the same Gaussian start after 5 untimed ones; ms per step, the
-    algorithmic fraction of the HBM peak (6 psi transfers per step in modes 0 and 1, 4 in
-    mode 2) and the largest difference from mode 0's final state relative to max|psi|."""
+def run_truncated(torch, gp, inputs, w, args, main):
+    """The halo-truncated inverse (gp_set_truncation) on the quench grid, per precision:
+    imaginary time in the exact sweeps (mode 0), the streaming x and y sweeps (mode 1) and
+    the exact x sweep followed by one fused pass of the truncated y sweep and the z sweep
+    (mode 2), each `trunc_steps` steps from the same Gaussian start after 5 untimed ones,
+    with the largest difference from mode 0's final state relative to max|psi|; real time
+    in mode 1 only, against the headline's own timed exact steps (`main`).  The exact
+    real-time kernels (and mode 2's exact x sweep, the same kernel) are not launched here,
+    so the kernel statistics of a default run hold only the timed region's calls of them.
+    ms per step and the algorithmic fraction of the HBM peak (6 psi transfers per step in
+    modes 0 and 1, 4 in mode 2)."""
     nx, ny, nz = w["nx"], w["ny"], w["nz"]
     npts = nx * ny * nz
     K = args.trunc_steps
@@ -238,13 +242,13 @@ def run_truncated(torch, gp, inputs, w, args):
         psi0 = torch.from_numpy(inputs.gaussian_psi(nx, ny, nz, w["dx"], w["dy"], w["dz"], w["nux"], w["nuy"],
                                                     w["nuz"], dtype=ndt)).to("cuda")
         psi = torch.empty_like(psi0)
-        for kind in ("imag", "real"):
+        for kind, modes in (("imag", (0, 1, 2)), ("real", (1,))):
             prm = dict(w, dt=w["dt_imag"]) if kind == "imag" else dict(w)
             ref = None
-            for mode in (0, 1, 2):
+            for mode in modes:
                 psi.copy_(psi0)
                 with gp.Solver.from_workload(psi, prm) as s:
-                    if not args.no_autotune:   # the exact sweeps' mapping (x in mode 2)
+                    if not args.no_autotune:   # the exact sweeps' mapping (z in mode 1, x in mode 2)
                         s.autotune(kind, steps=args.autotune_steps, cache_path=args.tune_cache)
                     s.set_truncation(mode)
                     step = s.step_imag if kind == "imag" else s.step_real
@@ -259,7 +263,9 @@ def run_truncated(torch, gp, inputs, w, args):
                     s.set_timing(False)
                     hlen = s.get_truncation()[1][0 if kind == "imag" else 1]
                 torch.cuda.synchronize()
-                if mode == 0:
+                if kind == "real":
+                    diff = None   # no exact reference from this start (tests cover the accuracy)
+                elif mode == 0:
                     ref = psi.clone()
                     diff = 0.0
                 else:
@@ -269,9 +275,13 @@ def run_truncated(torch, gp, inputs, w, args):
                          algorithmic_frac_of_hbm_peak=npts * K / wall * moves * esz / PEAK_HBM,
                          kernel_ms={KINDS[q]: float(ms[q]) for q in range(3) if n[q]},
                          halo=hlen if mode else None, max_rel_diff_vs_exact=diff)
+                if kind == "real" and prec in main:
+                    m = main[prec]
+                    r["exact_ms_per_step"] = m["ms_per_step"]
+                    r["speedup_vs_exact"] = m["ms_per_step"] / r["ms_per_step"]
                 out[f"{tag}_{kind}_mode{mode}"] = r
-                log(f"[bench] truncation {tag} {kind} mode {mode}: {r['ms_per_step']:.3f} ms/step, "
-                    f"diff vs exact {diff:.2e}")
+                log(f"[bench] truncation {tag} {kind} mode {mode}: {r['ms_per_step']:.3f} ms/step"
+                    + ("" if diff is None else f", diff vs exact {diff:.2e}"))
             del ref
         del psi, psi0
         torch.cuda.empty_cache()
@@ -546,7 +556,8 @@ def main():
         sub["precision"] = ("complex64 storage+sweeps, FP64 reductions" if other == gp.GP_C64 else "complex128")
         out["precision_form" if other == gp.GP_C64 else "complex128"] = sub
     if not args.no_trunc:
-        out["halo_truncated"] = run_truncated(torch, gp, inputs, w, args)
+        out["halo_truncated"] = run_truncated(torch, gp, inputs, w, args,
+                                              {p: summary(p) for p in precs})
     if not args.no_batch:
         out["batched"] = run_batch(torch, gp, inputs, args)
     if not args.no_ttgs and os.path.exists(args.weights):
