@@ -263,15 +263,19 @@ bool pick_lines(int prec, const AxisLines& a, bool nstep, int* m_out, int* sw_ou
 // z sweep grid: the blocks that fit on the device at once (LDS bound: each block holds
 // 4 L lines of nz points), each walking an equal share of the line groups; a second,
 // partial round of blocks would leave most CUs idle at the tail
-int zpad_of(int nz, int seg, int m, size_t esize) { return gpk::z_pad(nz, seg, m, esize, gpk::kMaxLdsBlock); }
+// complex64 z blocks hold the Sherman-Morrison vector (at most nz values) beside their rows
+size_t z_omega_bound(int nz, size_t esize) { return gpk::z_omega_in_lds(esize, 4) ? (size_t)nz * esize : 0; }
+int zpad_of(int nz, int seg, int m, size_t esize) {
+  return gpk::z_pad(nz, seg, m, esize, gpk::kMaxLdsBlock, z_omega_bound(nz, esize));
+}
 
 // z sweep grids.  4-wavefront blocks: complex128 one block per line group (measured
 // 723 -> 706 us, with the non-temporal policy 671 -> 654 us on the quench grid); complex64
 // the blocks that fit on the device at once, each walking an equal share of the groups
 // (one block per group measured 2-4% slower there; a second, partial round of resident
-// blocks would leave most CUs idle at the tail).  1-wavefront blocks (long lines): one
-// block per group in real time; in imaginary time the resident grid (the occupancy of the
-// kernel instance), which keeps the norm partials few.
+// blocks would leave most CUs idle at the tail).  1-wavefront blocks (long complex128
+// lines): one block per group in real time; in imaginary time one block per 16 groups,
+// which keeps the norm partials (one per block) few enough for the finalize kernel.
 struct ZPlan {
   int zw = 4;
   int64_t groups = 0;
@@ -285,31 +289,33 @@ ZPlan z_plan(const gp_ctx* c, int segz, int mz) {
   const int64_t per_grp = (int64_t)z.zw * (64 / segz);
   z.groups = ((int64_t)c->p.nx * c->p.ny + per_grp - 1) / per_grp;
   const int64_t one_shot = std::max<int64_t>(1, std::min<int64_t>(z.groups, 0x7fffffff));
+  if (z.zw == 1) {
+    z.grid_imag = (int)std::max<int64_t>(1, std::min<int64_t>((z.groups + 15) / 16, 0x7fffffff));
+    z.grid_real = (int)one_shot;
+    return z;
+  }
+  if (c->esize == 16) {
+    z.grid_imag = z.grid_real = (int)one_shot;
+    return z;
+  }
   int cus = 0, lds_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1) cus = 256;
   if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) != hipSuccess ||
       lds_cu < 65536)
     lds_cu = 65536;
-  const size_t lds = gpk::z_lds(c->p.nz, segz, mz, zpad, c->esize, z.zw);
-  if (z.zw == 1) {
-    int64_t per_cu = gpk::z_resident_per_cu(c->esize == 16 ? 1 : 0, mz, 1, lds);
-    if (per_cu < 1) per_cu = std::max<int64_t>(1, std::min<int64_t>(lds_cu / (int64_t)(lds + 512), 16));
-    z.grid_imag = (int)std::max<int64_t>(1, std::min<int64_t>(z.groups, per_cu * cus));
-    z.grid_real = (int)one_shot;
-  } else if (c->esize == 16) {
-    z.grid_imag = z.grid_real = (int)one_shot;
-  } else {
-    int64_t per_cu = lds_cu / std::max<int64_t>((int64_t)lds + 512, 1);
-    per_cu = std::max<int64_t>(1, std::min<int64_t>(per_cu, 8));
-    z.grid_imag = z.grid_real = (int)std::max<int64_t>(1, std::min<int64_t>(z.groups, per_cu * cus));
-  }
+  const int nom = std::max(c->nw[0][2], c->nw[1][2]);
+  const size_t lds = gpk::z_lds(c->p.nz, segz, mz, zpad, c->esize, z.zw) +
+                     (gpk::z_omega_in_lds(c->esize, z.zw) ? (size_t)nom * c->esize : 0);
+  int64_t per_cu = lds_cu / std::max<int64_t>((int64_t)lds + 512, 1);
+  per_cu = std::max<int64_t>(1, std::min<int64_t>(per_cu, 8));
+  z.grid_imag = z.grid_real = (int)std::max<int64_t>(1, std::min<int64_t>(z.groups, per_cu * cus));
   return z;
 }
 
 bool valid_z(int nz, int seg, int m, size_t esize) {
   if (seg < 2 || seg > 64 || (seg & (seg - 1)) != 0) return false;
   if (!gpk::sweep_z_supported(esize == 16 ? 1 : 0, m)) return false;
-  if ((size_t)4 * (64 / seg) * nz * esize + 512 > gpk::kMaxLdsBlock) return false;
+  if ((size_t)4 * (64 / seg) * nz * esize + z_omega_bound(nz, esize) + 512 > gpk::kMaxLdsBlock) return false;
   return (int64_t)seg * m >= nz;  // trailing positions are zero-coefficient padding
 }
 

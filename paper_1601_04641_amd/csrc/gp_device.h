@@ -614,7 +614,7 @@ __device__ __forceinline__ void z_line_solve(typename VecOf<R>::T (&v)[MZ], cons
 // Processes line groups grp_begin, grp_begin + grp_step, ...; returns this thread's FP64
 // sum of |psi|^2 over the stored points when NORM.
 // ---------------------------------------------------------------------------------------
-template <typename R, int MZ, bool CC, bool NORM, int EPI, int NW = 4>
+template <typename R, int MZ, bool CC, bool NORM, int EPI, int NW = 4, bool OML = false>
 __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca,
                                          typename VecOf<R>::T cb, typename VecOf<R>::T cbl,
                                          typename VecOf<R>::T cP, const typename VecOf<R>::T* __restrict__ omega,
@@ -652,6 +652,19 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
   const bool pairs = sizeof(V) == 8 && (nz & 1) == 0 && al16;  // with zp = 1 (MZ even)
   const int cn = pairs ? half : nz;
   const int dl = NT / cn, dq = NT % cn;
+  // One-wavefront blocks (long complex128 lines: 15-20 values per thread to copy) issue
+  // their copies KB at a time, all loads before the LDS stores: one copy per iteration
+  // waits out a whole memory latency per value, with few other wavefronts to cover it.
+  constexpr int KB = (NW == 1) ? 8 : 1;
+  // OML: the Sherman-Morrison vector is read from LDS (staged after the line rows once per
+  // block) instead of global memory: each lane's read of it depends on its segment, so the
+  // global loads were issued one at a time, each waiting out a cache latency, per group.
+  const V* om = omega;
+  if constexpr (OML) {
+    V* s_om = sdata + (size_t)lines_per_grp * pitch;
+    for (int q = tid; q < nwi; q += NT) s_om[q] = omega[q];
+    om = s_om;  // visible to every wavefront after the first group's copy-in barrier
+  }
 
   for (int64_t grp = grp_begin; grp < ngrp; grp += grp_step) {
     const int64_t line0 = grp * lines_per_grp;
@@ -663,6 +676,16 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
         const float4* s4 = reinterpret_cast<const float4*>(src);
         float4* d4 = reinterpret_cast<float4*>(sdata);
         for (int q = tid; q < (cnt >> 1); q += NT) d4[q] = gld(s4 + q);
+      } else if constexpr (KB > 1) {
+        for (int q0 = tid; q0 < cnt; q0 += KB * NT) {
+          V tmp[KB];
+#pragma unroll
+          for (int k = 0; k < KB; ++k)
+            if (q0 + k * NT < cnt) tmp[k] = gld(src + q0 + k * NT);
+#pragma unroll
+          for (int k = 0; k < KB; ++k)
+            if (q0 + k * NT < cnt) sdata[q0 + k * NT] = tmp[k];
+        }
       } else {
         for (int q = tid; q < cnt; q += NT) sdata[q] = gld(src + q);
       }
@@ -680,6 +703,26 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
           cq -= cn;
           ++cl;
         }
+      }
+    } else if constexpr (KB > 1) {
+      int cl = tid / cn, cq = tid % cn;
+      for (int f0 = tid; f0 < cnt; f0 += KB * NT) {
+        V tmp[KB];
+        int at[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          at[k] = cl * pitch + cq + cq / MZ;
+          if (f0 + k * NT < cnt) tmp[k] = gld(src + f0 + k * NT);
+          cq += dq;
+          cl += dl;
+          if (cq >= cn) {
+            cq -= cn;
+            ++cl;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+          if (f0 + k * NT < cnt) sdata[at[k]] = tmp[k];
       }
     } else {
       int cl = tid / cn, cq = tid % cn;
@@ -699,7 +742,7 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
     const bool act = (ll < nl) && (len > 0);
     V* row = sdata + (act ? ll * pitch : 0);
     V v[MZ];
-    z_line_solve<R, MZ, CC>(v, row, act, s, ss, zp, len, nz, nseg, l, p, cf, cP, omega, nwi);
+    z_line_solve<R, MZ, CC>(v, row, act, s, ss, zp, len, nz, nseg, l, p, cf, cP, om, nwi);
 
     if (act) {
       R vxy = 0;

@@ -48,11 +48,19 @@ inline size_t z_lds(int nz, int seg, int mz, int zpad, size_t esize, int nw = 4)
 inline int z_waves(int nz, int seg, int mz, int zpad, size_t esize) {
   return (esize == 16 && mz >= 8 && z_lds(nz, seg, mz, zpad, esize, 4) + 512 > 32768) ? 1 : 4;
 }
+// z blocks that hold the Sherman-Morrison vector in LDS after their line rows (read there by
+// every line's head correction): one-wavefront blocks and complex64 blocks.  Measured,
+// omega from global memory -> LDS: 1280-point complex128 lines 37.9 -> 32.6 ms together
+// with the batched copy-in; complex64 quench z sweep 322 -> 313 us (real time); complex128
+// 4-wavefront blocks ran 654 -> 677 us that way and read it from global memory.
+inline bool z_omega_in_lds(size_t esize, int zw) { return zw == 1 || esize == 8; }
 // Blocks whose packed rows already need more than 64 KiB (complex128 lines beyond 1016
-// points, complex64 beyond 2032) take the padded layout whenever it fits max_lds.
-inline int z_pad(int nz, int seg, int mz, size_t esize, size_t max_lds = 65536) {
+// points, complex64 beyond 2032) take the padded layout whenever it fits max_lds.  extra:
+// further bytes the block holds (the Sherman-Morrison vector).
+inline int z_pad(int nz, int seg, int mz, size_t esize, size_t max_lds = 65536, size_t extra = 0) {
   if (mz % 4 != 0) return 0;
-  const size_t packed = z_lds(nz, seg, mz, 0, esize) + 512, padded = z_lds(nz, seg, mz, 1, esize) + 512;
+  const size_t packed = z_lds(nz, seg, mz, 0, esize) + 512 + extra;
+  const size_t padded = z_lds(nz, seg, mz, 1, esize) + 512 + extra;
   if (padded <= 65536) return 1;
   return (packed > 65536 && padded <= max_lds) ? 1 : 0;
 }
@@ -92,9 +100,6 @@ struct SweepLaunch {
 // precision: 0 complex64, 1 complex128; cc: complex coefficients (real time)
 hipError_t launch_sweep_lines(int precision, bool cc, const SweepLaunch& a, hipStream_t s);
 hipError_t launch_sweep_z(int precision, bool cc, const SweepLaunch& a, hipStream_t s);
-// Resident blocks per CU of the imaginary-time z kernels (the fewer of the two instances,
-// with and without the Strang half step) for this mapping; 0 on failure
-int z_resident_per_cu(int precision, int mz, int zw, size_t lds);
 // Streaming x/y sweep with the back-substitution truncated after a.hlen terms
 hipError_t launch_stream_lines(int precision, bool cc, const SweepLaunch& a, hipStream_t s);
 int stream_h(int h);  // instance size for a required truncation length (-1: none)

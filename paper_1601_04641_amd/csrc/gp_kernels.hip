@@ -100,8 +100,10 @@ k_sweep_z(typename VecOf<R>::T* __restrict__ psi, typename VecOf<R>::T ca, typen
   __shared__ double red[4];
   R g = 0;
   if (EPI != 0) g = (R)st->g;
-  const double acc = z_body<R, MZ, CC, NORM, EPI, NW>(psi, ca, cb, cbl, cP, omega, nwi, nz, nseg, nlines, vx, vy, pz,
-                                                      ny, tau, g, blockIdx.x, gridDim.x, zpad, smem_raw);
+  // Sherman-Morrison vector from LDS or global memory: z_omega_in_lds
+  const double acc = z_body<R, MZ, CC, NORM, EPI, NW, (NW == 1 || sizeof(R) == 4)>(psi, ca, cb, cbl, cP, omega, nwi, nz, nseg, nlines, vx,
+                                                               vy, pz, ny, tau, g, blockIdx.x, gridDim.x, zpad,
+                                                               smem_raw);
   if (NORM) {
     const double t = block_sum_w<NW>(acc, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -400,7 +402,9 @@ template <typename R, int MZ, bool CC, bool NORM, int EPI, int NW>
 static hipError_t go_z_w(const SweepLaunch& a, hipStream_t s) {
   typedef typename VecOf<R>::T V;
   const int zpad = (MZ % 2 == 0) ? a.zpad : 0;
-  const size_t lds = z_lds(a.nz, a.nseg, MZ, zpad, sizeof(V), NW);
+  // the block's line rows, then (z_omega_in_lds) the Sherman-Morrison vector
+  const size_t lds =
+      z_lds(a.nz, a.nseg, MZ, zpad, sizeof(V), NW) + (z_omega_in_lds(sizeof(V), NW) ? (size_t)a.nw * sizeof(V) : 0);
   if (lds > 65536 - 512) {  // more than the default 64 KiB per block: opt in (up to 160 KiB)
     static size_t granted = 0;
     if (lds > granted) {
@@ -477,46 +481,6 @@ hipError_t launch_sweep_z(int precision, bool cc, const SweepLaunch& a, hipStrea
 }
 #undef GP_Z_M
 
-namespace {
-template <typename K> int occ_of(K kern, int threads, size_t lds) {
-  if (lds > 65536 - 512 && hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                (int)lds) != hipSuccess)
-    return 0;
-  int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, lds) != hipSuccess) return 0;
-  return n;
-}
-template <typename R, int MZ, int NW> int z_occ_w(size_t lds) {
-  return std::min(occ_of(k_sweep_z<R, MZ, false, true, 0, NW>, 64 * NW, lds),
-                  occ_of(k_sweep_z<R, MZ, false, true, 1, NW>, 64 * NW, lds));
-}
-template <typename R, int MZ> int z_occ(int zw, size_t lds) {
-  if constexpr (kZOneWave<MZ>)
-    if (zw == 1) return z_occ_w<R, MZ, 1>(lds);
-  return zw == 4 ? z_occ_w<R, MZ, 4>(lds) : 0;
-}
-template <typename R> int z_occ_m(int mz, int zw, size_t lds) {
-  switch (mz) {
-    case 2: return z_occ<R, 2>(zw, lds);
-    case 4: return z_occ<R, 4>(zw, lds);
-    case 6: return z_occ<R, 6>(zw, lds);
-    case 7: return z_occ<R, 7>(zw, lds);
-    case 8: return z_occ<R, 8>(zw, lds);
-    case 12: return z_occ<R, 12>(zw, lds);
-    case 14: return z_occ<R, 14>(zw, lds);
-    case 15: return z_occ<R, 15>(zw, lds);
-    case 16: return z_occ<R, 16>(zw, lds);
-    case 20: return z_occ<R, 20>(zw, lds);
-    case 24: return z_occ<R, 24>(zw, lds);
-    case 32: return z_occ<R, 32>(zw, lds);
-  }
-  return 0;
-}
-}  // namespace
-
-int z_resident_per_cu(int precision, int mz, int zw, size_t lds) {
-  return precision == 0 ? z_occ_m<float>(mz, zw, lds) : z_occ_m<double>(mz, zw, lds);
-}
 
 hipError_t launch_finalize_norm(const double* partials, int nb, double dV, double dt, DevState* st,
                                 hipStream_t s) {
