@@ -652,10 +652,13 @@ __device__ __forceinline__ double z_body(typename VecOf<R>::T* __restrict__ psi,
   const bool pairs = sizeof(V) == 8 && (nz & 1) == 0 && al16;  // with zp = 1 (MZ even)
   const int cn = pairs ? half : nz;
   const int dl = NT / cn, dq = NT % cn;
-  // One-wavefront blocks (long complex128 lines: 15-20 values per thread to copy) issue
-  // their copies KB at a time, all loads before the LDS stores: one copy per iteration
-  // waits out a whole memory latency per value, with few other wavefronts to cover it.
-  constexpr int KB = (NW == 1) ? 8 : 1;
+  // complex128 blocks issue their copies KB at a time, all loads before the LDS stores: one
+  // copy per iteration waits out a whole memory latency per value (the compiler keeps one
+  // load in flight).  Measured: 4-wavefront blocks of 448-point lines (7 copies per
+  // thread) z sweep 650 -> 607 us (real time), 696 -> 593 us (imaginary time); KB = 2, 3
+  // and 4 within 1-4% of that, 8 slower (635 / 624 us).  One-wavefront blocks (long
+  // lines, 15-20 copies per thread) take 8.  complex64 blocks ran 3-25% slower batched.
+  constexpr int KB = (sizeof(R) == 4) ? 1 : (NW == 1 ? 8 : 6);
   // OML: the Sherman-Morrison vector is read from LDS (staged after the line rows once per
   // block) instead of global memory: each lane's read of it depends on its segment, so the
   // global loads were issued one at a time, each waiting out a cache latency, per group.
