@@ -302,8 +302,14 @@ __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, type
   cf.b = cb;
   cf.bl = cbl;
 
+  // e0: this wavefront's first point, (first line of the block, first row of the
+  // wavefront's first segment).  With the early loads (below) a wavefront past the line's
+  // end (batched blocks are sized for the largest instance) takes the line's last row, so
+  // that e0 is always a point of psi.
+  constexpr bool kEarly = M >= 24;
   const int64_t line0 = min(bidx * LW, nlines - 1);
-  const int64_t e0 = (line0 / inner) * (inner * n) + (line0 % inner) + (int64_t)(w * SW * M) * inner;
+  const int row0 = kEarly ? min(w * SW * M, n - 1) : w * SW * M;
+  const int64_t e0 = (line0 / inner) * (inner * n) + (line0 % inner) + (int64_t)row0 * inner;
   const int64_t left_bytes = psi_bytes - e0 * (int64_t)sizeof(V);
   const uint32_t span = (uint32_t)min(left_bytes, (int64_t)0xffffffff);
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(psi + e0, span);
@@ -312,25 +318,53 @@ __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, type
   const uint32_t srow = (uint32_t)(inner * (int64_t)sizeof(V));
   const V* const lp = psi + base + (int64_t)s * inner;  // WIDE: this lane's first point
   V* const lq = dst + base + (int64_t)s * inner;
+  // Two load schemes.  Guarded (M < 24): each row's load sits behind a per-lane branch
+  // (t < len), and the compiler then waits for all rows before the first use.  Early
+  // (M >= 24, the long lines of the paper's grids): loads complete in issue order and each
+  // use waits only for the loads issued before it, so the potential tables go first (every
+  // point's potential step needs them), then the segment's first and last rows (the
+  // neighbour exchange and its barrier need only those), then the rows between, whose
+  // potential steps and forward recurrence run while later rows are still in flight; no
+  // row load sits behind a branch (a branch around them all also made the compiler wait
+  // for all of them): a row past the line's end (t >= len) loads the point e0 instead and
+  // is zeroed before its first use.  Measured (per sweep): 1920x1600x1280 complex128
+  // imaginary x 32.1 -> 28.8 ms, 1600x1280x960 complex64 y 7.41 -> 5.38 ms; on the
+  // 512x480x448 quench (M = 16) the early scheme ran 0-3% slower.
+  R vyz = 0;
+  if (NSTEP != 0 && kEarly) vyz = vy[line / nz] + vz[line % nz];  // x-sweep line index = j*nz + k
   V v[M];
+  if constexpr (kEarly) {
 #pragma unroll
-  for (int t = 0; t < M; ++t) {
-    v[t] = vzero<V>();
-    if (t < len) {
-      if (WIDE) v[t] = gld(lp + (int64_t)t * inner);
-      else bload<kNtLines<R, NSTEP>>(v[t], rs, voff, (uint32_t)t * srow);
+    for (int q = 0; q < M; ++q) {
+      const int t = (q == 0) ? 0 : (q == 1 ? M - 1 : q - 1);
+      if (WIDE) v[t] = gld(t < len ? lp + (int64_t)t * inner : psi + e0);
+      else bload<kNtLines<R, NSTEP>>(v[t], rs, t < len ? voff + (uint32_t)t * srow : 0u, 0u);
     }
-  }
-  if (NSTEP != 0) {
-    const R vyz = vy[line / nz] + vz[line % nz];  // x-sweep line index = j*nz + k
+#pragma unroll
+    for (int q = 0; q < 2 && q < M; ++q) {
+      const int t = (q == 0) ? 0 : M - 1;
+      if (t >= len) v[t] = vzero<V>();
+      if (NSTEP != 0) {
+        v[t] = nstep<NSTEP, R, V>(v[t], scale, px.at(min(s + t, n - 1)) + vyz, g, tau);  // padding stays 0
+        if constexpr (sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  } else {
 #pragma unroll
     for (int t = 0; t < M; ++t) {
-      const int pos = min(s + t, n - 1);
-      v[t] = nstep<NSTEP, R, V>(v[t], scale, px.at(pos) + vyz, g, tau);  // padding stays 0
-      // complex128 with 30+ points per thread: one point's exp or sin/cos at a time, else
-      // the scheduler overlaps many of them and the live temporaries exceed even 256 VGPRs
-      // (spills; complex64 keeps the overlap, which measured 9% faster there)
-      if constexpr (M >= 30 && sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
+      v[t] = vzero<V>();
+      if (t < len) {
+        if (WIDE) v[t] = gld(lp + (int64_t)t * inner);
+        else bload<kNtLines<R, NSTEP>>(v[t], rs, voff, (uint32_t)t * srow);
+      }
+    }
+    if (NSTEP != 0) {
+      vyz = vy[line / nz] + vz[line % nz];
+#pragma unroll
+      for (int t = 0; t < M; ++t) {
+        const int pos = min(s + t, n - 1);
+        v[t] = nstep<NSTEP, R, V>(v[t], scale, px.at(pos) + vyz, g, tau);  // padding stays 0
+      }
     }
   }
 
@@ -339,6 +373,21 @@ __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, type
   sh_first[p * LW + li] = v[0];
   sh_last[p * LW + li] = v[M - 1];
   __syncthreads();
+  if constexpr (kEarly) {
+#pragma unroll
+    for (int t = 1; t < M - 1; ++t)
+      if (t >= len) v[t] = vzero<V>();
+    if (NSTEP != 0) {
+#pragma unroll
+      for (int t = 1; t < M - 1; ++t) {
+        v[t] = nstep<NSTEP, R, V>(v[t], scale, px.at(min(s + t, n - 1)) + vyz, g, tau);
+        // complex128: one point's exp or sin/cos at a time, else the scheduler overlaps
+        // many of them and the live temporaries exceed even 256 VGPRs (spills; complex64
+        // keeps the overlap, which measured 9% faster there)
+        if constexpr (sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
   const V left = (p > 0 && p < nseg) ? sh_last[(p - 1) * LW + li] : vzero<V>();
   const V right = (p < nseg - 1) ? sh_first[(p + 1) * LW + li] : vzero<V>();
 

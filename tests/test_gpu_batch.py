@@ -105,6 +105,33 @@ def test_batch_matches_oracle_per_instance(prec, imag):
         assert np.max(np.abs(raw[i] - want) / np.abs(want)) <= 1e-12
 
 
+@pytest.mark.parametrize("imag", [True, False])
+def test_batch_long_segments_with_idle_wavefronts(imag):
+    """32 points per thread, one segment per wavefront, in complex64 (the line sweeps'
+    early-load scheme): the blocks hold 3 wavefronts for the 96-point lines, so on the
+    smaller instances (17-64 points along x, 33-64 along y) one or two wavefronts of each
+    block lie past the line's end.  Every instance against the oracle."""
+    ws = instances()
+    prec = gp.GP_C64
+    states, offs, total = pack(ws, prec, seed=40)
+    psi = to_dev(states, total, prec)
+    say(f"case: batch of {len(ws)} c64 mapping x (32, 1) y (32, 1) imag {imag}")
+    with gp.Batch(psi, ws, offs) as b:
+        mz = b.get_mapping()[4]
+        b.set_mapping(32, 1, 32, 1, mz)
+        assert b.get_mapping()[:4] == [32, 1, 32, 1]
+        (b.step_imag if imag else b.step_real)(20)
+        torch.cuda.synchronize()
+        outs = unpack(psi, ws, offs)
+    for i, (w, s0, out) in enumerate(zip(ws, states, outs)):
+        o = oracle.Oracle.from_params(w, s0)
+        (o.step_imag if imag else o.step_real)(20)
+        err = float(np.max(np.abs(out - o.psi)) / np.max(np.abs(o.psi)))
+        tol = c64_tolerance(w, s0, o.psi, imag)
+        say(f"  instance {i} {w['nx']}x{w['ny']}x{w['nz']}: rel err {err:.2e} (tol {tol:.1e})")
+        assert err <= tol
+
+
 def test_batch_real_time_bitwise_equals_single_grid_with_same_mapping():
     ws = instances()
     prec = gp.GP_C64
