@@ -66,11 +66,15 @@ k_stream_yz(const typename VecOf<R>::T* __restrict__ src, typename VecOf<R>::T* 
   const int s = lane * MZ, ss = s + zp * lane;
   const int len = max(0, min(MZ, nz - s));
 
+  // rows past the last one the chunk needs (j1 + H) are not read (they were, L rows per
+  // chunk: 6% of the reads of 120-row chunks; quench grid complex128 real time 1391 ->
+  // 1355 us, complex64 576 -> 570 us)
+  const int jend = min(ny, j1 + H + 1);
   V q[L], ring[L];
 #pragma unroll
   for (int t = 0; t < L; ++t) {
     ring[t] = vzero<V>();
-    q[(1 + t) % L] = (js + 1 + t < ny) ? load(js + 1 + t) : vzero<V>();
+    q[(1 + t) % L] = (js + 1 + t < jend) ? load(js + 1 + t) : vzero<V>();
   }
   V pm = vzero<V>(), pc = load(js), dprev = vzero<V>(), u0 = vzero<V>();
   double acc = 0.0;
@@ -88,7 +92,7 @@ k_stream_yz(const typename VecOf<R>::T* __restrict__ src, typename VecOf<R>::T* 
         if (j < ny) {
           const int s1 = (t + 1) % L;
           const V pn = (j + 1 < ny) ? q[s1] : vzero<V>();
-          if (j + 1 + L < ny) q[s1] = load(j + 1 + L);
+          if (j + 1 + L < jend) q[s1] = load(j + 1 + L);
           d = fwd_point<CC, R, V>(cy, pm, pn, dprev, pc);
           pm = pc;
           pc = pn;
@@ -163,8 +167,22 @@ template <typename R, int H, int MZ, bool CC, bool NORM, int EPI>
 hipError_t go_yz(const YZLaunch& a, hipStream_t s) {
   typedef typename VecOf<R>::T V;
   const int zp = (MZ % 4 == 0) ? 1 : 0;
-  const int waves = (a.nz + 63) / 64;
-  const int group = (H + 1) * ((waves + H) / (H + 1));  // L ceil(W / L) row slots
+  constexpr int L = H + 1;
+  // ceil(nz / 64) wavefronts cover the columns; if they do not divide the group of
+  // G = L ceil(W / L) rows that they solve along z one row per wave, the group's last round
+  // of z solves leaves waves idle.  Launch instead the fewest waves W >= ceil(nz / 64) (up
+  // to the instance's bound) that divide their own G (the extra waves only solve rows):
+  // G is unchanged, since W = G itself divides it.  Quench grid, nz = 448 (7 columns of
+  // waves): complex128 real time (H = 7) 8 waves, fused pass 1504 -> 1391 us; complex64
+  // real time (H = 3) 8 waves, 684 -> 576 us; complex64 imaginary time (H = 5) 12 waves,
+  // 446 -> 438 us.
+  int waves = (a.nz + 63) / 64;
+  for (int w2 = waves; w2 <= (sizeof(R) == 8 ? 8 : 16); ++w2)
+    if ((L * ((w2 + L - 1) / L)) % w2 == 0) {
+      waves = w2;
+      break;
+    }
+  const int group = L * ((waves + H) / L);  // L ceil(W / L) row slots
   const size_t lds = (size_t)group * z_pitch(a.nz, MZ, zp) * sizeof(V);
   auto kern = k_stream_yz<R, H, MZ, CC, NORM, EPI, 16>;
   int which = 0;
