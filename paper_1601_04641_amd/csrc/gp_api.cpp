@@ -1221,7 +1221,7 @@ int gp_set_truncation(gp_ctx* c, int32_t mode) {
         return GP_ERR_UNSUPPORTED;
       }
       nwy = std::max(nwy, c->nw[m][1]);
-      const size_t lds = gpk::yz_lds(p.nz, c->hlen[m][1], c->esize);
+      const size_t lds = gpk::yz_lds(p.nz, c->hlen[m][1], c->esize, c->nw[m][2]);
       if (lds > gpk::kMaxLdsBlock) {  // the rows of one group of z lines must fit one block's LDS
         snprintf(c->err, sizeof(c->err), "the fused y+z pass would need %zu bytes of LDS per block (at most %zu)",
                  lds, gpk::kMaxLdsBlock);

@@ -130,7 +130,7 @@ int yz_h(int h);    // instance size for a y truncation length (-1: none)
 int yz_mz(int nz);  // z points per lane of the fused kernel (-1: nz > 1024)
 // LDS bytes of one fused block (the rows of one group of z lines) for a y truncation
 // length h; 0 when no instance covers (nz, h)
-size_t yz_lds(int nz, int h, size_t esize);
+size_t yz_lds(int nz, int h, size_t esize, int znw);
 
 hipError_t launch_finalize_norm(const double* partials, int nb, double dV, double dt, DevState* st,
                                 hipStream_t s);

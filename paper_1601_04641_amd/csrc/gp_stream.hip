@@ -82,6 +82,12 @@ k_stream_yz(const typename VecOf<R>::T* __restrict__ src, typename VecOf<R>::T* 
   // rows are solved along z in groups of G = L ceil(W / L) steps, so that every wave has a
   // row to solve; LDS slot of step jj: jj - gstart
   const int G = L * ((W + L - 1) / L);
+  // the z Sherman-Morrison vector, staged after the group's rows: read from global memory,
+  // each lane's value depends on its segment and the loads of a z solve waited out a cache
+  // latency in every group (quench grid, fused pass: complex128 imaginary time 858 -> 829
+  // us, complex64 real 570 -> 540 us, imaginary 439 -> 418 us; complex128 real unchanged)
+  V* s_om = sdata + (size_t)G * pitch;
+  for (int q2 = threadIdx.x; q2 < znw; q2 += blockDim.x) s_om[q2] = zomega[q2];  // seen after the first barrier
   int gstart = 0;
   for (int jb = 0; jb < total; jb += L) {
 #pragma unroll
@@ -119,7 +125,7 @@ k_stream_yz(const typename VecOf<R>::T* __restrict__ src, typename VecOf<R>::T* 
       if (r >= j0) {
         V* row = sdata + slot * pitch;
         V v[MZ];
-        z_line_solve<R, MZ, CC>(v, row, len > 0, s, ss, zp, len, nz, 64, 0, lane, cz, zP, zomega, znw);
+        z_line_solve<R, MZ, CC>(v, row, len > 0, s, ss, zp, len, nz, 64, 0, lane, cz, zP, s_om, znw);
         if (len > 0) {
           R vxy = 0;
           if (EPI != 0) vxy = vx[i] + vy[r];
@@ -183,7 +189,7 @@ hipError_t go_yz(const YZLaunch& a, hipStream_t s) {
       break;
     }
   const int group = L * ((waves + H) / L);  // L ceil(W / L) row slots
-  const size_t lds = (size_t)group * z_pitch(a.nz, MZ, zp) * sizeof(V);
+  const size_t lds = ((size_t)group * z_pitch(a.nz, MZ, zp) + a.znw) * sizeof(V);
   auto kern = k_stream_yz<R, H, MZ, CC, NORM, EPI, 16>;
   int which = 0;
   if constexpr (sizeof(R) == 8)
@@ -246,13 +252,13 @@ int yz_h(int h) {
   return -1;
 }
 
-size_t yz_lds(int nz, int h, size_t esize) {
+size_t yz_lds(int nz, int h, size_t esize, int znw) {
   const int H = yz_h(h), mz = yz_mz(nz);
   if (H < 0 || mz < 0) return 0;
   const int waves = (nz + 63) / 64;
   const int group = (H + 1) * ((waves + H) / (H + 1));
   const int zp = (mz % 4 == 0) ? 1 : 0;
-  return (size_t)group * z_pitch(nz, mz, zp) * esize;
+  return ((size_t)group * z_pitch(nz, mz, zp) + znw) * esize;
 }
 
 int yz_mz(int nz) {
