@@ -64,7 +64,7 @@ template <typename R> __device__ __forceinline__ typename VecOf<R>::T dval(const
   return v;
 }
 
-template <typename R, int M, int SW, bool CC, int NSTEP>
+template <typename R, int M, int SW, bool CC, int NSTEP, bool LONGHC>
 __global__ void __launch_bounds__(1024)
 kb_sweep_lines(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst,
                const BWork* __restrict__ work, int axis, const R* __restrict__ vtab,
@@ -85,8 +85,9 @@ kb_sweep_lines(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restri
     tau = (R)(I.split ? 0.5 * I.dt : I.dt);
   }
   const int nw = I.nw[mode][axis];
-  lines_body<R, M, SW, CC, NSTEP>(psi_all + I.off, psi_all + I.off, I.bytes, dval<R>(cf), dval<R>(cf + 2), dval<R>(cf + 4),
-                                  dval<R>(cf + 6), omega_all + I.omega_off[mode][axis], nw <= M ? nw : 0, n,
+  lines_body<R, M, SW, CC, NSTEP, false, LONGHC>(psi_all + I.off, psi_all + I.off, I.bytes, dval<R>(cf), dval<R>(cf + 2),
+                                  dval<R>(cf + 4), dval<R>(cf + 6), omega_all + I.omega_off[mode][axis],
+                                  (LONGHC || nw <= M) ? nw : 0, n,
                                   I.nseg[axis], nlines, inner, Pot1D<R>{(R)I.ph[0], (R)I.pc[0], (R)I.pd[0]},
                                   vtab + I.v_off[1], vtab + I.v_off[2], I.nz, tau, scale, g, wk.blk, smem_raw);
 }
@@ -333,32 +334,6 @@ kb_sweep_yz(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict_
   }
 }
 
-// Sherman-Morrison head correction of x or y lines for instances whose correction is
-// longer than a segment (m points): one thread per line, lw lines per block (the line
-// blocks of the sweep's work table).
-template <typename R, bool CC>
-__global__ void __launch_bounds__(64)
-kb_head_correction(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restrict__ inst,
-                   const BWork* __restrict__ work, int axis, int lw, int m,
-                   const typename VecOf<R>::T* __restrict__ omega_all) {
-  typedef typename VecOf<R>::T V;
-  const BWork wk = work[blockIdx.x];
-  const BInst& I = inst[wk.inst];
-  constexpr int mode = CC ? 1 : 0;
-  const int nw = I.nw[mode][axis];
-  if (!I.active || nw <= m || (int)threadIdx.x >= lw) return;
-  const int n = axis == 0 ? I.nx : I.ny;
-  const int64_t nlines = axis == 0 ? (int64_t)I.ny * I.nz : (int64_t)I.nx * I.nz;
-  const int64_t inner = axis == 0 ? (int64_t)I.ny * I.nz : (int64_t)I.nz;
-  const int64_t line = (int64_t)wk.blk * lw + threadIdx.x;
-  if (line >= nlines) return;
-  V* psi = psi_all + I.off;
-  const V* omega = omega_all + I.omega_off[mode][axis];
-  const int64_t base = (line / inner) * (inner * n) + (line % inner);
-  const V u0 = psi[base];
-  for (int i = nw - 1; i >= 0; --i) psi[base + i * inner] = cfma<CC>(omega[i], u0, psi[base + i * inner]);
-}
-
 __global__ void __launch_bounds__(256)
 kb_finalize_norm(const double* __restrict__ partials, const BInst* __restrict__ inst, DevState* st) {
   __shared__ double red[4];
@@ -543,14 +518,19 @@ struct BLaunch {
   const DevState* st;
   double* partials;
   int m, sw;
-  int nstep;  // 0 none, 1 imaginary, 2 real
+  int nstep;    // 0 none, 1 imaginary, 2 real
+  bool longhc;  // some instance's head correction is longer than a segment (x/y sweeps)
 };
 
 template <typename R, int M, int SW, bool CC, int NSTEP>
 static hipError_t gob_lines(const BLaunch& a, hipStream_t s) {
   typedef typename VecOf<R>::T V;
-  hipLaunchKernelGGL((kb_sweep_lines<R, M, SW, CC, NSTEP>), dim3(a.nblocks), dim3(a.threads), a.lds, s, (V*)a.psi,
-                     a.inst, a.work, a.axis, (const R*)a.vtab, (const V*)a.omega, a.st);
+  if (a.longhc)
+    hipLaunchKernelGGL((kb_sweep_lines<R, M, SW, CC, NSTEP, true>), dim3(a.nblocks), dim3(a.threads), a.lds, s,
+                       (V*)a.psi, a.inst, a.work, a.axis, (const R*)a.vtab, (const V*)a.omega, a.st);
+  else
+    hipLaunchKernelGGL((kb_sweep_lines<R, M, SW, CC, NSTEP, false>), dim3(a.nblocks), dim3(a.threads), a.lds, s,
+                       (V*)a.psi, a.inst, a.work, a.axis, (const R*)a.vtab, (const V*)a.omega, a.st);
   return hipGetLastError();
 }
 template <typename R, int M, int SW>
@@ -813,7 +793,7 @@ int configure(gp_batch* b) {
       for (int a = 0; a < 3; ++a) {
         gpk::AxisConst ac;
         gpk::cn_axis_constants(n[a], d[a], p.dt, mode, m[a], f32, &ac);
-        if (a < 2 && ac.nw > m[a]) need_hc[mode][a] = true;  // separate correction pass
+        if (a < 2 && ac.nw > m[a]) need_hc[mode][a] = true;  // LONGHC sweep instances
         for (int q = 0; q < 8; ++q) I.coef[mode][a][q] = ac.coef[q];
         I.nw[mode][a] = ac.nw;
         I.omega_off[mode][a] = (int)(omega.size() / b->esize);
@@ -982,41 +962,18 @@ int benqueue_step(gp_batch* b, int mode, hipStream_t s) {
   const bool cc = mode == 1;
   const int strang = b->p[0].split == GP_SPLIT_STRANG;
   gpk::BLaunch ax{b->psi, b->dinst, b->wx, b->nbx, b->thrx, b->ldsx, 0, b->vtab, b->omega, b->st, nullptr,
-                  b->map[0], b->map[1], mode == 0 ? 1 : 2};
+                  b->map[0], b->map[1], mode == 0 ? 1 : 2, b->need_hc[mode][0]};
   gpk::BLaunch ay{b->psi, b->dinst, b->wy, b->nby, b->thry, b->ldsy, 1, b->vtab, b->omega, b->st, nullptr,
-                  b->map[2], b->map[3], 0};
+                  b->map[2], b->map[3], 0, b->need_hc[mode][1]};
   gpk::BLaunch az{b->psi, b->dinst, b->wz, b->nbz, 256, b->ldsz, 2, b->vtab, b->omega, b->st, b->zpart,
-                  b->map[4], 0, strang ? (mode == 0 ? 1 : 2) : 0};
-  auto head = [&](const gpk::BLaunch& l, hipStream_t t) {
-    const int lw = 64 / l.sw;
-    if (b->prec == GP_C64) {
-      if (cc)
-        hipLaunchKernelGGL((gpk::kb_head_correction<float, true>), dim3(l.nblocks), dim3(64), 0, t, (float2*)b->psi,
-                           b->dinst, l.work, l.axis, lw, l.m, (const float2*)b->omega);
-      else
-        hipLaunchKernelGGL((gpk::kb_head_correction<float, false>), dim3(l.nblocks), dim3(64), 0, t,
-                           (float2*)b->psi, b->dinst, l.work, l.axis, lw, l.m, (const float2*)b->omega);
-    } else {
-      if (cc)
-        hipLaunchKernelGGL((gpk::kb_head_correction<double, true>), dim3(l.nblocks), dim3(64), 0, t,
-                           (double2*)b->psi, b->dinst, l.work, l.axis, lw, l.m, (const double2*)b->omega);
-      else
-        hipLaunchKernelGGL((gpk::kb_head_correction<double, false>), dim3(l.nblocks), dim3(64), 0, t,
-                           (double2*)b->psi, b->dinst, l.work, l.axis, lw, l.m, (const double2*)b->omega);
-    }
-    return hipGetLastError();
-  };
+                  b->map[4], 0, strang ? (mode == 0 ? 1 : 2) : 0, false};
   int rc = btimed(b, s, 0, [&](hipStream_t t) {
-    hipError_t e = gpk::launch_b_lines(b->prec, cc, ax, t);
-    if (e == hipSuccess && b->need_hc[mode][0]) e = head(ax, t);
-    return e;
+    return gpk::launch_b_lines(b->prec, cc, ax, t);
   });
   if (rc) return rc;
   if (b->nby > 0) {
     rc = btimed(b, s, 1, [&](hipStream_t t) {
-      hipError_t e = gpk::launch_b_lines(b->prec, cc, ay, t);
-      if (e == hipSuccess && b->need_hc[mode][1]) e = head(ay, t);
-      return e;
+      return gpk::launch_b_lines(b->prec, cc, ay, t);
     });
     if (rc) return rc;
   }

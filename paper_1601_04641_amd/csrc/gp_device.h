@@ -272,7 +272,7 @@ template <typename R> struct Pot1D {
 // writes dst (the same array for the in-place sweeps; another one for the x sweep ahead of
 // the fused y+z pass, which must not read values another block has already replaced).
 // ---------------------------------------------------------------------------------------
-template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE = false>
+template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE = false, bool LONGHC = false>
 __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, typename VecOf<R>::T* dst,
                                            int64_t psi_bytes,
                                            typename VecOf<R>::T ca, typename VecOf<R>::T cb,
@@ -441,15 +441,33 @@ __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, type
     }
   }
   // Sherman-Morrison head correction of segment 0
-  if (w == 0 && nwi > 0) {
-    const bool mine = (SW == 1) || (lane < LW);
-    const V u0 = v[0];
+  if (!LONGHC || nwi <= M) {
+    if (w == 0 && nwi > 0) {
+      const bool mine = (SW == 1) || (lane < LW);
+      const V u0 = v[0];
 #pragma unroll
-    for (int t = 0; t < M; ++t) {
-      if (t < nwi) {
-        const V c = cfma<CC>(omega[t], u0, v[t]);
-        if (mine) v[t] = c;
+      for (int t = 0; t < M; ++t) {
+        if (t < nwi) {
+          const V c = cfma<CC>(omega[t], u0, v[t]);
+          if (mine) v[t] = c;
+        }
       }
+    }
+  } else {
+    // LONGHC instances, correction longer than a segment (large c, e.g. imaginary time on
+    // coarse grids): u_0 reaches the other segments through LDS (sh_B is free: its last
+    // reads precede the barrier above).  A separate pass over the first nw points of every
+    // line, as the single-grid sweeps take, cost the batched ground-state runs about a
+    // fifth of their time in extra launches.  (Instances without it keep the registers of
+    // this path free: the omega loads of a general path raised the complex128 sweeps by
+    // 18-36 VGPRs.)
+    if (p == 0) sh_B[li] = v[0];
+    __syncthreads();
+    const V u0 = sh_B[li];
+    if (s < nwi) {
+#pragma unroll
+      for (int t = 0; t < M; ++t)
+        if (s + t < nwi) v[t] = cfma<CC>(omega[s + t], u0, v[t]);
     }
   }
 
