@@ -155,6 +155,50 @@ def test_batch_real_time_bitwise_equals_single_grid_with_same_mapping():
         assert np.array_equal(single.cpu().numpy().astype(np.complex128), out)
 
 
+def long_correction_instances():
+    """Two instances with dt/dx^2 ~ 2-10 (c'_inf close to 1: Sherman-Morrison corrections
+    of tens of points, longer than a segment of 8) and one with a small dt (correction
+    inside segment 0), so one launch runs both branches of the in-kernel correction."""
+    big = dict(dx=0.1, dy=0.15, dz=0.05, nux=1.0, nuy=1.2, nuz=0.8, g=5.0, dt=0.1)
+    return [dict(big, nx=70, ny=45, nz=33), dict(big, nx=40, ny=66, nz=24, g=40.0),
+            dict(nx=48, ny=40, nz=36, dx=0.2, dy=0.22, dz=0.18, nux=1.3, nuy=0.9, nuz=2.0, g=20.0, dt=0.0001)]
+
+
+@pytest.mark.parametrize("prec", [gp.GP_C128, gp.GP_C64])
+@pytest.mark.parametrize("imag", [True, False])
+def test_batch_long_head_correction_matches_oracle(prec, imag):
+    """Batched x/y sweeps with 8 points per thread apply corrections longer than a segment
+    in-kernel (u_0 passed through LDS): every instance against the oracle, and in real time
+    bitwise against single-grid contexts with the same mapping (whose separate correction
+    pass performs the same operations)."""
+    ws = long_correction_instances()
+    states, offs, total = pack(ws, prec, seed=60)
+    psi = to_dev(states, total, prec)
+    say(f"case: batch long head correction prec {prec} imag {imag}")
+    with gp.Batch(psi, ws, offs) as b:
+        mz = b.get_mapping()[4]
+        b.set_mapping(8, 1, 8, 1, mz)
+        (b.step_imag if imag else b.step_real)(2)
+        torch.cuda.synchronize()
+        outs = unpack(psi, ws, offs)
+    for i, (w, s0, out) in enumerate(zip(ws, states, outs)):
+        o = oracle.Oracle.from_params(w, s0)
+        (o.step_imag if imag else o.step_real)(2)
+        err = float(np.max(np.abs(out - o.psi)) / np.max(np.abs(o.psi)))
+        say(f"  instance {i} {w['nx']}x{w['ny']}x{w['nz']} dt {w['dt']}: rel err {err:.2e}")
+        assert err <= (1e-12 if prec == gp.GP_C128 else 5e-6)
+        if not imag:
+            seg = 2
+            while seg < 64 and seg * mz < w["nz"]:
+                seg *= 2
+            single = to_dev([s0], s0.size, prec).reshape(w["nx"], w["ny"], w["nz"])
+            with gp.Solver.from_workload(single, w) as s:
+                s.set_mapping(8, 1, 8, 1, seg, mz)
+                s.step_real(2)
+                torch.cuda.synchronize()
+            assert np.array_equal(single.cpu().numpy().astype(np.complex128), out)
+
+
 def test_batch_masking_leaves_inactive_instances_untouched():
     ws = instances()
     prec = gp.GP_C64
