@@ -167,8 +167,8 @@ typedef unsigned int u32x4 __attribute__((__vector_size__(16)));
 // Cache policy of psi's loads and stores: non-temporal (cache-policy value 2), since psi
 // streams through once per sweep and nothing re-reads it from the caches.  Measured on the
 // 512x480x448 quench: y and z sweeps 1-7% faster (complex128 y 666 -> 626 us, z 723 ->
-// 671 us; complex64 z 348 -> 324 us); the complex64 x sweep 4% slower (346 -> 360 us),
-// so the x sweeps' buffer accesses take NT as a template choice (kNtLines).
+// 671 us; complex64 z 348 -> 324 us); the x sweeps' loads keep the default policy
+// (kLdLines, kStLines below).
 #ifndef GP_NT
 #define GP_NT 2
 #endif
@@ -188,9 +188,16 @@ template <int AUX = GP_NT>
 __device__ __forceinline__ void bstore(const double2& v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)vo, (int)so, AUX);
 }
-// cache policy of a line sweep's accesses: the complex64 sweep with the potential step
-// (the x sweep) keeps the default policy
-template <typename R, int NSTEP> constexpr int kNtLines = (sizeof(R) == 4 && NSTEP != 0) ? 0 : GP_NT;
+// Cache policy of a line sweep's loads and stores.  The sweep with the potential step (the
+// x sweep) loads with the default policy and stores non-temporally; the y sweep does both
+// non-temporally.  Measured on the 512x480x448 quench (x sweep, loads / stores):
+// complex128 NT / NT 702 us, default / NT 673-675 us, default / default 680 us, NT /
+// default 677 us (y sweep after it 642 instead of 626 us); complex64 default / default
+// 333 us, default / NT 329 us (y 316 instead of 318 us), NT / default 324 us (y 328 us),
+// NT / NT 365 us.  Non-temporal loads in the y sweep stay (default loads: 645 instead of
+// 626 us in complex128, 328 instead of 318 us in complex64).
+template <typename R, int NSTEP> constexpr int kLdLines = NSTEP != 0 ? 0 : GP_NT;
+template <typename R, int NSTEP> constexpr int kStLines = GP_NT;
 // plain global loads and stores of psi values (8 or 16 bytes) under the same policy
 template <typename T> __device__ __forceinline__ T gld(const T* p) {
   static_assert(sizeof(T) == 8 || sizeof(T) == 16, "8- or 16-byte values");
@@ -338,7 +345,7 @@ __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, type
     for (int q = 0; q < M; ++q) {
       const int t = (q == 0) ? 0 : (q == 1 ? M - 1 : q - 1);
       if (WIDE) v[t] = gld(t < len ? lp + (int64_t)t * inner : psi + e0);
-      else bload<kNtLines<R, NSTEP>>(v[t], rs, t < len ? voff + (uint32_t)t * srow : 0u, 0u);
+      else bload<kLdLines<R, NSTEP>>(v[t], rs, t < len ? voff + (uint32_t)t * srow : 0u, 0u);
     }
 #pragma unroll
     for (int q = 0; q < 2 && q < M; ++q) {
@@ -355,7 +362,7 @@ __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, type
       v[t] = vzero<V>();
       if (t < len) {
         if (WIDE) v[t] = gld(lp + (int64_t)t * inner);
-        else bload<kNtLines<R, NSTEP>>(v[t], rs, voff, (uint32_t)t * srow);
+        else bload<kLdLines<R, NSTEP>>(v[t], rs, voff, (uint32_t)t * srow);
       }
     }
     if (NSTEP != 0) {
@@ -475,7 +482,7 @@ __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, type
   for (int t = 0; t < M; ++t)
     if (t < len) {
       if (WIDE) gst(lq + (int64_t)t * inner, v[t]);
-      else bstore<kNtLines<R, NSTEP>>(v[t], rd, voff, (uint32_t)t * srow);
+      else bstore<kStLines<R, NSTEP>>(v[t], rd, voff, (uint32_t)t * srow);
     }
 }
 
