@@ -85,7 +85,7 @@ kb_sweep_lines(typename VecOf<R>::T* __restrict__ psi_all, const BInst* __restri
     tau = (R)(I.split ? 0.5 * I.dt : I.dt);
   }
   const int nw = I.nw[mode][axis];
-  lines_body<R, M, SW, CC, NSTEP, false, LONGHC>(psi_all + I.off, psi_all + I.off, I.bytes, dval<R>(cf), dval<R>(cf + 2),
+  lines_body<R, M, SW, CC, NSTEP, false, LONGHC, kBatchLines<R, NSTEP>, kBatchLines<R, NSTEP>>(psi_all + I.off, psi_all + I.off, I.bytes, dval<R>(cf), dval<R>(cf + 2),
                                   dval<R>(cf + 4), dval<R>(cf + 6), omega_all + I.omega_off[mode][axis],
                                   (LONGHC || nw <= M) ? nw : 0, n,
                                   I.nseg[axis], nlines, inner, Pot1D<R>{(R)I.ph[0], (R)I.pc[0], (R)I.pd[0]},

@@ -198,6 +198,11 @@ __device__ __forceinline__ void bstore(const double2& v, __amdgpu_buffer_rsrc_t 
 // 626 us in complex128, 328 instead of 318 us in complex64).
 template <typename R, int NSTEP> constexpr int kLdLines = NSTEP != 0 ? 0 : GP_NT;
 template <typename R, int NSTEP> constexpr int kStLines = GP_NT;
+// The batched sweeps (many small instances per launch) keep non-temporal loads and stores,
+// except the complex64 x sweep, which keeps the default policy for both: with the single
+// grid's x-sweep policy the batched complex128 x sweep of the ground-state runs took 277.5
+// instead of 262.1 us.
+template <typename R, int NSTEP> constexpr int kBatchLines = (sizeof(R) == 4 && NSTEP != 0) ? 0 : GP_NT;
 // plain global loads and stores of psi values (8 or 16 bytes) under the same policy
 template <typename T> __device__ __forceinline__ T gld(const T* p) {
   static_assert(sizeof(T) == 8 || sizeof(T) == 16, "8- or 16-byte values");
@@ -279,7 +284,8 @@ template <typename R> struct Pot1D {
 // writes dst (the same array for the in-place sweeps; another one for the x sweep ahead of
 // the fused y+z pass, which must not read values another block has already replaced).
 // ---------------------------------------------------------------------------------------
-template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE = false, bool LONGHC = false>
+template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE = false, bool LONGHC = false,
+          int LDP = kLdLines<R, NSTEP>, int STP = kStLines<R, NSTEP>>
 __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, typename VecOf<R>::T* dst,
                                            int64_t psi_bytes,
                                            typename VecOf<R>::T ca, typename VecOf<R>::T cb,
@@ -345,7 +351,7 @@ __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, type
     for (int q = 0; q < M; ++q) {
       const int t = (q == 0) ? 0 : (q == 1 ? M - 1 : q - 1);
       if (WIDE) v[t] = gld(t < len ? lp + (int64_t)t * inner : psi + e0);
-      else bload<kLdLines<R, NSTEP>>(v[t], rs, t < len ? voff + (uint32_t)t * srow : 0u, 0u);
+      else bload<LDP>(v[t], rs, t < len ? voff + (uint32_t)t * srow : 0u, 0u);
     }
 #pragma unroll
     for (int q = 0; q < 2 && q < M; ++q) {
@@ -362,7 +368,7 @@ __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, type
       v[t] = vzero<V>();
       if (t < len) {
         if (WIDE) v[t] = gld(lp + (int64_t)t * inner);
-        else bload<kLdLines<R, NSTEP>>(v[t], rs, voff, (uint32_t)t * srow);
+        else bload<LDP>(v[t], rs, voff, (uint32_t)t * srow);
       }
     }
     if (NSTEP != 0) {
@@ -482,7 +488,7 @@ __device__ __forceinline__ void lines_body(const typename VecOf<R>::T* psi, type
   for (int t = 0; t < M; ++t)
     if (t < len) {
       if (WIDE) gst(lq + (int64_t)t * inner, v[t]);
-      else bstore<kStLines<R, NSTEP>>(v[t], rd, voff, (uint32_t)t * srow);
+      else bstore<STP>(v[t], rd, voff, (uint32_t)t * srow);
     }
 }
 
