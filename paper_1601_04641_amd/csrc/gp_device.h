@@ -195,7 +195,8 @@ __device__ __forceinline__ void bstore(const double2& v, __amdgpu_buffer_rsrc_t 
 // default 677 us (y sweep after it 642 instead of 626 us); complex64 default / default
 // 333 us, default / NT 329 us (y 316 instead of 318 us), NT / default 324 us (y 328 us),
 // NT / NT 365 us.  Non-temporal loads in the y sweep stay (default loads: 645 instead of
-// 626 us in complex128, 328 instead of 318 us in complex64).
+// 626 us in complex128, 328 instead of 318 us in complex64).  The 64-bit-addressed (WIDE)
+// instances access psi through gld / gst below, non-temporally in both directions.
 template <typename R, int NSTEP> constexpr int kLdLines = NSTEP != 0 ? 0 : GP_NT;
 template <typename R, int NSTEP> constexpr int kStLines = GP_NT;
 // The batched sweeps (many small instances per launch) keep non-temporal loads and stores,
