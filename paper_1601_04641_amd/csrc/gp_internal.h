@@ -43,10 +43,11 @@ inline size_t z_lds(int nz, int seg, int mz, int zpad, size_t esize, int nw = 4)
 // 4-wavefront blocks, and a block's phases (copy in, solve, copy out) stop overlapping
 // with other blocks' memory traffic; one-wavefront blocks keep about the same lines per
 // CU in flight in independent units.  Measured (1000 steps): 1280-point lines 48.2 ->
-// 37.8 ms (imaginary time), 960-point lines 18.3 -> 15.4 ms (real time), the quench
-// grid's 448-point lines with 14 points per lane 619 -> 572 us.  complex64 ran slower that
-// way (1280-point lines 14.2 -> 20.3 ms, the quench grid 317 -> 324 us) and keeps 4
-// wavefronts.
+// 37.8 ms (imaginary time), 960-point lines 18.3 -> 15.4 ms (real time); the quench
+// grid's 448-point lines take 572 us as 32 segments of 14 points in one-wavefront blocks
+// against 619 us as 64 of 7 in 4-wavefront blocks (under 32 KiB).  complex64 ran slower in
+// one-wavefront blocks (1280-point lines 14.2 -> 20.3 ms, the quench grid 317 -> 324 us)
+// and keeps 4 wavefronts.
 inline int z_waves(int nz, int seg, int mz, int zpad, size_t esize) {
   return (esize == 16 && mz >= 8 && z_lds(nz, seg, mz, zpad, esize, 4) + 512 > 32768) ? 1 : 4;
 }
