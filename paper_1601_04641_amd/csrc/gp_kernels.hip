@@ -47,7 +47,9 @@ namespace gpk {
 // potential step's phase factor), and spilling there cost 30% extra HBM traffic (scratch
 // reads and writes), so blocks of at most 8 wavefronts run an instance bounded at 512
 // (256 VGPRs).  The same holds for 30 and 32 points per thread in either precision.
-template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE, int MAXW>
+// LONGHC: the Sherman-Morrison correction reaches past the first segment and is applied
+// in the kernel (u_0 through LDS) instead of by a separate pass (k_head_correction).
+template <typename R, int M, int SW, bool CC, int NSTEP, bool WIDE, int MAXW, bool LONGHC = false>
 __global__ void __launch_bounds__(64 * MAXW)
 k_sweep_lines(const typename VecOf<R>::T* psi, typename VecOf<R>::T* dst, int64_t psi_bytes, typename VecOf<R>::T ca,
               typename VecOf<R>::T cb, typename VecOf<R>::T cbl, typename VecOf<R>::T cP,
@@ -61,8 +63,8 @@ k_sweep_lines(const typename VecOf<R>::T* psi, typename VecOf<R>::T* dst, int64_
     g = (R)st->g;
   }
   const int64_t b = GP_XCD_REMAP ? xcd_bundle(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-  lines_body<R, M, SW, CC, NSTEP, WIDE>(psi, dst, psi_bytes, ca, cb, cbl, cP, omega, nwi, n, nseg, nlines, inner, px, vy,
-                                        vz, nz, tau, scale, g, b, smem_raw);
+  lines_body<R, M, SW, CC, NSTEP, WIDE, LONGHC>(psi, dst, psi_bytes, ca, cb, cbl, cP, omega, nwi, n, nseg, nlines, inner,
+                                                px, vy, vz, nz, tau, scale, g, b, smem_raw);
 }
 
 // Streaming x or y sweep with the truncated back-substitution (stream_line): thread =
@@ -260,10 +262,24 @@ static hipError_t go_lines(const SweepLaunch& a, hipStream_t s) {
   const int waves = (a.nseg + SW - 1) / SW;
   const size_t lds = (size_t)3 * waves * SW * LW * sizeof(V);
   const int64_t blocks = (a.nlines + LW - 1) / LW;
-  const int nwi = (a.nw <= M) ? a.nw : 0;
+  // corrections longer than a segment: in the kernel for 8 and 16 points per thread (the
+  // mappings of the small and coarse grids where a large c occurs), else a separate pass.
+  // Measured, 512 complex128 64^3 imaginary-time problems one after another (8 points per
+  // thread along x, 16 along y): 12.7 -> 10.1 s, the same step counts and mu.
+  constexpr bool kLong = !WIDE && (M == 8 || M == 16);
+  const bool lng = kLong && a.nw > M;
+  const int nwi = (a.nw <= M || lng) ? a.nw : 0;
+  constexpr bool kMax8 = (sizeof(R) == 8 && M == 16 && NSTEP != 0) || M >= 30;
   auto kern = k_sweep_lines<R, M, SW, CC, NSTEP, WIDE, 16>;
-  if constexpr ((sizeof(R) == 8 && M == 16 && NSTEP != 0) || M >= 30)
+  if constexpr (kMax8)
     if (waves <= 8) kern = k_sweep_lines<R, M, SW, CC, NSTEP, WIDE, 8>;
+  if constexpr (kLong) {
+    if (lng) {
+      kern = k_sweep_lines<R, M, SW, CC, NSTEP, WIDE, 16, true>;
+      if constexpr (kMax8)
+        if (waves <= 8) kern = k_sweep_lines<R, M, SW, CC, NSTEP, WIDE, 8, true>;
+    }
+  }
   V* dst = (V*)(a.dst ? a.dst : a.psi);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(waves * 64), lds, s,
                      (const V*)a.psi, dst, a.psi_bytes, cval<R>(a.coef), cval<R>(a.coef + 2), cval<R>(a.coef + 4),

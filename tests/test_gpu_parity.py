@@ -140,7 +140,8 @@ def test_ragged_shapes_match_oracle(shape, prec, imag, split):
 @pytest.mark.parametrize("imag", [True, False])
 def test_large_dt_long_head_correction(prec, imag):
     """dt/dx^2 ~ 5-40: c'_inf close to 1, so the constant-pivot solve needs Sherman-Morrison
-    corrections longer than one thread's segment (separate x/y correction pass)."""
+    corrections longer than one thread's segment (applied inside the x/y sweeps with 8 or
+    16 points per thread, the default mappings here)."""
     nx, ny, nz = 70, 45, 33
     prm = dict(nx=nx, ny=ny, nz=nz, dx=0.1, dy=0.15, dz=0.05, nux=1.0, nuy=1.2, nuz=0.8, g=5.0, dt=0.1)
     psi0 = inputs.perturbed_psi(nx, ny, nz, 0.1, 0.15, 0.05, 1.0, 1.2, 0.8, seed=12, amp=0.2)
@@ -150,6 +151,21 @@ def test_large_dt_long_head_correction(prec, imag):
     err = rel_err(out, ref)
     say(f"  rel err {err:.2e}")
     assert err <= (1e-12 if prec == gp.GP_C128 else 5e-6)
+
+
+@pytest.mark.parametrize("imag", [True, False])
+def test_large_dt_head_correction_separate_pass(imag):
+    """The same large-dt problem in complex64 with 12 and 10 points per thread along x and y:
+    instances without the in-kernel long correction, so the separate correction pass runs."""
+    nx, ny, nz = 70, 45, 33
+    prm = dict(nx=nx, ny=ny, nz=nz, dx=0.1, dy=0.15, dz=0.05, nux=1.0, nuy=1.2, nuz=0.8, g=5.0, dt=0.1)
+    psi0 = inputs.perturbed_psi(nx, ny, nz, 0.1, 0.15, 0.05, 1.0, 1.2, 0.8, seed=12, amp=0.2)
+    say(f"case: large dt, separate correction pass, c64 mapping (12, 4 | 10, 2) imag {imag}")
+    out, _ = run_gpu(prm, psi0, gp.GP_C64, imag, 2, mapping=(12, 4, 10, 2, 0, 0))
+    ref = run_ref(prm, psi0, imag, 2).psi
+    err = rel_err(out, ref)
+    say(f"  rel err {err:.2e}")
+    assert err <= 5e-6
 
 
 MAPPINGS = [(8, 1, 8, 1, 4, 0), (16, 1, 16, 2, 8, 0), (32, 2, 8, 4, 16, 0), (0, 4, 0, 1, 32, 0),
