@@ -262,12 +262,14 @@ static hipError_t go_lines(const SweepLaunch& a, hipStream_t s) {
   const int waves = (a.nseg + SW - 1) / SW;
   const size_t lds = (size_t)3 * waves * SW * LW * sizeof(V);
   const int64_t blocks = (a.nlines + LW - 1) / LW;
-  // corrections longer than a segment: in the kernel for 8 and 16 points per thread (the
-  // mappings of the small and coarse grids where a large c occurs), else a separate pass.
-  // Measured, 512 complex128 64^3 imaginary-time problems one after another (8 points per
-  // thread along x, 16 along y): 12.7 -> 10.1 s, the same step counts and mu.
+  // Corrections longer than a segment: in the kernel for 8 and 16 points per thread on
+  // grids of up to 2^23 points, where the separate pass is mostly launch overhead; else a
+  // separate pass.  Measured: 512 complex128 64^3 imaginary-time problems one after another
+  // (8 points per thread along x, 16 along y) 12.7 -> 10.1 s, the same step counts and mu;
+  // on the 512x480x448 grid (8 points per thread, 1024-thread blocks) the x sweep with the
+  // separate pass took 800 us, in-kernel 882 us.
   constexpr bool kLong = !WIDE && (M == 8 || M == 16);
-  const bool lng = kLong && a.nw > M;
+  const bool lng = kLong && a.nw > M && a.nlines * (int64_t)a.n <= ((int64_t)1 << 23);
   const int nwi = (a.nw <= M || lng) ? a.nw : 0;
   constexpr bool kMax8 = (sizeof(R) == 8 && M == 16 && NSTEP != 0) || M >= 30;
   auto kern = k_sweep_lines<R, M, SW, CC, NSTEP, WIDE, 16>;
